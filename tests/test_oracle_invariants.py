@@ -1,0 +1,141 @@
+"""Exact invariants of the oracle (integer / sign bookkeeping) and its
+determinism, checked against independent numpy re-computation.
+
+- sp1 pair generation conserves the net sign; annihilation conserves the net
+  sign inside the box; escaped and k-truncated sign is tallied: the sum
+  net + escaped + killed equals N0 at all times (Alg. 1 rule 5, Eq.
+  signed_histogram).
+- The regenerated ensemble after an sp1 annihilation has, per cell, exactly
+  |n_nu| particles of sign sgn(n_nu) where n_nu is recomputed here with numpy
+  from the pre-annihilation ensemble; ids are (nu << 32) | j in ascending order.
+- Batched instances equal single runs keyed by the same instance index.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def numpy_cells(cfg, x, k):
+    g = cfg["grid"]
+    dx = (g["x_hi"] - g["x_lo"]) / g["nx"]
+    dk = (g["k_hi"] - g["k_lo"]) / g["nk"]
+    qx = (x - g["x_lo"]) / dx
+    qk = (k - g["k_lo"]) / dk
+    ok = np.all((qx >= 0) & (qx < g["nx"]) & (qk >= 0) & (qk < g["nk"]), axis=0)
+    ix = np.where(ok, qx, 0).astype(np.int64)
+    ik = np.where(ok, qk, 0).astype(np.int64)
+    if cfg["dim"] == 1:
+        nu = ix[0] + g["nx"] * ik[0]
+    else:
+        nu = ((ik[1] * g["nk"] + ik[0]) * g["nx"] + ix[1]) * g["nx"] + ix[0]
+    return np.where(ok, nu, -1)
+
+
+def test_net_sign_conserved_sp1(oracle_mod):
+    cfg = W.gaussian_barrier_small(N0=np.array([5000]))
+    # narrow box so that escapes and k-truncation both happen
+    cfg["grid"] = {"x_lo": -20.0, "x_hi": 20.0, "nx": 80, "k_lo": -1.0, "k_hi": 3.5, "nk": 36}
+    s = oracle_mod.OracleSim(cfg)
+    for _ in range(12):
+        s.step(5)
+        st = s.stats()
+        assert st["net"] + st["escaped"] + st["killed"] == 5000
+        s.annihilate()
+        st = s.stats()
+        assert st["net"] + st["escaped"] + st["killed"] == 5000
+    assert st["escaped"] != 0 and st["killed"] != 0
+
+
+@pytest.mark.parametrize("maker", [W.gaussian_barrier_small, W.helium_soft_coulomb])
+def test_annihilation_counts_match_numpy_rebinning(oracle_mod, maker):
+    N0 = 20000 if maker is W.gaussian_barrier_small else 3000
+    cfg = maker(N0=np.array([N0]))
+    if maker is W.helium_soft_coulomb:   # coarse 4D grid so that cells are shared
+        cfg["grid"] = {"x_lo": -10.0, "x_hi": 10.0, "nx": 6, "k_lo": -4.0, "k_hi": 4.0, "nk": 6}
+    s = oracle_mod.OracleSim(cfg)
+    s.step(10)
+    p = s.particles()
+    nu = numpy_cells(cfg, p["x"], p["k"])
+    inbox = nu >= 0
+    ncell = (cfg["grid"]["nx"] * cfg["grid"]["nk"]) ** cfg["dim"]
+    n_nu = np.bincount(nu[inbox], weights=p["sign"][inbox].astype(np.float64), minlength=ncell).astype(np.int64)
+    esc_before = s.stats()["escaped"]
+    s.annihilate()
+    q = s.particles()
+    st = s.stats()
+    assert st["escaped"] - esc_before == int(p["sign"][~inbox].sum())
+    assert s.count() == int(np.abs(n_nu).sum())
+    # every regenerated particle lies in its cell and carries sgn(n_nu)
+    nu2 = numpy_cells(cfg, q["x"], q["k"])
+    cell_of_id = (q["id"] >> np.uint64(32)).astype(np.int64)
+    j_of_id = (q["id"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    assert np.array_equal(nu2, cell_of_id)
+    assert np.array_equal(q["sign"], np.sign(n_nu[cell_of_id]).astype(np.int8))
+    # ascending (nu, j) with j = 0..|n_nu|-1
+    order = np.lexsort((j_of_id, cell_of_id))
+    assert np.array_equal(order, np.arange(len(order)))
+    assert np.array_equal(np.bincount(cell_of_id, minlength=ncell), np.abs(n_nu))
+    assert np.all(j_of_id < np.abs(n_nu[cell_of_id]))
+
+
+def test_children_follow_parents_and_are_classed(oracle_mod):
+    cfg = W.gaussian_barrier_small(N0=np.array([3000]))
+    s = oracle_mod.OracleSim(cfg)
+    s.step(1)
+    p = s.particles()
+    n = s.count()
+    assert np.array_equal(p["id"][:3000], np.arange(3000, dtype=np.uint64))
+    cls = p["id"][3000:] >> np.uint64(62)
+    assert n > 3000 and np.all(cls == 2)
+    # children come in +/- pairs of opposite sign
+    assert int(p["sign"][3000:].sum()) == 0
+
+
+def test_batched_equals_single_instances(oracle_mod):
+    cfg = W.batched_barriers(B=3, N0=np.array([500, 1500, 800]), steps=30)
+    s = oracle_mod.OracleSim(cfg)
+    s.run(30, 10)
+    dB = s.density()
+    for b in range(3):
+        single = W.scaled(cfg, B=1, instance_offset=b)
+        single["N0"] = cfg["N0"][b:b + 1].copy()
+        single["components"] = [dict(cfg["components"][0])]
+        for key in ("H", "width", "center"):
+            single["components"][0][key] = cfg["components"][0][key][b:b + 1].copy()
+        s1 = oracle_mod.OracleSim(single)
+        s1.run(30, 10)
+        pa, pb = s.particles(b), s1.particles(0)
+        for f in ("x", "k", "sign", "id"):
+            assert np.array_equal(pa[f], pb[f]), (b, f)
+        assert np.array_equal(dB[b], s1.density()[0])
+
+
+def test_deterministic_and_seed_sensitive(oracle_mod):
+    cfg = W.gaussian_barrier_small(N0=np.array([2000]))
+    a = oracle_mod.OracleSim(cfg); a.run(20, 10)
+    b = oracle_mod.OracleSim(cfg); b.run(20, 10)
+    assert np.array_equal(a.particles()["x"], b.particles()["x"])
+    c = oracle_mod.OracleSim(W.gaussian_barrier_small(N0=np.array([2000]), seed=1)); c.run(20, 10)
+    assert a.count() != c.count() or not np.array_equal(a.particles()["x"], c.particles()["x"])
+
+
+def test_density_sums_to_net_weight(oracle_mod):
+    cfg = W.gaussian_barrier_small(N0=np.array([4000]))
+    s = oracle_mod.OracleSim(cfg)
+    s.run(30, 10)
+    d = s.density()[0]
+    p = s.particles()
+    inwin = (p["x"][0] >= -60) & (p["x"][0] < 60)
+    assert abs(d.sum() * 0.5 * 4000 - p["sign"][inwin].sum()) < 1e-9
+
+
+def test_sp2_weights_are_signed_units_after_annihilation(oracle_mod):
+    cfg = W.gaussian_barrier_small(N0=np.array([3000]), strategy="sp2")
+    s = oracle_mod.OracleSim(cfg)
+    s.step(10)
+    w = s.particles()["w"]
+    assert np.any((np.abs(w) < 1) & (w != 0))
+    s.annihilate()
+    w = s.particles()["w"]
+    assert set(np.unique(w)) <= {-1.0, 1.0}
