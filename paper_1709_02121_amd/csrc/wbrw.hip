@@ -1,0 +1,847 @@
+// Host runtime and C ABI of the WBRW library (declared in include/wbrw.h).
+//
+// The runtime validates the configuration, lays one caller-owned device
+// workspace out into the arrays described in wbrw_dev.hpp, derives the
+// per-instance constants of the jump process, and enqueues kernels.  It never
+// allocates device memory and never synchronises except where the ABI says so.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/wbrw.h"
+#include "wbrw_cells.hpp"
+#include "wbrw_dev.hpp"
+#include "wbrw_math.hpp"
+#include "wbrw_sp2.hpp"
+#include "wbrw_step.hpp"
+
+using namespace wbrw;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Layout {
+    size_t total = 0;
+    size_t zero_begin = 0, zero_end = 0;   // region cleared at init
+    // offsets
+    size_t ens[2][8] = {}, gens[2][8] = {};
+    size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
+    size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, chc = 0, tileA = 0, tileB = 0, tileR = 0,
+           tileG = 0, tally = 0, ev_idx = 0, ev_x0 = 0, ev_x1 = 0, gev_idx = 0, gev_x0 = 0,
+           gev_x1 = 0, stA = 0, stAg = 0, stB = 0, stBg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
+           occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
+           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0;
+    int64_t cap_total = 0, gcap_total = 0, Nh = 0;
+    int64_t tilesA = 0, tilesAg = 0, tilesB = 0, tilesBg = 0, tilesS = 0, tilesP = 0;
+};
+
+size_t take(size_t &cursor, size_t bytes)
+{
+    cursor = (cursor + kAlign - 1) / kAlign * kAlign;
+    const size_t at = cursor;
+    cursor += bytes;
+    return at;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int validate(const wbrw_config *c)
+{
+    if (!c) return WBRW_EINVAL;
+    if (c->dim != 1 && c->dim != 2) return WBRW_EINVAL;
+    if (c->strategy != WBRW_SP1 && c->strategy != WBRW_SP2) return WBRW_EINVAL;
+    if (c->n_components < 1 || c->n_components > WBRW_MAX_COMPONENTS) return WBRW_EINVAL;
+    if (c->n_instances < 1 || c->n_instances > 65536) return WBRW_EINVAL;
+    if (!c->N0 || !c->capacity) return WBRW_EINVAL;
+    if (!(c->hbar > 0) || !(c->mass > 0) || !(c->dt > 0)) return WBRW_EINVAL;
+    if (!(c->x_hi > c->x_lo) || !(c->k_hi > c->k_lo) || c->nx < 1 || c->nk < 1) return WBRW_EINVAL;
+    if (c->max_density_bins < 1) return WBRW_EINVAL;
+    if (c->track_tangent) {
+        if (c->strategy != WBRW_SP1 || c->dim != 1 || c->n_components != 1 ||
+            c->comp[0].kind != WBRW_KERNEL_GAUSSIAN || c->ghost_capacity < 1)
+            return WBRW_EINVAL;
+    }
+    if (!(c->gamma0 > 0) && !(c->gamma_scale > 0)) return WBRW_EINVAL;
+    for (int m = 0; m < c->n_components; ++m) {
+        const wbrw_component &q = c->comp[m];
+        if (q.axis < 0 || q.axis > 2 || (c->dim == 1 && q.axis != 0)) return WBRW_EINVAL;
+        if (q.kind == WBRW_KERNEL_GAUSSIAN) {
+            if (!q.H || !q.width || !q.center_b) return WBRW_EINVAL;
+            for (int b = 0; b < c->n_instances; ++b)
+                if (!(q.width[b] > 0) || q.H[b] == 0.0 || !std::isfinite(q.H[b])) return WBRW_EINVAL;
+        } else if (q.kind == WBRW_KERNEL_TABLE) {
+            if (!q.table || q.table_n < 1 || q.table_n > 65536 || !(q.q_hi > q.q_lo)) return WBRW_EINVAL;
+            if (q.sign != 1.0 && q.sign != -1.0) return WBRW_EINVAL;
+            double s = 0;
+            for (int j = 0; j < q.table_n; ++j) {
+                if (!(q.table[j] >= 0)) return WBRW_EINVAL;
+                s += q.table[j];
+            }
+            if (!(s > 0)) return WBRW_EINVAL;
+        } else {
+            return WBRW_EINVAL;
+        }
+    }
+    for (int b = 0; b < c->n_instances; ++b) {
+        if (c->N0[b] < 0 || c->capacity[b] < c->N0[b] || c->capacity[b] >= (1ll << 31)) return WBRW_EINVAL;
+    }
+    const int64_t nh = c->dim == 1 ? (int64_t)c->nx * c->nk
+                                   : (int64_t)c->nx * c->nx * (int64_t)c->nk * c->nk;
+    if (nh >= (1ll << 31)) return WBRW_EINVAL;
+    return WBRW_OK;
+}
+
+Layout make_layout(const wbrw_config *c)
+{
+    Layout L;
+    const int B = c->n_instances;
+    const bool sp2 = c->strategy == WBRW_SP2, tan = c->track_tangent != 0;
+    for (int b = 0; b < B; ++b) {
+        L.cap_total += c->capacity[b];
+        L.tilesA += ceil_div(c->capacity[b], kTileA) + 1;
+        L.tilesB += ceil_div(c->capacity[b], kTileB) + 1;
+        L.tilesP += ceil_div(c->capacity[b], kTileS) + 1;
+        if (tan) {
+            L.gcap_total += c->ghost_capacity;
+            L.tilesAg += ceil_div(c->ghost_capacity, kTileA) + 1;
+            L.tilesBg += ceil_div(c->ghost_capacity, kTileB) + 1;
+        }
+    }
+    L.Nh = c->dim == 1 ? (int64_t)c->nx * c->nk : (int64_t)c->nx * c->nx * (int64_t)c->nk * c->nk;
+    L.tilesS = ceil_div(L.Nh, kTileS) * B;
+    const size_t C = (size_t)L.cap_total, G = (size_t)L.gcap_total, Nh = (size_t)L.Nh;
+    const size_t BB = (size_t)B, MB = (size_t)c->max_density_bins;
+    size_t cur = 0;
+    for (int s = 0; s < 2; ++s) {
+        L.ens[s][0] = take(cur, C * 8);
+        L.ens[s][1] = c->dim == 2 ? take(cur, C * 8) : 0;
+        L.ens[s][2] = take(cur, C * 8);
+        L.ens[s][3] = c->dim == 2 ? take(cur, C * 8) : 0;
+        L.ens[s][4] = sp2 ? 0 : take(cur, C);
+        L.ens[s][5] = sp2 ? take(cur, C * 8) : 0;
+        L.ens[s][6] = take(cur, C * 8);
+        L.ens[s][7] = tan ? take(cur, C * 24) : 0;
+        if (tan) {
+            L.gens[s][0] = take(cur, G * 8);
+            L.gens[s][2] = take(cur, G * 8);
+            L.gens[s][4] = take(cur, G);
+            L.gens[s][6] = take(cur, G * 8);
+            L.gens[s][7] = take(cur, G * 24);
+        }
+    }
+    L.ev_idx = take(cur, C * 4);
+    L.ev_x0 = take(cur, C * 8);
+    L.ev_x1 = c->dim == 2 ? take(cur, C * 8) : 0;
+    if (tan) {
+        L.gev_idx = take(cur, G * 4);
+        L.gev_x0 = take(cur, G * 8);
+    }
+    L.ip = take(cur, BB * sizeof(InstParam));
+    for (int m = 0; m < c->n_components; ++m)
+        if (c->comp[m].kind == WBRW_KERNEL_TABLE) L.tab[m] = take(cur, ((size_t)c->comp[m].table_n + 1) * 8);
+    L.off = take(cur, BB * Nh * 8);
+    if (sp2) {
+        L.bA = take(cur, C * 8);
+        L.bcopies = take(cur, C * 4);
+        L.bcls = take(cur, C);
+        L.bcell = take(cur, C * 8);
+        L.bP = take(cur, 2 * C * 16);
+        L.bTile = take(cur, 2 * (size_t)L.tilesP * 16);
+    }
+    // everything below starts zeroed
+    L.zero_begin = (cur + kAlign - 1) / kAlign * kAlign;
+    L.ctl = take(cur, sizeof(Ctl));
+    L.N = take(cur, BB * 8);
+    L.NG = take(cur, BB * 8);
+    L.Nnew = take(cur, BB * 8);
+    L.NGnew = take(cur, BB * 8);
+    L.evc = take(cur, 2 * BB * 8);
+    L.chc = take(cur, 2 * BB * 8);
+    L.tileA = take(cur, 2 * (BB + 1) * 8);
+    L.tileB = take(cur, 2 * (BB + 1) * 8);
+    L.tileR = take(cur, (BB + 1) * 8);
+    L.tileG = take(cur, (BB + 1) * 8);
+    L.tally = take(cur, BB * kTalCount * 8);
+    L.stA = take(cur, (size_t)L.tilesA * 8);
+    L.stB = take(cur, (size_t)L.tilesB * 8);
+    if (tan) {
+        L.stAg = take(cur, (size_t)L.tilesAg * 8);
+        L.stBg = take(cur, (size_t)L.tilesBg * 8);
+        L.stG = take(cur, (size_t)L.tilesS * 8);
+    }
+    L.stS = take(cur, (size_t)L.tilesS * 8);
+    L.cnt = take(cur, BB * Nh * 4);
+    if (tan) {
+        L.occ = take(cur, BB * Nh * 4);
+        L.Tcell = take(cur, 3 * BB * Nh * 8);
+        L.dTacc = take(cur, 3 * BB * MB * 8);
+    }
+    if (sp2) {
+        L.ntil = take(cur, 2 * BB * Nh * 4);
+        L.bcls_stat = take(cur, BB * 8 * 8);
+        L.tileD = take(cur, 2 * (BB + 1) * 8);
+        L.bscan_tiles = take(cur, (BB + 1) * 8);
+    }
+    L.dacc = take(cur, BB * MB * 8);
+    L.zero_end = (cur + kAlign - 1) / kAlign * kAlign;
+    L.total = L.zero_end;
+    return L;
+}
+
+}  // namespace
+
+struct wbrw_handle {
+    int B = 0, dim = 0, M = 0, strategy = 0, tangent = 0;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    Layout L;
+    Dev d{};
+    std::vector<InstParam> ip;
+    int cus = 0;
+    int grid[16] = {};
+    hipGraphExec_t gexec = nullptr;
+    int graph_every = -1;
+    int sticky = WBRW_OK;
+    bool prof = false;
+    struct Mark { int stage; hipEvent_t a, b; };
+    std::vector<Mark> marks;
+    int open_stage = -1;
+    hipEvent_t open_ev = nullptr;
+};
+
+namespace {
+
+#define HIPCHK(x)                                        \
+    do {                                                 \
+        hipError_t e_ = (x);                             \
+        if (e_ != hipSuccess) {                          \
+            std::fprintf(stderr, "wbrw: %s failed: %s\n", #x, hipGetErrorString(e_)); \
+            return WBRW_EHIP;                            \
+        }                                                \
+    } while (0)
+
+template <typename T>
+T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off); }
+
+enum { G_STREAM = 0, G_FAMILY, G_BIN, G_SCAN, G_REGEN, G_DENS, G_SP2, G_GHOST };
+
+template <typename K>
+int persistent_blocks(K kernel, int cus)
+{
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) != hipSuccess || per < 1) per = 1;
+    return per * cus;
+}
+
+// derived per-instance constants (Remark 3: xi_m and the pair probability)
+void derive(const wbrw_config *c, int b, const std::vector<double> &xi_tab,
+            InstParam &P)
+{
+    std::memset(&P, 0, sizeof(P));
+    double g = 0.0;
+    for (int m = 0; m < c->n_components; ++m) {
+        const wbrw_component &q = c->comp[m];
+        double xi;
+        if (q.kind == WBRW_KERNEL_GAUSSIAN) {
+            P.H[m] = q.H[b];
+            P.width[m] = q.width[b];
+            P.center[m] = q.center_b[b];
+            xi = (2.0 * std::fabs(P.H[m])) / c->hbar;   // (1/(pi hbar)) int |F[V](s)| ds = 2|H|/hbar
+            P.sq[m] = 0.5 / P.width[m];
+            P.sgnV[m] = P.H[m] >= 0.0 ? 1.0 : -1.0;
+        } else {
+            xi = xi_tab[m];
+            P.center[m] = q.center;
+            P.sgnV[m] = q.sign;
+            P.H[m] = 1.0;
+            P.width[m] = 1.0;
+        }
+        P.c[m] = xi;   // temporarily hold xi_m
+        if (xi > g) g = xi;
+    }
+    P.gamma0 = (c->gamma0 > 0.0) ? c->gamma0 : c->gamma_scale * (g / 2.0);
+    for (int m = 0; m < c->n_components; ++m) P.c[m] = P.c[m] / (2.0 * P.gamma0);
+    // probability of a first jump within dt, and a band around it outside of
+    // which the comparison tau <= dt cannot be decided differently by rounding
+    const long double pj = -std::expm1l(-(long double)P.gamma0 * (long double)c->dt);
+    P.thr_lo = (double)(pj * (1.0L - 1e-9L));
+    P.thr_hi = (double)(pj * (1.0L + 1e-9L));
+    P.N0 = c->N0[b];
+    P.key = (uint32_t)(c->instance_offset + b);
+}
+
+void plan_host(std::vector<int64_t> &plan, const int64_t *n, int B, int64_t tile)
+{
+    plan.assign(B + 1, 0);
+    for (int b = 0; b < B; ++b) plan[b + 1] = plan[b] + ceil_div(n[b], tile);
+}
+
+int launch_check()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "wbrw: kernel launch failed: %s\n", hipGetErrorString(e));
+        return WBRW_EHIP;
+    }
+    return WBRW_OK;
+}
+
+// per-stage profiling marks (no-ops unless wbrw_profile enabled them)
+void stage_begin(wbrw_t h, int stage)
+{
+    if (!h->prof) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, h->stream);
+    h->open_stage = stage;
+    h->open_ev = e;
+}
+
+void stage_end(wbrw_t h)
+{
+    if (!h->prof || h->open_stage < 0) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, h->stream);
+    h->marks.push_back({h->open_stage, h->open_ev, e});
+    h->open_stage = -1;
+    h->open_ev = nullptr;
+}
+
+template <int DIM>
+void enqueue_step_dim(wbrw_t h)
+{
+    const Dev &d = h->d;
+    hipStream_t s = h->stream;
+    const bool tan = h->tangent != 0;
+    stage_begin(h, WBRW_STAGE_STREAM);
+    hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 0);
+    stage_end(h);
+    stage_begin(h, WBRW_STAGE_FAMILY);
+    if (h->strategy == WBRW_SP2)
+        hipLaunchKernelGGL((k_family<DIM, true, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0, 1);
+    else if (tan)
+        hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0, 0);
+    else
+        hipLaunchKernelGGL((k_family<DIM, false, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0, 1);
+    stage_end(h);
+    if (tan) {
+        stage_begin(h, WBRW_STAGE_GHOST);
+        hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1, 1);
+        stage_end(h);
+    }
+}
+
+int enqueue_step(wbrw_t h)
+{
+    if (h->dim == 1) enqueue_step_dim<1>(h); else enqueue_step_dim<2>(h);
+    return launch_check();
+}
+
+template <int DIM>
+int enqueue_annihilate_dim(wbrw_t h)
+{
+    const Dev &d = h->d;
+    hipStream_t s = h->stream;
+    if (h->strategy == WBRW_SP2) {
+        stage_begin(h, WBRW_STAGE_BOOTSTRAP);
+        int rc = enqueue_sp2_bootstrap<DIM>(d, s, h->grid[G_SP2], h->grid[G_SCAN]);
+        stage_end(h);
+        if (rc) return rc;
+        stage_begin(h, WBRW_STAGE_SCAN);
+        hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
+        stage_end(h);
+        stage_begin(h, WBRW_STAGE_REGEN);
+        hipLaunchKernelGGL((k_regen<DIM, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+        stage_end(h);
+        return launch_check();
+    }
+    if (h->tangent) {
+        stage_begin(h, WBRW_STAGE_BIN);
+        hipLaunchKernelGGL((k_bin<DIM, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
+        hipLaunchKernelGGL((k_bin<DIM, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 1);
+        stage_end(h);
+        stage_begin(h, WBRW_STAGE_SCAN);
+        hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 0);
+        stage_end(h);
+        stage_begin(h, WBRW_STAGE_REGEN);
+        hipLaunchKernelGGL((k_regen<DIM, false, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+        stage_end(h);
+        stage_begin(h, WBRW_STAGE_GHOST);
+        hipLaunchKernelGGL(k_ghosts, dim3(h->grid[G_GHOST]), dim3(kThreads), 0, s, d);
+        stage_end(h);
+        return launch_check();
+    }
+    stage_begin(h, WBRW_STAGE_BIN);
+    hipLaunchKernelGGL((k_bin<DIM, false>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
+    stage_end(h);
+    stage_begin(h, WBRW_STAGE_SCAN);
+    hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
+    stage_end(h);
+    stage_begin(h, WBRW_STAGE_REGEN);
+    hipLaunchKernelGGL((k_regen<DIM, false, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+    stage_end(h);
+    return launch_check();
+}
+
+int enqueue_annihilate(wbrw_t h)
+{
+    return h->dim == 1 ? enqueue_annihilate_dim<1>(h) : enqueue_annihilate_dim<2>(h);
+}
+
+template <int DIM>
+void set_grids_dim(wbrw_t h)
+{
+    const int cus = h->cus;
+    h->grid[G_STREAM] = persistent_blocks(k_stream<DIM>, cus);
+    if (h->strategy == WBRW_SP2)
+        h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, true, false>, cus);
+    else if (h->tangent)
+        h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, false, true>, cus);
+    else
+        h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, false, false>, cus);
+    h->grid[G_BIN] = persistent_blocks(k_bin<DIM, false>, cus);
+    h->grid[G_SCAN] = persistent_blocks(k_scan, cus);
+    h->grid[G_REGEN] = persistent_blocks(k_regen<DIM, false, false>, cus);
+    h->grid[G_DENS] = persistent_blocks(k_density_bin<DIM, false, false>, cus);
+    h->grid[G_SP2] = persistent_blocks(k_sp2_classify<DIM>, cus);
+    h->grid[G_GHOST] = persistent_blocks(k_ghosts, cus);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wbrw_strerror(int code)
+{
+    switch (code) {
+    case WBRW_OK: return "ok";
+    case WBRW_EINVAL: return "invalid argument or configuration";
+    case WBRW_ECAPACITY: return "an instance outgrew its particle capacity";
+    case WBRW_EHIP: return "HIP runtime error";
+    case WBRW_ESTATE: return "invalid state";
+    case WBRW_EDEPTH: return "family tree deeper than the per-step limit";
+    default: return "unknown error";
+    }
+}
+
+int wbrw_workspace_size(const wbrw_config *cfg, size_t *bytes)
+{
+    if (!bytes) return WBRW_EINVAL;
+    const int v = validate(cfg);
+    if (v) return v;
+    *bytes = make_layout(cfg).total;
+    return WBRW_OK;
+}
+
+int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, void *hip_stream,
+              wbrw_t *out)
+{
+    if (!out || !workspace) return WBRW_EINVAL;
+    *out = nullptr;
+    const int v = validate(cfg);
+    if (v) return v;
+    if (((uintptr_t)workspace) % kAlign) return WBRW_EINVAL;
+    Layout L = make_layout(cfg);
+    if (workspace_bytes < L.total) return WBRW_EINVAL;
+
+    wbrw_handle *h = new (std::nothrow) wbrw_handle();
+    if (!h) return WBRW_EINVAL;
+    h->B = cfg->n_instances;
+    h->dim = cfg->dim;
+    h->M = cfg->n_components;
+    h->strategy = cfg->strategy;
+    h->tangent = cfg->track_tangent;
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = (char *)workspace;
+    h->L = L;
+    char *w = h->ws;
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        delete h;
+        return WBRW_EHIP;
+    }
+
+    Dev &d = h->d;
+    d.B = h->B;
+    d.dim = h->dim;
+    d.M = h->M;
+    d.strategy = h->strategy;
+    d.tangent = h->tangent;
+    d.nx = cfg->nx;
+    d.nk = cfg->nk;
+    d.seed = cfg->seed;
+    d.Nh = L.Nh;
+    d.cap_total = L.cap_total;
+    d.gcap_total = L.gcap_total;
+    d.dt = cfg->dt;
+    d.vfac = cfg->hbar / cfg->mass;
+    d.x_lo = cfg->x_lo;
+    d.x_hi = cfg->x_hi;
+    d.k_lo = cfg->k_lo;
+    d.k_hi = cfg->k_hi;
+    d.dx = (cfg->x_hi - cfg->x_lo) / (double)cfg->nx;
+    d.dk = (cfg->k_hi - cfg->k_lo) / (double)cfg->nk;
+    d.max_bins = cfg->max_density_bins;
+
+    // kernel tables: cumulative sums and normalisers
+    std::vector<double> xi_tab(kMaxM, 0.0);
+    std::vector<std::vector<double>> cums(kMaxM);
+    for (int m = 0; m < h->M; ++m) {
+        const wbrw_component &q = cfg->comp[m];
+        d.kind[m] = q.kind;
+        d.axis[m] = q.axis;
+        if (q.kind != WBRW_KERNEL_TABLE) continue;
+        std::vector<double> &cm = cums[m];
+        cm.resize((size_t)q.table_n + 1);
+        cm[0] = 0.0;
+        for (int j = 0; j < q.table_n; ++j) cm[j + 1] = cm[j] + q.table[j];
+        const double dq = (q.q_hi - q.q_lo) / (double)q.table_n;
+        // xi_m = (2/(pi hbar)) sum_j |F[V](2 q_j)| dq
+        xi_tab[m] = ((2.0 * cm[q.table_n]) * dq) / (0x1.921fb54442d18p+1 * cfg->hbar);
+        d.tab[m].cum = at<double>(w, L.tab[m]);
+        d.tab[m].n = q.table_n;
+        d.tab[m].q_lo = q.q_lo;
+        d.tab[m].dq = dq;
+    }
+    h->ip.resize(h->B);
+    int64_t base = 0, gbase = 0;
+    for (int b = 0; b < h->B; ++b) {
+        derive(cfg, b, xi_tab, h->ip[b]);
+        h->ip[b].base = base;
+        h->ip[b].cap = cfg->capacity[b];
+        base += cfg->capacity[b];
+        if (h->tangent) {
+            h->ip[b].gbase = gbase;
+            h->ip[b].gcap = cfg->ghost_capacity;
+            gbase += cfg->ghost_capacity;
+        }
+    }
+    for (int s = 0; s < 2; ++s) {
+        Ens &E = d.ens[s];
+        E.x0 = at<double>(w, L.ens[s][0]);
+        E.x1 = cfg->dim == 2 ? at<double>(w, L.ens[s][1]) : nullptr;
+        E.k0 = at<double>(w, L.ens[s][2]);
+        E.k1 = cfg->dim == 2 ? at<double>(w, L.ens[s][3]) : nullptr;
+        E.sg = h->strategy == WBRW_SP2 ? nullptr : at<int8_t>(w, L.ens[s][4]);
+        E.w = h->strategy == WBRW_SP2 ? at<double>(w, L.ens[s][5]) : nullptr;
+        E.id = at<uint64_t>(w, L.ens[s][6]);
+        E.D = h->tangent ? at<double>(w, L.ens[s][7]) : nullptr;
+        Ens &G = d.gens[s];
+        std::memset(&G, 0, sizeof(G));
+        if (h->tangent) {
+            G.x0 = at<double>(w, L.gens[s][0]);
+            G.k0 = at<double>(w, L.gens[s][2]);
+            G.sg = at<int8_t>(w, L.gens[s][4]);
+            G.id = at<uint64_t>(w, L.gens[s][6]);
+            G.D = at<double>(w, L.gens[s][7]);
+        }
+    }
+    d.ip = at<InstParam>(w, L.ip);
+    d.ctl = at<Ctl>(w, L.ctl);
+    d.N = at<int64_t>(w, L.N);
+    d.NG = at<int64_t>(w, L.NG);
+    d.Nnew = at<int64_t>(w, L.Nnew);
+    d.NGnew = at<int64_t>(w, L.NGnew);
+    d.evc = at<int64_t>(w, L.evc);
+    d.chc = at<int64_t>(w, L.chc);
+    d.tileA = at<int64_t>(w, L.tileA);
+    d.tileB = at<int64_t>(w, L.tileB);
+    d.tileR = at<int64_t>(w, L.tileR);
+    d.tileG = at<int64_t>(w, L.tileG);
+    d.tally = at<int64_t>(w, L.tally);
+    d.ev_idx = at<uint32_t>(w, L.ev_idx);
+    d.ev_x0 = at<double>(w, L.ev_x0);
+    d.ev_x1 = cfg->dim == 2 ? at<double>(w, L.ev_x1) : nullptr;
+    d.gev_idx = h->tangent ? at<uint32_t>(w, L.gev_idx) : nullptr;
+    d.gev_x0 = h->tangent ? at<double>(w, L.gev_x0) : nullptr;
+    d.gev_x1 = nullptr;
+    d.stA = at<uint64_t>(w, L.stA);
+    d.stB = at<uint64_t>(w, L.stB);
+    d.stAg = h->tangent ? at<uint64_t>(w, L.stAg) : nullptr;
+    d.stBg = h->tangent ? at<uint64_t>(w, L.stBg) : nullptr;
+    d.stG = h->tangent ? at<uint64_t>(w, L.stG) : nullptr;
+    d.stS = at<uint64_t>(w, L.stS);
+    d.cnt = at<int32_t>(w, L.cnt);
+    d.off = at<int64_t>(w, L.off);
+    d.occ = h->tangent ? at<int32_t>(w, L.occ) : nullptr;
+    d.Tcell = h->tangent ? at<double>(w, L.Tcell) : nullptr;
+    d.dTacc = h->tangent ? at<double>(w, L.dTacc) : nullptr;
+    d.dacc = at<int64_t>(w, L.dacc);
+    if (h->strategy == WBRW_SP2) {
+        d.ntil = at<int32_t>(w, L.ntil);
+        d.bA = at<uint64_t>(w, L.bA);
+        d.bcopies = at<int32_t>(w, L.bcopies);
+        d.bcls = at<int8_t>(w, L.bcls);
+        d.bcell = at<int64_t>(w, L.bcell);
+        d.bP = at<uint64_t>(w, L.bP);
+        d.bTile = at<uint64_t>(w, L.bTile);
+        d.bcls_stat = at<int64_t>(w, L.bcls_stat);
+        d.tileD = at<int64_t>(w, L.tileD);
+        d.bscan_tiles = at<int64_t>(w, L.bscan_tiles);
+        d.tstride = L.tilesP;
+    }
+
+    if (h->dim == 1) set_grids_dim<1>(h); else set_grids_dim<2>(h);
+
+    hipStream_t s = h->stream;
+    auto fail = [&](int rc) { delete h; return rc; };
+    // clear the bookkeeping region with a kernel
+    const int64_t nz = (int64_t)((L.zero_end - L.zero_begin) / 8);
+    hipLaunchKernelGGL(k_fill64, dim3(std::max(1, std::min<int>(h->cus * 8, (int)ceil_div(nz, kThreads)))),
+                       dim3(kThreads), 0, s, at<uint64_t>(w, L.zero_begin), nz, 0ull);
+    if (launch_check()) return fail(WBRW_EHIP);
+    // constants and initial counts / plans
+    std::vector<int64_t> N0(cfg->N0, cfg->N0 + h->B), plan;
+    plan_host(plan, N0.data(), h->B, kTileA);
+    if (hipMemcpyAsync((void *)d.ip, h->ip.data(), sizeof(InstParam) * h->B, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d.N, N0.data(), 8 * h->B, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d.tileA, plan.data(), 8 * (h->B + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(WBRW_EHIP);
+    if (h->tangent) {
+        std::vector<int64_t> gplan(h->B + 1, 0);
+        if (hipMemcpyAsync(d.tileA + h->B + 1, gplan.data(), 8 * (h->B + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(WBRW_EHIP);
+    }
+    for (int m = 0; m < h->M; ++m)
+        if (cfg->comp[m].kind == WBRW_KERNEL_TABLE &&
+            hipMemcpyAsync((void *)d.tab[m].cum, cums[m].data(), 8 * cums[m].size(), hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(WBRW_EHIP);
+    const int init_blocks = std::max<int64_t>(1, std::min<int64_t>(plan[h->B], (int64_t)h->cus * 16));
+    if (h->dim == 1)
+        hipLaunchKernelGGL(k_init<1>, dim3(init_blocks), dim3(kThreads), 0, s, d,
+                           cfg->init_mean_x[0], cfg->init_mean_x[1], cfg->init_sigma_x[0], cfg->init_sigma_x[1],
+                           cfg->init_mean_k[0], cfg->init_mean_k[1], cfg->init_sigma_k[0], cfg->init_sigma_k[1]);
+    else
+        hipLaunchKernelGGL(k_init<2>, dim3(init_blocks), dim3(kThreads), 0, s, d,
+                           cfg->init_mean_x[0], cfg->init_mean_x[1], cfg->init_sigma_x[0], cfg->init_sigma_x[1],
+                           cfg->init_mean_k[0], cfg->init_mean_k[1], cfg->init_sigma_k[0], cfg->init_sigma_k[1]);
+    if (launch_check()) return fail(WBRW_EHIP);
+    // host staging buffers above must outlive the copies
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(WBRW_EHIP);
+    *out = h;
+    return WBRW_OK;
+}
+
+int wbrw_step(wbrw_t h, int32_t nsteps)
+{
+    if (!h || nsteps < 0) return WBRW_EINVAL;
+    for (int i = 0; i < nsteps; ++i) {
+        const int rc = enqueue_step(h);
+        if (rc) return rc;
+    }
+    return WBRW_OK;
+}
+
+int wbrw_annihilate(wbrw_t h)
+{
+    if (!h) return WBRW_EINVAL;
+    return enqueue_annihilate(h);
+}
+
+int wbrw_run(wbrw_t h, int32_t nsteps, int32_t every, int32_t use_graph)
+{
+    if (!h || nsteps < 0 || every < 0) return WBRW_EINVAL;
+    if (every == 0) return wbrw_step(h, nsteps);
+    const int epochs = nsteps / every, rest = nsteps % every;
+    if (use_graph && h->stream != nullptr && epochs > 0) {
+        if (h->graph_every != every) {
+            if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+            hipGraph_t g;
+            const bool prof = h->prof;
+            h->prof = false;
+            HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+            int rc = WBRW_OK;
+            for (int i = 0; i < every && !rc; ++i) rc = enqueue_step(h);
+            if (!rc) rc = enqueue_annihilate(h);
+            hipError_t e = hipStreamEndCapture(h->stream, &g);
+            h->prof = prof;
+            if (rc) return rc;
+            HIPCHK(e);
+            HIPCHK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+            (void)hipGraphDestroy(g);
+            h->graph_every = every;
+        }
+        for (int ep = 0; ep < epochs; ++ep) HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+    } else {
+        for (int ep = 0; ep < epochs; ++ep) {
+            int rc = wbrw_step(h, every);
+            if (!rc) rc = enqueue_annihilate(h);
+            if (rc) return rc;
+        }
+    }
+    return wbrw_step(h, rest);
+}
+
+int wbrw_density(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, double *d_out)
+{
+    if (!h || !d_out || nbins < 1 || nbins > h->d.max_bins || !(hi > lo)) return WBRW_EINVAL;
+    if (axis < 0 || axis >= h->dim) return WBRW_EINVAL;
+    const double dxb = (hi - lo) / (double)nbins;
+    const Dev &d = h->d;
+    hipStream_t s = h->stream;
+    const bool sp2 = h->strategy == WBRW_SP2;
+    const int outb = std::max(1, std::min(h->cus * 4, (int)ceil_div((int64_t)h->B * nbins, kThreads)));
+    stage_begin(h, WBRW_STAGE_DENSITY);
+    if (h->dim == 1) {
+        if (sp2) hipLaunchKernelGGL((k_density_bin<1, true, false>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+        else hipLaunchKernelGGL((k_density_bin<1, false, false>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+    } else {
+        if (sp2) hipLaunchKernelGGL((k_density_bin<2, true, false>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+        else hipLaunchKernelGGL((k_density_bin<2, false, false>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+    }
+    if (sp2) hipLaunchKernelGGL((k_density_out<true, false>), dim3(outb), dim3(kThreads), 0, s, d, nbins, dxb, d_out);
+    else hipLaunchKernelGGL((k_density_out<false, false>), dim3(outb), dim3(kThreads), 0, s, d, nbins, dxb, d_out);
+    stage_end(h);
+    return launch_check();
+}
+
+int wbrw_density_tangent(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, double *d_out)
+{
+    if (!h || !d_out || !h->tangent || nbins < 1 || nbins > h->d.max_bins || !(hi > lo) || axis != 0)
+        return WBRW_EINVAL;
+    const double dxb = (hi - lo) / (double)nbins;
+    const Dev &d = h->d;
+    hipStream_t s = h->stream;
+    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 1, axis, nbins, lo, dxb);
+    const int outb = std::max(1, std::min(h->cus * 4, (int)ceil_div((int64_t)h->B * 3 * nbins, kThreads)));
+    hipLaunchKernelGGL((k_density_out<false, true>), dim3(outb), dim3(kThreads), 0, s, d, nbins, dxb, d_out);
+    return launch_check();
+}
+
+int wbrw_stats(wbrw_t h, int32_t b, wbrw_stats_t *out)
+{
+    if (!h || !out || b < 0 || b >= h->B) return WBRW_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    Ctl c;
+    int64_t tal[kTalCount], n = 0, ng = 0;
+    HIPCHK(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(tal, h->d.tally + (int64_t)b * kTalCount, sizeof(tal), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&n, h->d.N + b, 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&ng, h->d.NG + b, 8, hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->n = n;
+    out->n_ghost = ng;
+    out->events = tal[kTalEvents];
+    out->pairs = tal[kTalPairs];
+    out->killed = tal[kTalKilled];
+    out->escaped = tal[kTalEscaped];
+    out->max_depth = tal[kTalMaxDepth];
+    out->event_cap_hits = tal[kTalEventCap];
+    out->S_plus = tal[kTalSplus];
+    out->S_minus = tal[kTalSminus];
+    out->N_plus = tal[kTalNplus];
+    out->N_minus = tal[kTalNminus];
+    out->step = c.step;
+    out->particle_steps = tal[kTalPSteps];
+    out->gamma0 = h->ip[b].gamma0;
+    if (c.err & kErrCapacity) return WBRW_ECAPACITY;
+    if (c.err & kErrDepth) return WBRW_EDEPTH;
+    return WBRW_OK;
+}
+
+int wbrw_count(wbrw_t h, int32_t b, int32_t ghost, int64_t *n)
+{
+    if (!h || !n || b < 0 || b >= h->B) return WBRW_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(n, (ghost ? h->d.NG : h->d.N) + b, 8, hipMemcpyDeviceToHost));
+    return WBRW_OK;
+}
+
+int wbrw_export(wbrw_t h, int32_t b, int32_t ghost, int64_t n, double *x, double *k, int8_t *sign,
+                double *w, uint64_t *id, double *D)
+{
+    if (!h || b < 0 || b >= h->B || n < 0) return WBRW_EINVAL;
+    if (ghost && !h->tangent) return WBRW_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    Ctl c;
+    int64_t cur_n = 0;
+    HIPCHK(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&cur_n, (ghost ? h->d.NG : h->d.N) + b, 8, hipMemcpyDeviceToHost));
+    if (cur_n != n) return WBRW_EINVAL;
+    const Ens E = ghost ? h->d.gens[c.gcur] : h->d.ens[c.cur];
+    const InstParam &P = h->ip[b];
+    const int64_t base = ghost ? P.gbase : P.base;
+    const int64_t tot = ghost ? h->d.gcap_total : h->d.cap_total;
+    hipStream_t s = h->stream;
+    const hipMemcpyKind kd = hipMemcpyDeviceToDevice;
+    if (n == 0) return WBRW_OK;
+    if (x) {
+        HIPCHK(hipMemcpyAsync(x, E.x0 + base, 8 * n, kd, s));
+        if (h->dim == 2) HIPCHK(hipMemcpyAsync(x + n, E.x1 + base, 8 * n, kd, s));
+    }
+    if (k) {
+        HIPCHK(hipMemcpyAsync(k, E.k0 + base, 8 * n, kd, s));
+        if (h->dim == 2) HIPCHK(hipMemcpyAsync(k + n, E.k1 + base, 8 * n, kd, s));
+    }
+    if (sign) {
+        if (!E.sg) return WBRW_EINVAL;
+        HIPCHK(hipMemcpyAsync(sign, E.sg + base, n, kd, s));
+    }
+    if (w) {
+        if (!E.w) return WBRW_EINVAL;
+        HIPCHK(hipMemcpyAsync(w, E.w + base, 8 * n, kd, s));
+    }
+    if (id) HIPCHK(hipMemcpyAsync(id, E.id + base, 8 * n, kd, s));
+    if (D) {
+        if (!E.D) return WBRW_EINVAL;
+        for (int c3 = 0; c3 < 3; ++c3)
+            HIPCHK(hipMemcpy2DAsync(D + c3, 24, E.D + c3 * tot + base, 8, 8, n, kd, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return WBRW_OK;
+}
+
+static void drop_marks(wbrw_t h)
+{
+    for (auto &m : h->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    h->marks.clear();
+}
+
+int wbrw_profile(wbrw_t h, int32_t enable)
+{
+    if (!h) return WBRW_EINVAL;
+    if (enable) {
+        HIPCHK(hipStreamSynchronize(h->stream));
+        drop_marks(h);
+    }
+    h->prof = enable != 0;
+    return WBRW_OK;
+}
+
+int wbrw_profile_read(wbrw_t h, double *ms, int64_t *launches)
+{
+    if (!h || !ms || !launches) return WBRW_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int s = 0; s < WBRW_STAGE_COUNT; ++s) { ms[s] = 0.0; launches[s] = 0; }
+    for (auto &m : h->marks) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, m.a, m.b));
+        ms[m.stage] += t;
+        launches[m.stage] += 1;
+    }
+    return WBRW_OK;
+}
+
+int wbrw_destroy(wbrw_t h)
+{
+    if (!h) return WBRW_EINVAL;
+    drop_marks(h);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    delete h;
+    return WBRW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,415 @@
+// Phase-space cells: initial sampling, sp1 annihilation and the density readout.
+//
+// Annihilation (Sec. 4.3, Eq. signed_histogram; Alg. 3 step 3):
+//   k_bin     one pass over the particles: cell index on the uniform grid
+//             D_nu = X_nu1 x K_nu2 (escaped sign tallied), integer atomic add of
+//             the sign into the instance's count grid: the per-cell sums
+//             n_nu^+ - n_nu^- are exact and order independent;
+//   k_scan    ordered exclusive scan of |n_nu| per instance (decoupled
+//             look-back), which is also the output layout: ascending cell,
+//             then index within the cell;
+//   k_regen   one thread per output particle: the cell by binary search in the
+//             scan, position uniform in the cell, sign sgn(n_nu), lineage id
+//             (nu << 32) | j; written to the inactive buffer set, which then
+//             becomes active.
+// Density (Eq. estimator with an indicator observable): integer (sp1) or
+// 2^-32 fixed-point (sp2) atomics per bin, then one division per bin.
+#pragma once
+#include "wbrw_dev.hpp"
+#include "wbrw_math.hpp"
+
+namespace wbrw {
+
+constexpr int64_t kOffMask = (1ll << 62) - 1;
+constexpr int64_t kOffNeg = 1ll << 62;
+
+// Cell of a phase-space point or -1 outside the grid.
+template <int DIM>
+__device__ __forceinline__ int64_t cell_index(const Dev &d, double x0, double x1, double k0, double k1)
+{
+    const double qx0 = (x0 - d.x_lo) / d.dx;
+    const double qk0 = (k0 - d.k_lo) / d.dk;
+    if (!(qx0 >= 0.0 && qx0 < (double)d.nx)) return -1;
+    if (!(qk0 >= 0.0 && qk0 < (double)d.nk)) return -1;
+    const int64_t ix0 = (int64_t)qx0, ik0 = (int64_t)qk0;
+    if (DIM == 1) return ix0 + (int64_t)d.nx * ik0;
+    const double qx1 = (x1 - d.x_lo) / d.dx;
+    const double qk1 = (k1 - d.k_lo) / d.dk;
+    if (!(qx1 >= 0.0 && qx1 < (double)d.nx)) return -1;
+    if (!(qk1 >= 0.0 && qk1 < (double)d.nk)) return -1;
+    const int64_t ix1 = (int64_t)qx1, ik1 = (int64_t)qk1;
+    return ((ik1 * d.nk + ik0) * d.nx + ix1) * d.nx + ix0;
+}
+
+// Uniform position in cell nu from the uniforms of draw sub 0 (axis 0) and 1.
+template <int DIM>
+__device__ __forceinline__ void cell_point(const Dev &d, int64_t nu, uint64_t id, uint32_t tag,
+                                           uint32_t step, uint32_t key, double *x, double *k)
+{
+    int64_t ix[2], ik[2];
+    if (DIM == 1) {
+        ix[0] = nu % d.nx;
+        ik[0] = nu / d.nx;
+    } else {
+        int64_t r = nu;
+        ix[0] = r % d.nx; r /= d.nx;
+        ix[1] = r % d.nx; r /= d.nx;
+        ik[0] = r % d.nk; r /= d.nk;
+        ik[1] = r;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const W4 u = draw(id, step, tag, 0u, (uint32_t)a, d.seed, key);
+        x[a] = d.x_lo + ((double)ix[a] + unit53(u.a, u.b)) * d.dx;
+        k[a] = d.k_lo + ((double)ik[a] + unit53(u.c, u.d)) * d.dk;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial ensembles: x ~ N(mean_x, sigma_x), k ~ N(mean_k, sigma_k) per axis by
+// Box-Muller on draw (id = j, step 0, tag init, sub = axis); sign +1.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_init(Dev d, double mx0, double mx1, double sx0,
+                                                   double sx1, double mk0, double mk1, double sk0,
+                                                   double sk1)
+{
+    const int B = d.B;
+    const int64_t *plan = d.tileA;
+    const int64_t ntiles = plan[B];
+    const Ens E = d.ens[0];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int b = segment_of(plan, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t n = d.N[b];
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + threadIdx.x;
+            if (li >= n) continue;
+            const int64_t i = P.base + li;
+            const double mx[2] = {mx0, mx1}, sx[2] = {sx0, sx1}, mk[2] = {mk0, mk1}, sk[2] = {sk0, sk1};
+            double xo[2], ko[2];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const W4 r = draw((uint64_t)li, 0u, kTagInit, 0u, (uint32_t)a, d.seed, P.key);
+                const double u1 = unit53(r.a, r.b), u2 = unit53(r.c, r.d);
+                const double R = sqrt(-2.0 * ln_series(1.0 - u1));
+                const double th = kTwoPi * u2;
+                const double z1 = R * cos_det(th);
+                const double z2 = R * sin_det(th);
+                xo[a] = mx[a] + sx[a] * z1;
+                ko[a] = mk[a] + sk[a] * z2;
+            }
+            E.x0[i] = xo[0];
+            E.k0[i] = ko[0];
+            if (DIM == 2) { E.x1[i] = xo[1]; E.k1[i] = ko[1]; }
+            if (d.strategy == 1) E.w[i] = 1.0; else E.sg[i] = 1;
+            E.id[i] = (uint64_t)li;
+            if (d.tangent) {
+                E.D[i] = 0.0;
+                E.D[d.cap_total + i] = 0.0;
+                E.D[2 * d.cap_total + i] = 0.0;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sp1 annihilation, pass 1: binning with exact integer sums per cell.
+// ---------------------------------------------------------------------------
+template <int DIM, bool TAN>
+__global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
+{
+    __shared__ int64_t s_t;
+    __shared__ int64_t s_esc;
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
+    const int64_t ntiles = plan[B];
+    const int64_t *Ncur = ghost ? d.NG : d.N;
+    const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) { s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u); s_esc = 0; }
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= ntiles) break;
+        const int b = segment_of(plan, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t base = ghost ? P.gbase : P.base;
+        const int64_t n = Ncur[b];
+        const int64_t cbase = (int64_t)b * d.Nh;
+        int64_t esc = 0;
+#pragma unroll 4
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            if (li >= n) continue;
+            const int64_t i = base + li;
+            const int64_t nu = cell_index<DIM>(d, E.x0[i], DIM == 2 ? E.x1[i] : 0.0, E.k0[i],
+                                               DIM == 2 ? E.k1[i] : 0.0);
+            const int s = ghost ? 0 : (int)E.sg[i];
+            if (nu < 0) { esc += s; continue; }
+            if (!ghost) atomicAdd(&d.cnt[cbase + nu], s);
+            if (TAN) {
+                atomicAdd(&d.occ[cbase + nu], 1);
+                const int64_t nc = d.Nh * (int64_t)B;
+                atomicAdd(&d.Tcell[cbase + nu], E.D[i]);
+                atomicAdd(&d.Tcell[nc + cbase + nu], E.D[d.cap_total + i]);
+                atomicAdd(&d.Tcell[2 * nc + cbase + nu], E.D[2 * d.cap_total + i]);
+            }
+        }
+        if (esc) atomicAdd((unsigned long long *)&s_esc, (unsigned long long)esc);
+        __syncthreads();
+        if (tid == 0 && s_esc)
+            atomicAdd((unsigned long long *)&d.tally[(int64_t)b * kTalCount + kTalEscaped],
+                      (unsigned long long)s_esc);
+        __syncthreads();
+    }
+    if (last_block_done(&ctl->done[kPassTiles])) {
+        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sp1 annihilation, pass 2: ordered scan of |n_nu| per instance.
+// off[nu] = exclusive prefix | (n_nu < 0 ? bit 62 : 0); Nnew[b] = total.
+// With zero_counts the count grid is cleared for the next annihilation.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
+{
+    __shared__ int64_t s_t;
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_excl;
+    Ctl *ctl = d.ctl;
+    const uint32_t epoch = ctl->ann_seq + 1u;
+    const int B = d.B;
+    const int64_t tiles_per = (d.Nh + kTileS - 1) / kTileS;
+    const int64_t ntiles = tiles_per * B;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassScan], 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= ntiles) break;
+        const int b = (int)(t / tiles_per);
+        const int64_t tl = t - (int64_t)b * tiles_per;
+        const int64_t cbase = (int64_t)b * d.Nh;
+        // thread owns kPPT consecutive cells
+        const int64_t c0 = tl * kTileS + (int64_t)tid * kPPT;
+        int32_t v[kPPT];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t c = c0 + j;
+            v[j] = (c < d.Nh) ? d.cnt[cbase + c] : 0;
+            sum += (uint32_t)(v[j] < 0 ? -v[j] : v[j]);
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) s_wsum[wv] = incl;
+        __syncthreads();
+        uint32_t woff = 0, agg = 0;
+        for (int q = 0; q < 4; ++q) { if (q < wv) woff += s_wsum[q]; agg += s_wsum[q]; }
+        if (tid == 0) {
+            uint32_t excl = 0;
+            if (tl == 0) {
+                lb_publish(d.stS + t, epoch, 2u, agg);
+            } else {
+                lb_publish(d.stS + t, epoch, 1u, agg);
+                excl = lb_lookback(d.stS, t, (int64_t)b * tiles_per, epoch);
+                lb_publish(d.stS + t, epoch, 2u, excl + agg);
+            }
+            if (tl == tiles_per - 1) d.Nnew[b] = (int64_t)(excl + agg);
+            s_excl = excl;
+        }
+        __syncthreads();
+        int64_t run = (int64_t)s_excl + (int64_t)(woff + incl - sum);
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t c = c0 + j;
+            if (c < d.Nh) {
+                d.off[cbase + c] = run | (v[j] < 0 ? kOffNeg : 0);
+                run += (v[j] < 0 ? -v[j] : v[j]);
+                if (zero_counts && v[j] != 0) d.cnt[cbase + c] = 0;
+            }
+        }
+        __syncthreads();
+    }
+    if (last_block_done(&ctl->done[kPassScan])) {
+        for (int b = tid; b < B; b += kThreads) {
+            if (d.Nnew[b] > d.ip[b].cap) {
+                atomicOr(&ctl->err, kErrCapacity);
+                d.Nnew[b] = d.ip[b].cap;
+            }
+        }
+        __syncthreads();
+        block_plan(d.tileR, d.Nnew, B, kTileR);
+        if (tid == 0) { ctl->ticket[kPassScan] = 0u; ctl->done[kPassScan] = 0u; }
+    }
+}
+
+// largest cell nu with (off[nu] & mask) <= o
+__device__ __forceinline__ int64_t cell_of_output(const int64_t *off, int64_t Nh, int64_t o)
+{
+    int64_t lo = 0, hi = Nh - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if ((off[mid] & kOffMask) <= o) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// sp1/sp2 annihilation, pass 3: regeneration into the inactive buffer set.
+// ---------------------------------------------------------------------------
+template <int DIM, bool SP2, bool TAN>
+__global__ __launch_bounds__(kThreads) void k_regen(Dev d)
+{
+    __shared__ int64_t s_t;
+    Ctl *ctl = d.ctl;
+    const uint32_t step = ctl->step;
+    const int B = d.B;
+    const int64_t ntiles = d.tileR[B];
+    const Ens O = pick_set(d, 0, ctl->cur ^ 1u);
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassRegen], 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        __syncthreads();
+        if (t >= ntiles) break;
+        const int b = segment_of(d.tileR, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t nout = d.Nnew[b];
+        const int64_t cbase = (int64_t)b * d.Nh;
+        const int64_t *off = d.off + cbase;
+        for (int j = 0; j < kTileR / kThreads; ++j) {
+            const int64_t o = (t - d.tileR[b]) * kTileR + (int64_t)j * kThreads + tid;
+            if (o >= nout) break;
+            const int64_t nu = cell_of_output(off, d.Nh, o);
+            const int64_t onu = off[nu];
+            const int64_t jj = o - (onu & kOffMask);
+            const uint64_t id = ((uint64_t)nu << 32) | (uint64_t)jj;
+            double x[2] = {0.0, 0.0}, k[2] = {0.0, 0.0};
+            cell_point<DIM>(d, nu, id, kTagRegen, step, P.key, x, k);
+            const int64_t i = P.base + o;
+            O.x0[i] = x[0];
+            O.k0[i] = k[0];
+            if (DIM == 2) { O.x1[i] = x[1]; O.k1[i] = k[1]; }
+            const bool neg = (onu & kOffNeg) != 0;
+            if (SP2) O.w[i] = neg ? -1.0 : 1.0; else O.sg[i] = neg ? (int8_t)-1 : (int8_t)1;
+            O.id[i] = id;
+            if (TAN) {
+                const int64_t nxt = (nu + 1 < d.Nh) ? (off[nu + 1] & kOffMask) : nout;
+                const double an = (double)(nxt - (onu & kOffMask));
+                const int64_t nc = d.Nh * (int64_t)B;
+                O.D[i] = d.Tcell[cbase + nu] / an;
+                O.D[d.cap_total + i] = d.Tcell[nc + cbase + nu] / an;
+                O.D[2 * d.cap_total + i] = d.Tcell[2 * nc + cbase + nu] / an;
+            }
+        }
+    }
+    if (last_block_done(&ctl->done[kPassRegen])) {
+        for (int b = tid; b < B; b += kThreads) d.N[b] = d.Nnew[b];
+        __syncthreads();
+        block_plan(d.tileA, d.N, B, kTileA);
+        if (tid == 0) {
+            ctl->cur ^= 1u;
+            ctl->ann_seq += 1u;
+            ctl->ticket[kPassRegen] = 0u;
+            ctl->done[kPassRegen] = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Density: bins of width (hi - lo)/nbins on position axis `axis`.
+// ---------------------------------------------------------------------------
+template <int DIM, bool SP2, bool TAN>
+__global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int axis, int nbins,
+                                                          double lo, double dxb)
+{
+    __shared__ int64_t s_t;
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
+    const int64_t ntiles = plan[B];
+    const int64_t *Ncur = ghost ? d.NG : d.N;
+    const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
+    const double *X = (axis == 1) ? E.x1 : E.x0;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        __syncthreads();
+        if (t >= ntiles) break;
+        const int b = segment_of(plan, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t base = ghost ? P.gbase : P.base;
+        const int64_t n = Ncur[b];
+#pragma unroll 4
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            if (li >= n) continue;
+            const int64_t i = base + li;
+            const double q = (X[i] - lo) / dxb;
+            if (!(q >= 0.0 && q < (double)nbins)) continue;
+            const int64_t bin = (int64_t)q;
+            if (TAN) {
+                double *acc = d.dTacc + (int64_t)b * 3 * d.max_bins;
+                atomicAdd(&acc[bin], E.D[i]);
+                atomicAdd(&acc[d.max_bins + bin], E.D[d.cap_total + i]);
+                atomicAdd(&acc[2 * d.max_bins + bin], E.D[2 * d.cap_total + i]);
+            } else {
+                int64_t v;
+                if (SP2) v = (int64_t)(E.w[i] * 4294967296.0); else v = (int64_t)E.sg[i];
+                atomicAdd((unsigned long long *)&d.dacc[(int64_t)b * d.max_bins + bin],
+                          (unsigned long long)v);
+            }
+        }
+    }
+    if (last_block_done(&ctl->done[kPassTiles])) {
+        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
+    }
+}
+
+// out[b][j] = acc / (N0_b dxb); the accumulator is cleared.
+template <bool SP2, bool TAN>
+__global__ __launch_bounds__(kThreads) void k_density_out(Dev d, int nbins, double dxb, double *out)
+{
+    const int B = d.B;
+    const int comps = TAN ? 3 : 1;
+    const int64_t total = (int64_t)B * comps * nbins;
+    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * kThreads) {
+        const int64_t b = g / ((int64_t)comps * nbins);
+        const int64_t r = g - b * comps * nbins;
+        const int64_t c = r / nbins, j = r - c * nbins;
+        const double denom = (double)d.ip[b].N0 * dxb;
+        if (TAN) {
+            double *acc = d.dTacc + b * 3 * d.max_bins + c * d.max_bins + j;
+            out[g] = *acc / denom;
+            *acc = 0.0;
+        } else {
+            int64_t *acc = d.dacc + b * d.max_bins + j;
+            double v = (double)*acc;
+            if (SP2) v = v * 0x1p-32;
+            out[g] = v / denom;
+            *acc = 0;
+        }
+    }
+}
+
+// Clears `n` 64-bit words (used instead of hipMemsetAsync so that every
+// enqueued operation is a kernel).
+__global__ __launch_bounds__(kThreads) void k_fill64(uint64_t *p, int64_t n, uint64_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        p[i] = v;
+}
+
+}  // namespace wbrw

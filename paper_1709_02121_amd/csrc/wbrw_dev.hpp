@@ -1,0 +1,222 @@
+// Device-side data layout of the WBRW library.
+//
+// Particles of all instances live in one structure of arrays; instance b owns
+// the segment [base_b, base_b + cap_b).  Two such sets exist and annihilation
+// writes the regenerated ensemble into the inactive one ("cur" flips).  All
+// mutable bookkeeping (counts, tile plans, tickets, look-back status words,
+// tallies, the step counter) is device resident, so a step or an epoch can be
+// enqueued, or captured into a hipGraph, without host round trips.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wbrw {
+
+constexpr int kMaxM = 4;
+constexpr int kThreads = 256;           // threads per block in every kernel
+constexpr int kPPT = 8;                 // particles (or cells) per thread in streaming passes
+constexpr int kTileA = kThreads * kPPT; // particles per streaming tile
+constexpr int kTileB = kThreads;        // event-parents per family tile
+constexpr int kTileS = kThreads * kPPT; // cells per scan tile
+constexpr int kTileR = kThreads * 4;    // regenerated particles per tile
+constexpr int kMaxDepth = 16;           // deepest family tree walked within one step
+constexpr uint32_t kEventCap = 4096u;   // jumps per particle-step
+
+enum : uint32_t { kErrCapacity = 1u, kErrDepth = 2u };
+
+// tally slots per instance
+enum : int {
+    kTalEvents = 0, kTalPairs, kTalKilled, kTalEscaped, kTalMaxDepth, kTalEventCap,
+    kTalSplus, kTalSminus, kTalNplus, kTalNminus, kTalPSteps, kTalCount = 16
+};
+
+// ticket / done slots
+enum : int {
+    kPassStream = 0, kPassFamily = 1, kPassStreamG = 2, kPassFamilyG = 3,
+    kPassScan = 4, kPassRegen = 5, kPassTiles = 6, kPassGhost = 7, kPassCount = 8
+};
+
+struct InstParam {
+    double gamma0;
+    double thr_lo, thr_hi;          // certain-jump / certain-no-jump band on the first uniform
+    double c[kMaxM];                // xi_m / (2 gamma0)
+    double sq[kMaxM];               // Gaussian kick std 1/(2w)
+    double H[kMaxM], width[kMaxM];  // Gaussian parameters (tangent scores)
+    double center[kMaxM];           // centre of the kernel phase
+    double sgnV[kMaxM];             // sign of F[V_m]
+    int64_t base, cap;              // particle segment
+    int64_t gbase, gcap;            // ghost segment
+    int64_t N0;                     // sample size N_alpha
+    uint32_t key;                   // Philox key word 1
+    uint32_t pad;
+};
+
+struct Table {
+    const double *cum;  // n + 1 cumulative sums of |F[V](2q_j)|
+    int32_t n;
+    int32_t pad;
+    double q_lo, dq;
+};
+
+struct Ens {
+    double *x0, *x1, *k0, *k1;
+    int8_t *sg;
+    double *w;
+    uint64_t *id;
+    double *D;     // planar [3][cap_total]
+};
+
+struct Ctl {
+    uint32_t step;             // steps completed (Philox counter word 2)
+    uint32_t cur;              // active real buffer set
+    uint32_t gcur;             // active ghost buffer set
+    uint32_t err;              // sticky error bits
+    uint32_t ann_seq;          // annihilations so far (look-back epoch of the scans)
+    uint32_t pad[3];
+    uint32_t ticket[kPassCount];
+    uint32_t done[kPassCount];
+};
+
+struct Dev {
+    // sizes and constants
+    int32_t B, dim, M, strategy, tangent;
+    int32_t nx, nk;
+    uint32_t seed;
+    int64_t Nh;                 // cells per instance
+    int64_t cap_total, gcap_total;
+    double dt, vfac;
+    double x_lo, x_hi, k_lo, k_hi, dx, dk;
+    int32_t kind[kMaxM], axis[kMaxM];
+    Table tab[kMaxM];
+    // buffers
+    Ens ens[2], gens[2];
+    const InstParam *ip;
+    Ctl *ctl;
+    int64_t *N, *NG, *Nnew, *NGnew;
+    int64_t *evc;               // [2][B] event counts (real, ghost)
+    int64_t *chc;               // [2][B] child counts
+    int64_t *tileA;             // [2][B+1] streaming-tile plan (real, ghost)
+    int64_t *tileB;             // [2][B+1] family-tile plan
+    int64_t *tileR;             // [B+1] regeneration-tile plan
+    int64_t *tileG;             // [B+1] ghost-regeneration plan
+    int64_t *tally;             // [B][kTalCount]
+    uint32_t *ev_idx;           // [cap_total] event-parent index within its instance
+    double *ev_x0, *ev_x1;      // [cap_total] its position at the start of the step
+    uint32_t *gev_idx;          // ghosts
+    double *gev_x0, *gev_x1;
+    uint64_t *stA, *stAg, *stB, *stBg, *stS, *stG;   // look-back status words
+    int32_t *cnt;               // [B][Nh] signed counts (sp1) / rounded counts (sp2)
+    int64_t *off;               // [B][Nh] exclusive prefix of |n_nu|, bit 62 = negative cell
+    int32_t *occ;               // [B][Nh] occupancy (tangents)
+    double *Tcell;              // [3][B][Nh] tangent sums per cell
+    int32_t *ntil;              // [2][B][Nh] sp2 bootstrap counts per class
+    int64_t *dacc;              // [B][max_bins] density accumulator
+    double *dTacc;              // [B][3][max_bins] tangent density accumulator
+    int32_t max_bins;
+    // sp2 bootstrap scratch
+    uint64_t *bA;               // [cap_total] quantised weight
+    int32_t *bcopies;           // [cap_total] copies per particle
+    int8_t *bcls;               // [cap_total] class (0 +, 1 -, -1 none)
+    int64_t *bcell;             // [cap_total] cell or -1
+    uint64_t *bP;               // [2][cap_total] 128-bit residual prefix (lo, hi interleaved)
+    uint64_t *bTile;            // [2][tiles] 128-bit tile sums
+    int64_t *bcls_stat;         // [B][8]: N+, N-, S+, S-, sumk+, sumk-, Nr+, Nr-
+    int64_t *tileD;             // [2][B+1] draw-tile plan (per class)
+    int64_t *bscan_tiles;       // [B+1] tiles per instance for the residual scan
+    int64_t tstride;            // tiles per class in bTile
+};
+
+__device__ __forceinline__ Ens pick_set(const Dev &d, int ghost, uint32_t which)
+{
+    if (ghost) return which ? d.gens[1] : d.gens[0];
+    return which ? d.ens[1] : d.ens[0];
+}
+
+// segment b with plan[b] <= t < plan[b+1]
+__device__ __forceinline__ int segment_of(const int64_t *plan, int B, int64_t t)
+{
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (plan[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---- decoupled look-back (single-pass ordered scans) ----------------------
+// status word: [epoch:30 | flag:2 | value:32]; flag 1 = tile aggregate, 2 = inclusive prefix
+__device__ __forceinline__ void lb_publish(uint64_t *st, uint32_t epoch, uint32_t flag, uint32_t v)
+{
+    const uint64_t w = ((uint64_t)((epoch << 2) | flag) << 32) | (uint64_t)v;
+    __hip_atomic_store(st, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// exclusive prefix of tile t over the tiles [first, t) of its segment
+__device__ __forceinline__ uint32_t lb_lookback(uint64_t *st, int64_t t, int64_t first, uint32_t epoch)
+{
+    uint32_t excl = 0;
+    int64_t p = t - 1;
+    while (p >= first) {
+        uint64_t w;
+        for (;;) {
+            w = __hip_atomic_load(st + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t hi = (uint32_t)(w >> 32);
+            if ((hi >> 2) == epoch && (hi & 3u) != 0u) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        excl += (uint32_t)w;
+        if (((uint32_t)(w >> 32) & 3u) == 2u) break;
+        --p;
+    }
+    return excl;
+}
+
+// The calling block is the last of the grid to finish (all other blocks'
+// global writes are visible afterwards).  Must be called by every thread.
+__device__ __forceinline__ bool last_block_done(uint32_t *done_ctr)
+{
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(done_ctr, 1u);
+        s_last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_last) __threadfence();
+    return s_last != 0;
+}
+
+// plan[b] = sum_{b' < b} ceil(cnt[b'] / tile), plan[B] = total; one block.
+__device__ __forceinline__ void block_plan(int64_t *plan, const int64_t *cnt, int B, int64_t tile)
+{
+    __shared__ int64_t s_v[kThreads];
+    __shared__ int64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < B; c0 += kThreads) {
+        const int b = c0 + (int)threadIdx.x;
+        const int64_t v = (b < B) ? (cnt[b] + tile - 1) / tile : 0;
+        s_v[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kThreads; o <<= 1) {
+            const int64_t add = (threadIdx.x >= (unsigned)o) ? s_v[threadIdx.x - o] : 0;
+            __syncthreads();
+            s_v[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (b < B) plan[b] = s_carry + s_v[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == kThreads - 1) s_carry += s_v[kThreads - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) plan[B] = s_carry;
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+}  // namespace wbrw

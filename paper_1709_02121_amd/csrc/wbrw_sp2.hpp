@@ -1,0 +1,558 @@
+// sp2 annihilation: the signed residual bootstrap (Alg. 2 applied to each sign
+// class, Eqs. lambda and double_bootstrap of Sec. 3.3), the histogram of the
+// filtered classes (Eq. boostrap_histogram, Sec. 4.3) and the rounding step of
+// Alg. 3; plus the tangent ghosts of the differentiation form.
+//
+// The weights are quantised once, A_i = floor(|w_i| 2^32); everything after
+// that is exact integer arithmetic, so the result does not depend on the order
+// in which the GPU reduces:
+//   N_c, S_c = sum A_i                    per class c (integer atomics)
+//   k_i = floor(N_c A_i / S_c), r_i = N_c A_i - k_i S_c   (copies kept, residual)
+//   P_c = exclusive prefix of r_i over the class in particle order (128-bit)
+//   N_r = N_c - sum k_i draws U_d uniform in [0, S_c N_r), each adding one copy
+//         to the i with P_c[i] <= U_d < P_c[i+1]
+//   n~_c[nu] = sum of copies per cell
+//   m_nu = |S+ n~+ N- - S- n~- N+| / (2^32 N+ N-), rounded up with probability
+//          equal to its fractional part (one uniform per cell), sign of the
+//          difference; then the sp1 scan / regeneration.
+#pragma once
+#include "wbrw_cells.hpp"
+#include "wbrw_dev.hpp"
+#include "wbrw_math.hpp"
+
+namespace wbrw {
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+// bcls_stat slots per instance
+enum : int { kBN0 = 0, kBN1, kBS0, kBS1, kBK0, kBK1, kBNr0, kBNr1 };
+
+// floor(r * R / 2^64): an integer uniform on [0, R) from 64 random bits
+__device__ __forceinline__ u128 scale64(uint64_t r, u128 R)
+{
+    const uint64_t lo = (uint64_t)R;
+    const u128 hi = R >> 64;
+    return (u128)r * hi + (((u128)r * (u128)lo) >> 64);
+}
+
+__device__ __forceinline__ void st128(uint64_t *p, u128 v)
+{
+    p[0] = (uint64_t)v;
+    p[1] = (uint64_t)(v >> 64);
+}
+
+__device__ __forceinline__ u128 ld128(const uint64_t *p)
+{
+    return ((u128)p[1] << 64) | (u128)p[0];
+}
+
+// ---- stage 1: classes, quantised weights, cells; class sizes and sums ------
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
+{
+    __shared__ int64_t s_t;
+    __shared__ unsigned long long s_acc[5];   // N0, N1, S0, S1, escaped
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int64_t *plan = d.tileA;
+    const int64_t ntiles = plan[B];
+    const Ens E = pick_set(d, 0, ctl->cur);
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        if (tid < 5) s_acc[tid] = 0ull;
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= ntiles) break;
+        const int b = segment_of(plan, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t n = d.N[b];
+        unsigned long long a_n0 = 0, a_n1 = 0, a_s0 = 0, a_s1 = 0;
+        long long a_esc = 0;
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            if (li >= n) continue;
+            const int64_t i = P.base + li;
+            const double w = E.w[i];
+            const uint64_t A = (uint64_t)floor(fabs(w) * 4294967296.0);
+            const int64_t nu = cell_index<DIM>(d, E.x0[i], DIM == 2 ? E.x1[i] : 0.0, E.k0[i],
+                                               DIM == 2 ? E.k1[i] : 0.0);
+            int8_t cls = -1;
+            if (nu < 0) {
+                a_esc += w < 0.0 ? -(long long)A : (long long)A;
+            } else if (w > 0.0) {
+                cls = 0; a_n0 += 1; a_s0 += A;
+            } else if (w < 0.0) {
+                cls = 1; a_n1 += 1; a_s1 += A;
+            }
+            d.bcls[i] = cls;
+            d.bA[i] = cls >= 0 ? A : 0ull;
+            d.bcell[i] = nu;
+        }
+        if (a_n0) atomicAdd(&s_acc[0], a_n0);
+        if (a_n1) atomicAdd(&s_acc[1], a_n1);
+        if (a_s0) atomicAdd(&s_acc[2], a_s0);
+        if (a_s1) atomicAdd(&s_acc[3], a_s1);
+        if (a_esc) atomicAdd(&s_acc[4], (unsigned long long)a_esc);
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long *st = (unsigned long long *)(d.bcls_stat + (int64_t)b * 8);
+            for (int q = 0; q < 4; ++q)
+                if (s_acc[q]) atomicAdd(&st[q], s_acc[q]);
+            if (s_acc[4])
+                atomicAdd((unsigned long long *)&d.tally[(int64_t)b * kTalCount + kTalEscaped], s_acc[4]);
+        }
+        __syncthreads();
+    }
+    if (last_block_done(&ctl->done[kPassTiles])) {
+        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
+    }
+}
+
+// ---- stage 2: kept copies k_i, residuals r_i, per-tile residual sums --------
+__global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
+{
+    __shared__ int64_t s_t;
+    __shared__ unsigned long long s_acc[6];    // sumk0, sumk1, tile sums (lo,hi) x 2
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int64_t *plan = d.tileA;
+    const int64_t ntiles = plan[B];
+    const int tid = threadIdx.x;
+    const int64_t C = d.cap_total;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        if (tid < 6) s_acc[tid] = 0ull;
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= ntiles) break;
+        const int b = segment_of(plan, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t n = d.N[b];
+        const int64_t *st = d.bcls_stat + (int64_t)b * 8;
+        const uint64_t Nc[2] = {(uint64_t)st[kBN0], (uint64_t)st[kBN1]};
+        const uint64_t Sc[2] = {(uint64_t)st[kBS0], (uint64_t)st[kBS1]};
+        unsigned long long sk[2] = {0, 0};
+        u128 rs[2] = {0, 0};
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            if (li >= n) continue;
+            const int64_t i = P.base + li;
+            const int8_t c = d.bcls[i];
+            uint64_t k = 0, r = 0;
+            if (c >= 0 && Sc[c] > 0) {
+                const uint64_t num = Nc[c] * d.bA[i];       // < 2^63
+                k = num / Sc[c];
+                r = num - k * Sc[c];
+                sk[c] += k;
+                rs[c] += r;
+            }
+            d.bcopies[i] = (int32_t)k;
+            d.bP[2 * i] = r;           // residual, replaced by the prefix in stage 4
+            d.bP[2 * i + 1] = 0;
+        }
+        // block sums: 64-bit halves of the 128-bit residual sums
+        for (int c = 0; c < 2; ++c) {
+            if (sk[c]) atomicAdd(&s_acc[c], sk[c]);
+            // residual sums of a thread stay < 2^66: add as lo + carry-free hi
+            const uint64_t lo = (uint64_t)rs[c], hi = (uint64_t)(rs[c] >> 64);
+            const unsigned long long old = atomicAdd(&s_acc[2 + 2 * c], (unsigned long long)lo);
+            const uint64_t carry = (old + lo < old) ? 1ull : 0ull;
+            if (hi + carry) atomicAdd(&s_acc[3 + 2 * c], (unsigned long long)(hi + carry));
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long *bs = (unsigned long long *)(d.bcls_stat + (int64_t)b * 8);
+            if (s_acc[0]) atomicAdd(&bs[kBK0], s_acc[0]);
+            if (s_acc[1]) atomicAdd(&bs[kBK1], s_acc[1]);
+            for (int c = 0; c < 2; ++c) {
+                uint64_t *ts = d.bTile + 2 * ((int64_t)c * d.tstride + t);
+                ts[0] = s_acc[2 + 2 * c];
+                ts[1] = s_acc[3 + 2 * c];
+            }
+        }
+        __syncthreads();
+    }
+    if (last_block_done(&ctl->done[kPassTiles])) {
+        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
+    }
+}
+
+// ---- stage 3: exclusive scan of the tile sums per instance and class; the
+// draw counts N_r and the draw-tile plan.  One block per instance. ----------
+__global__ __launch_bounds__(kThreads) void k_sp2_tilescan(Dev d)
+{
+    __shared__ uint64_t s_lo[kThreads], s_hi[kThreads];
+    __shared__ uint64_t s_clo, s_chi;
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const int64_t t0 = d.tileA[b], t1 = d.tileA[b + 1];
+        for (int c = 0; c < 2; ++c) {
+            uint64_t *ts = d.bTile + 2 * ((int64_t)c * d.tstride);
+            if (tid == 0) { s_clo = 0; s_chi = 0; }
+            __syncthreads();
+            for (int64_t c0 = t0; c0 < t1; c0 += kThreads) {
+                const int64_t t = c0 + tid;
+                u128 v = (t < t1) ? ld128(ts + 2 * t) : (u128)0;
+                // inclusive Hillis-Steele scan in LDS
+                s_lo[tid] = (uint64_t)v;
+                s_hi[tid] = (uint64_t)(v >> 64);
+                __syncthreads();
+                for (int o = 1; o < kThreads; o <<= 1) {
+                    u128 add = 0;
+                    if (tid >= o) add = ((u128)s_hi[tid - o] << 64) | s_lo[tid - o];
+                    __syncthreads();
+                    const u128 cur = (((u128)s_hi[tid] << 64) | s_lo[tid]) + add;
+                    s_lo[tid] = (uint64_t)cur;
+                    s_hi[tid] = (uint64_t)(cur >> 64);
+                    __syncthreads();
+                }
+                const u128 carry = ((u128)s_chi << 64) | s_clo;
+                const u128 incl = (((u128)s_hi[tid] << 64) | s_lo[tid]) + carry;
+                if (t < t1) st128(ts + 2 * t, incl - v);   // exclusive
+                __syncthreads();
+                if (tid == kThreads - 1) { s_clo = (uint64_t)incl; s_chi = (uint64_t)(incl >> 64); }
+                __syncthreads();
+            }
+        }
+        if (tid == 0) {
+            int64_t *st = d.bcls_stat + (int64_t)b * 8;
+            st[kBNr0] = st[kBN0] - st[kBK0];
+            st[kBNr1] = st[kBN1] - st[kBK1];
+            if (st[kBS0] == 0) st[kBNr0] = 0;
+            if (st[kBS1] == 0) st[kBNr1] = 0;
+            d.Nnew[b] = st[kBNr0];            // staging for the draw plan (class 0)
+            d.NGnew[b] = st[kBNr1];           // (class 1)
+        }
+        __syncthreads();
+    }
+    if (last_block_done(&ctl->done[kPassScan])) {
+        block_plan(d.tileD, d.Nnew, B, kTileR);
+        block_plan(d.tileD + (B + 1), d.NGnew, B, kTileR);
+        if (tid == 0) { ctl->ticket[kPassScan] = 0u; ctl->done[kPassScan] = 0u; }
+    }
+}
+
+// ---- stage 4: per-particle exclusive prefixes P_0, P_1 (128-bit) -----------
+__global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
+{
+    __shared__ int64_t s_t;
+    __shared__ uint64_t s_lo[2][kThreads], s_hi[2][kThreads];
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int64_t *plan = d.tileA;
+    const int64_t ntiles = plan[B];
+    const int64_t C = d.cap_total;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= ntiles) break;
+        const int b = segment_of(plan, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t n = d.N[b];
+        // this thread's kPPT particles are consecutive: li0 .. li0 + kPPT - 1
+        const int64_t li0 = (t - plan[b]) * kTileA + (int64_t)tid * kPPT;
+        uint64_t r[kPPT];
+        int8_t cl[kPPT];
+        u128 sum[2] = {0, 0};
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = li0 + j;
+            r[j] = 0;
+            cl[j] = -1;
+            if (li < n) {
+                const int64_t i = P.base + li;
+                r[j] = d.bP[2 * i];
+                cl[j] = d.bcls[i];
+                if (cl[j] >= 0) sum[cl[j]] += r[j];
+            }
+        }
+        for (int c = 0; c < 2; ++c) { s_lo[c][tid] = (uint64_t)sum[c]; s_hi[c][tid] = (uint64_t)(sum[c] >> 64); }
+        __syncthreads();
+        for (int o = 1; o < kThreads; o <<= 1) {
+            u128 add[2] = {0, 0};
+            if (tid >= o)
+                for (int c = 0; c < 2; ++c) add[c] = ((u128)s_hi[c][tid - o] << 64) | s_lo[c][tid - o];
+            __syncthreads();
+            for (int c = 0; c < 2; ++c) {
+                const u128 cur = (((u128)s_hi[c][tid] << 64) | s_lo[c][tid]) + add[c];
+                s_lo[c][tid] = (uint64_t)cur;
+                s_hi[c][tid] = (uint64_t)(cur >> 64);
+            }
+            __syncthreads();
+        }
+        u128 run[2];
+        for (int c = 0; c < 2; ++c) {
+            const uint64_t *ts = d.bTile + 2 * ((int64_t)c * d.tstride + t);
+            run[c] = ld128(ts) + ((((u128)s_hi[c][tid] << 64) | s_lo[c][tid]) - sum[c]);
+        }
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = li0 + j;
+            if (li >= n) continue;
+            const int64_t i = P.base + li;
+            st128(d.bP + 2 * i, run[0]);
+            st128(d.bP + 2 * C + 2 * i, run[1]);
+            if (cl[j] >= 0) run[cl[j]] += r[j];
+        }
+        __syncthreads();
+    }
+    if (last_block_done(&ctl->done[kPassTiles])) {
+        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
+    }
+}
+
+// ---- stage 5: the N_r i.i.d. draws of each class (Alg. 2 step 2) ------------
+__global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
+{
+    __shared__ int64_t s_t;
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const uint32_t step = ctl->step;
+    const int64_t n0 = d.tileD[B], ntiles = n0 + d.tileD[2 * B + 1];
+    const int64_t C = d.cap_total;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        __syncthreads();
+        if (t >= ntiles) break;
+        const int c = t < n0 ? 0 : 1;
+        const int64_t *plan = d.tileD + (int64_t)c * (B + 1);
+        const int64_t tc = t - (c ? n0 : 0);
+        const int b = segment_of(plan, B, tc);
+        const InstParam &P = d.ip[b];
+        const int64_t *st = d.bcls_stat + (int64_t)b * 8;
+        const int64_t Nr = st[kBNr0 + c];
+        const u128 R = (u128)(uint64_t)st[kBS0 + c] * (u128)(uint64_t)Nr;
+        const int64_t n = d.N[b];
+        const uint64_t *Pc = d.bP + 2 * (int64_t)c * C + 2 * P.base;
+        for (int j = 0; j < kTileR / kThreads; ++j) {
+            const int64_t dd = (tc - plan[b]) * kTileR + (int64_t)j * kThreads + tid;
+            if (dd >= Nr) break;
+            const W4 w = draw((uint64_t)dd, step, kTagBoot, 0u, (uint32_t)c, d.seed, P.key);
+            const uint64_t bits = ((uint64_t)w.b << 32) | (uint64_t)w.a;
+            const u128 U = scale64(bits, R);
+            int64_t lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (ld128(Pc + 2 * mid) <= U) lo = mid; else hi = mid - 1;
+            }
+            atomicAdd(&d.bcopies[P.base + lo], 1);
+        }
+    }
+    if (last_block_done(&ctl->done[kPassTiles])) {
+        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
+    }
+}
+
+// ---- stage 6: filtered counts per cell and class ---------------------------
+__global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
+{
+    __shared__ int64_t s_t;
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int64_t *plan = d.tileA;
+    const int64_t ntiles = plan[B];
+    const int tid = threadIdx.x;
+    const int64_t plane = (int64_t)B * d.Nh;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        __syncthreads();
+        if (t >= ntiles) break;
+        const int b = segment_of(plan, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t n = d.N[b];
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            if (li >= n) continue;
+            const int64_t i = P.base + li;
+            const int8_t c = d.bcls[i];
+            const int32_t cp = d.bcopies[i];
+            if (c < 0 || cp == 0) continue;
+            atomicAdd(&d.ntil[(int64_t)c * plane + (int64_t)b * d.Nh + d.bcell[i]], cp);
+        }
+    }
+    if (last_block_done(&ctl->done[kPassTiles])) {
+        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
+    }
+}
+
+// ---- stage 7: exact rational cell values and the rounding step -------------
+__global__ __launch_bounds__(kThreads) void k_sp2_round(Dev d)
+{
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const uint32_t step = ctl->step;
+    const int64_t plane = (int64_t)B * d.Nh;
+    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < plane;
+         g += (int64_t)gridDim.x * kThreads) {
+        const int64_t b = g / d.Nh, nu = g - b * d.Nh;
+        const int32_t n0 = d.ntil[g], n1 = d.ntil[plane + g];
+        if (n0 == 0 && n1 == 0) continue;
+        d.ntil[g] = 0;
+        d.ntil[plane + g] = 0;
+        const int64_t *st = d.bcls_stat + b * 8;
+        const uint64_t N0 = (uint64_t)st[kBN0], N1 = (uint64_t)st[kBN1];
+        const uint64_t S0 = (uint64_t)st[kBS0], S1 = (uint64_t)st[kBS1];
+        i128 num;
+        u128 den;
+        if (N0 > 0 && N1 > 0) {
+            num = (i128)((u128)S0 * (u128)(uint64_t)n0 * (u128)N1) -
+                  (i128)((u128)S1 * (u128)(uint64_t)n1 * (u128)N0);
+            den = ((u128)N0 * (u128)N1) << 32;
+        } else if (N0 > 0) {
+            num = (i128)((u128)S0 * (u128)(uint64_t)n0);
+            den = (u128)N0 << 32;
+        } else {
+            num = -(i128)((u128)S1 * (u128)(uint64_t)n1);
+            den = (u128)N1 << 32;
+        }
+        if (num == 0) continue;
+        const u128 an = num < 0 ? (u128)(-num) : (u128)num;
+        const u128 q = an / den;
+        const u128 rem = an - q * den;
+        const W4 w = draw((uint64_t)nu, step, kTagRound, 0u, 0u, d.seed, d.ip[b].key);
+        const uint64_t bits = ((uint64_t)w.b << 32) | (uint64_t)w.a;
+        const u128 U = scale64(bits, den);
+        const int64_t m = (int64_t)q + (U < rem ? 1 : 0);
+        d.cnt[g] = (int32_t)(num < 0 ? -m : m);
+    }
+}
+
+// the last bootstrap's class sizes and sums into the tallies; clear the stats
+__global__ __launch_bounds__(kThreads) void k_sp2_close(Dev d)
+{
+    for (int b = blockIdx.x * kThreads + threadIdx.x; b < d.B; b += gridDim.x * kThreads) {
+        int64_t *st = d.bcls_stat + (int64_t)b * 8;
+        int64_t *T = d.tally + (int64_t)b * kTalCount;
+        T[kTalNplus] = st[kBN0];
+        T[kTalNminus] = st[kBN1];
+        T[kTalSplus] = st[kBS0];
+        T[kTalSminus] = st[kBS1];
+        for (int q = 0; q < 8; ++q) st[q] = 0;
+    }
+}
+
+template <int DIM>
+int enqueue_sp2_bootstrap(const Dev &d, hipStream_t s, int grid, int grid_scan)
+{
+    hipLaunchKernelGGL(k_sp2_classify<DIM>, dim3(grid), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_resid, dim3(grid), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_tilescan, dim3(std::min(d.B, grid_scan)), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_prefix, dim3(grid), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_draw, dim3(grid), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_cells, dim3(grid), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_round, dim3(grid), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_close, dim3(1), dim3(kThreads), 0, s, d);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// ---------------------------------------------------------------------------
+// Tangent ghosts: one per cell that was occupied but nets to zero, carrying the
+// cell's tangent sum T_nu; positions uniform in the cell (draw tag ghost, id
+// (1 << 62) | (nu << 32)); ascending cell order.  Also clears the count,
+// occupancy and tangent grids.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_ghosts(Dev d)
+{
+    __shared__ int64_t s_t;
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_excl;
+    Ctl *ctl = d.ctl;
+    const uint32_t epoch = ctl->ann_seq;      // already advanced by the regeneration
+    const uint32_t step = ctl->step;
+    const int B = d.B;
+    const int64_t tiles_per = (d.Nh + kTileS - 1) / kTileS;
+    const int64_t ntiles = tiles_per * B;
+    const Ens G = pick_set(d, 1, ctl->gcur ^ 1u);
+    const int64_t nc = d.Nh * (int64_t)B;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassGhost], 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= ntiles) break;
+        const int b = (int)(t / tiles_per);
+        const int64_t tl = t - (int64_t)b * tiles_per;
+        const int64_t cbase = (int64_t)b * d.Nh;
+        const InstParam &P = d.ip[b];
+        const int64_t c0 = tl * kTileS + (int64_t)tid * kPPT;
+        uint32_t flags = 0, sum = 0;
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t c = c0 + j;
+            if (c < d.Nh && d.cnt[cbase + c] == 0 && d.occ[cbase + c] > 0) { flags |= 1u << j; sum++; }
+        }
+        uint32_t incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) s_wsum[wv] = incl;
+        __syncthreads();
+        uint32_t woff = 0, agg = 0;
+        for (int q = 0; q < 4; ++q) { if (q < wv) woff += s_wsum[q]; agg += s_wsum[q]; }
+        if (tid == 0) {
+            uint32_t excl = 0;
+            if (tl == 0) {
+                lb_publish(d.stG + t, epoch, 2u, agg);
+            } else {
+                lb_publish(d.stG + t, epoch, 1u, agg);
+                excl = lb_lookback(d.stG, t, (int64_t)b * tiles_per, epoch);
+                lb_publish(d.stG + t, epoch, 2u, excl + agg);
+            }
+            if (tl == tiles_per - 1) d.NGnew[b] = (int64_t)(excl + agg);
+            s_excl = excl;
+        }
+        __syncthreads();
+        int64_t gi = (int64_t)s_excl + (int64_t)(woff + incl - sum);
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t c = c0 + j;
+            if (c >= d.Nh) break;
+            if ((flags >> j) & 1u) {
+                if (gi < P.gcap) {
+                    const int64_t o = P.gbase + gi;
+                    const uint64_t id = (1ull << 62) | ((uint64_t)c << 32);
+                    double x[2], k[2];
+                    cell_point<1>(d, c, id, kTagGhost, step, P.key, x, k);
+                    G.x0[o] = x[0];
+                    G.k0[o] = k[0];
+                    G.sg[o] = 0;
+                    G.id[o] = id;
+                    G.D[o] = d.Tcell[cbase + c];
+                    G.D[d.gcap_total + o] = d.Tcell[nc + cbase + c];
+                    G.D[2 * d.gcap_total + o] = d.Tcell[2 * nc + cbase + c];
+                }
+                gi++;
+            }
+            d.cnt[cbase + c] = 0;
+            d.occ[cbase + c] = 0;
+            d.Tcell[cbase + c] = 0.0;
+            d.Tcell[nc + cbase + c] = 0.0;
+            d.Tcell[2 * nc + cbase + c] = 0.0;
+        }
+        __syncthreads();
+    }
+    if (last_block_done(&ctl->done[kPassGhost])) {
+        for (int b = tid; b < B; b += kThreads) {
+            int64_t n = d.NGnew[b];
+            if (n > d.ip[b].gcap) { atomicOr(&ctl->err, kErrCapacity); n = d.ip[b].gcap; }
+            d.NG[b] = n;
+        }
+        __syncthreads();
+        block_plan(d.tileA + (B + 1), d.NG, B, kTileA);
+        if (tid == 0) {
+            ctl->gcur ^= 1u;
+            ctl->ticket[kPassGhost] = 0u;
+            ctl->done[kPassGhost] = 0u;
+        }
+    }
+}
+
+}  // namespace wbrw

@@ -1,0 +1,514 @@
+// One time step of the Wigner branching random walk (Alg. 1, Sec. 2) as two
+// persistent kernels.
+//
+// Pass 1, k_stream (HBM-bound): every particle draws its first life-length
+// (exact for a constant gamma0, Sec. 3.2.1), moves freely to the end of the
+// step (a particle keeps its k after a jump: offspring 2M+1 of Alg. 1, so its
+// end position does not depend on its jumps) and, if its first jump falls
+// inside the step, is appended to an ordered per-instance event list together
+// with its start position.  Ordering uses a wavefront ballot, an LDS scan over
+// the block and a decoupled look-back across tiles.  Only the first of the
+// two uniforms decides, and only a 1e-9-wide band around the threshold
+// evaluates the logarithm.
+//
+// Pass 2, k_family (latency-bound, ~3% of particles): one thread per event
+// parent walks the parent's whole family within the step, depth first: for
+// each jump in time order, each component in order, the "+" offspring, its own
+// family, then the "-" offspring and its family.  Offspring are new particles
+// of the system with their own lineage ids and exponential clocks (Alg. 1
+// rule 3).  The walk runs twice: once to count records, then (after an ordered
+// scan with look-back fixes the output offset) to write them.  Records hold
+// the end-of-step state, so no generation is revisited in a later launch.
+#pragma once
+#include "wbrw_dev.hpp"
+#include "wbrw_math.hpp"
+
+namespace wbrw {
+
+// ---------------------------------------------------------------------------
+// Kernel phase and kick sampling (Sec. 4.2, Remark 3 / Eq. majorant_approach)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double phase_offset(const Dev &d, int m, const double *xe, double c)
+{
+    const int a = d.axis[m];
+    if (a == 0) return xe[0] - c;
+    if (a == 1) return xe[1] - c;
+    return (xe[0] - xe[1]) - c;
+}
+
+// q from G_m / xi_m: Gaussian (Box-Muller, std 1/(2w)) or inverse CDF of the
+// piecewise-constant table with a uniform offset inside the chosen bin.
+__device__ __forceinline__ double kick_sample(const Dev &d, const InstParam &P, int m, double u1,
+                                              double u2)
+{
+    if (d.kind[m] == 0) {
+        const double R = sqrt(-2.0 * ln_series(1.0 - u1));
+        const double z = R * cos_det(kTwoPi * u2);
+        return z * P.sq[m];
+    }
+    const Table T = d.tab[m];
+    const double target = u1 * T.cum[T.n];
+    int lo = 0, hi = T.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T.cum[mid] <= target) lo = mid; else hi = mid - 1;
+    }
+    return T.q_lo + ((double)lo + u2) * T.dq;
+}
+
+template <int DIM>
+__device__ __forceinline__ bool in_kbox(const Dev &d, const double *k)
+{
+    if (!(k[0] >= d.k_lo && k[0] < d.k_hi)) return false;
+    if (DIM == 2 && !(k[1] >= d.k_lo && k[1] < d.k_hi)) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: streaming clock test + free flight + ordered event compaction
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_stream(Dev d, int ghost)
+{
+    __shared__ int64_t s_t;
+    __shared__ uint32_t s_wcnt[kPPT * 4];
+    __shared__ uint32_t s_woff[kPPT * 4];
+    __shared__ uint32_t s_excl;
+
+    Ctl *ctl = d.ctl;
+    const uint32_t step = ctl->step;
+    const uint32_t epoch = 2u * step + (uint32_t)ghost + 1u;
+    const int B = d.B;
+    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
+    const int64_t ntiles = plan[B];
+    const int64_t *Ncur = ghost ? d.NG : d.N;
+    const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
+    uint64_t *st = ghost ? d.stAg : d.stA;
+    uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
+    double *evx0 = ghost ? d.gev_x0 : d.ev_x0;
+    double *evx1 = ghost ? d.gev_x1 : d.ev_x1;
+    const int pass = ghost ? kPassStreamG : kPassStream;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[pass], 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= ntiles) break;
+        const int b = segment_of(plan, B, t);
+        const int64_t first = plan[b];
+        const int64_t tl = t - first;
+        const int64_t last = plan[b + 1] - 1;
+        const InstParam &P = d.ip[b];
+        const int64_t base = ghost ? P.gbase : P.base;
+        const int64_t n = Ncur[b];
+        const double thr_lo = P.thr_lo, thr_hi = P.thr_hi, g0 = P.gamma0;
+        const uint32_t key = P.key;
+
+        double xs0[kPPT], xs1[kPPT];
+        uint32_t rank[kPPT];
+        uint32_t evbits = 0;
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = tl * kTileA + (int64_t)j * kThreads + tid;
+            bool ev = false;
+            xs0[j] = 0.0;
+            xs1[j] = 0.0;
+            if (li < n) {
+                const int64_t i = base + li;
+                const double x = E.x0[i];
+                const double k = E.k0[i];
+                const uint64_t id = E.id[i];
+                double y = 0.0, ky = 0.0;
+                if (DIM == 2) { y = E.x1[i]; ky = E.k1[i]; }
+                const W4 r = draw(id, step, kTagStep, 0u, 0u, d.seed, key);
+                const double u = unit53(r.a, r.b);
+                if (u < thr_lo) {
+                    ev = true;
+                } else if (u <= thr_hi) {
+                    const double tau = -ln_series(1.0 - u) / g0;
+                    const double te = 0.0 + tau;
+                    ev = (te <= d.dt);
+                }
+                E.x0[i] = x + (d.vfac * k) * d.dt;
+                if (DIM == 2) E.x1[i] = y + (d.vfac * ky) * d.dt;
+                xs0[j] = x;
+                xs1[j] = y;
+            }
+            const uint64_t m = __ballot(ev);
+            rank[j] = lane_rank(m);
+            if (lane == 0) s_wcnt[j * 4 + wv] = (uint32_t)__popcll(m);
+            evbits |= (ev ? 1u : 0u) << j;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0;
+            for (int q = 0; q < kPPT * 4; ++q) { s_woff[q] = acc; acc += s_wcnt[q]; }
+            uint32_t excl = 0;
+            if (tl == 0) {
+                lb_publish(st + t, epoch, 2u, acc);
+            } else {
+                lb_publish(st + t, epoch, 1u, acc);
+                excl = lb_lookback(st, t, first, epoch);
+                lb_publish(st + t, epoch, 2u, excl + acc);
+            }
+            if (t == last) d.evc[(int64_t)ghost * B + b] = (int64_t)(excl + acc);
+            s_excl = excl;
+        }
+        __syncthreads();
+        const uint32_t ex = s_excl;
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {
+            if ((evbits >> j) & 1u) {
+                const int64_t pos = base + ex + s_woff[j * 4 + wv] + rank[j];
+                evi[pos] = (uint32_t)(tl * kTileA + (int64_t)j * kThreads + tid);
+                evx0[pos] = xs0[j];
+                if (DIM == 2) evx1[pos] = xs1[j];
+            }
+        }
+        __syncthreads();
+    }
+
+    if (last_block_done(&ctl->done[pass])) {
+        block_plan(d.tileB + (int64_t)ghost * (B + 1), d.evc + (int64_t)ghost * B, B, kTileB);
+        for (int b = tid; b < B; b += kThreads) {
+            d.chc[(int64_t)ghost * B + b] = 0;
+            if (!ghost) d.tally[(int64_t)b * kTalCount + kTalPSteps] += Ncur[b];
+        }
+        if (tid == 0) {
+            ctl->ticket[pass] = 0u;
+            ctl->done[pass] = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: family trees of event parents
+// ---------------------------------------------------------------------------
+struct Node {
+    double x[2], k[2];   // position at t0, wave vector
+    double t0;           // start of this particle's walk within the step
+    double w;            // sp2 weight
+    double D[3];         // tangent
+    uint64_t id;
+    int32_t sg;          // sp1 sign, 0 for a ghost
+    int32_t depth;
+    double t;            // time of its latest jump (t0 before the first)
+    double te;           // time of the jump being expanded
+    double xe[2];        // position at te
+    double ua0;          // acceptance uniform of component 0
+    uint32_t e;          // jump index
+    int32_t m, side, in_ev;
+};
+
+struct Tally {
+    int64_t events, pairs, killed, cap;
+    int32_t maxdepth;
+};
+
+template <int DIM, bool SP2, bool TAN, bool EMIT>
+__device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step, Node cur,
+                                const Ens &out, int64_t base, int64_t first_rec, int64_t cap,
+                                Tally &tl, uint32_t &err)
+{
+    Node stack[kMaxDepth];
+    int sp = 0;
+    uint32_t nrec = 0;
+    const uint32_t seed = d.seed, key = P.key;
+    const int M = d.M;
+    cur.t = cur.t0;
+    cur.e = 0;
+    cur.in_ev = 0;
+    cur.depth = 0;
+    for (;;) {
+        if (!cur.in_ev) {
+            bool done = false;
+            if (cur.e >= kEventCap) {
+                if (!EMIT) tl.cap++;
+                done = true;
+            } else {
+                const W4 r = draw(cur.id, step, kTagStep, cur.e, 0u, seed, key);
+                const double u = unit53(r.a, r.b);
+                const double tau = -ln_series(1.0 - u) / P.gamma0;
+                const double te = cur.t + tau;
+                if (!(te <= d.dt)) {
+                    done = true;
+                } else {
+                    if (!EMIT) tl.events++;
+                    cur.te = te;
+                    cur.ua0 = unit53(r.c, r.d);
+                    cur.xe[0] = cur.x[0] + (d.vfac * cur.k[0]) * (te - cur.t0);
+                    if (DIM == 2) cur.xe[1] = cur.x[1] + (d.vfac * cur.k[1]) * (te - cur.t0);
+                    else cur.xe[1] = 0.0;
+                    cur.in_ev = 1;
+                    cur.m = 0;
+                    cur.side = 0;
+                }
+            }
+            if (done) {
+                if (sp == 0) break;
+                cur = stack[--sp];
+                continue;
+            }
+        }
+        if (cur.m >= M) {
+            cur.t = cur.te;
+            cur.e += 1u;
+            cur.in_ev = 0;
+            continue;
+        }
+        const int m = cur.m;
+        const W4 rq = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(1 + m), seed, key);
+        const double q = kick_sample(d, P, m, unit53(rq.a, rq.b), unit53(rq.c, rq.d));
+        const double arg = (2.0 * q) * phase_offset(d, m, cur.xe, P.center[m]);
+        const double sn = sin_det(arg);
+        const double sigma = (sn > 0.0) ? P.sgnV[m] : -P.sgnV[m];
+        double amp = 0.0;
+        if (!SP2) {
+            double ua = cur.ua0;
+            if (m > 0) {
+                const W4 ra = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(8 + m), seed, key);
+                ua = unit53(ra.a, ra.b);
+            }
+            if (!(ua < P.c[m] * fabs(sn))) {   // no pair: only the survivor continues
+                cur.m += 1;
+                cur.side = 0;
+                continue;
+            }
+        } else {
+            amp = cur.w * (P.c[m] * fabs(sn));
+        }
+        const int side = cur.side;
+        if (!EMIT && side == 0) tl.pairs++;
+        if (side == 0) { cur.side = 1; } else { cur.side = 0; cur.m += 1; }
+
+        const W4 rc = draw(cur.id, step, kTagChild, cur.e, (uint32_t)m, seed, key);
+        const uint64_t cls = ((cur.id >> 62) & 1ull) ? 3ull : 2ull;
+        const uint64_t cid = side == 0
+            ? ((cls << 62) | ((uint64_t)(rc.b & 0x3FFFFFFFu) << 32) | (uint64_t)rc.a)
+            : ((cls << 62) | ((uint64_t)(rc.d & 0x3FFFFFFFu) << 32) | (uint64_t)rc.c);
+        const double kick = sigma * q;
+        Node ch;
+        ch.k[0] = cur.k[0];
+        ch.k[1] = cur.k[1];
+        const int ax = d.axis[m];
+        if (ax == 0) {
+            ch.k[0] = side == 0 ? cur.k[0] + kick : cur.k[0] - kick;
+        } else if (ax == 1) {
+            ch.k[1] = side == 0 ? cur.k[1] + kick : cur.k[1] - kick;
+        } else {
+            ch.k[0] = side == 0 ? cur.k[0] + kick : cur.k[0] - kick;
+            ch.k[1] = side == 0 ? cur.k[1] - kick : cur.k[1] + kick;
+        }
+        ch.sg = side == 0 ? cur.sg : -cur.sg;
+        ch.w = side == 0 ? amp : -amp;
+        ch.id = cid;
+        if (TAN) {
+            const double wd = P.width[m];
+            const double s0 = 1.0 / P.H[m];
+            const double s1 = 1.0 / wd - ((4.0 * wd) * q) * q;
+            const double s2 = -(2.0 * q) * (cos_det(arg) / sn);
+            const double sdir = side == 0 ? 1.0 : -1.0;
+            const double sgd = (double)ch.sg;
+            ch.D[0] = sdir * cur.D[0] + sgd * s0;
+            ch.D[1] = sdir * cur.D[1] + sgd * s1;
+            ch.D[2] = sdir * cur.D[2] + sgd * s2;
+        } else {
+            ch.D[0] = ch.D[1] = ch.D[2] = 0.0;
+        }
+        if (!in_kbox<DIM>(d, ch.k)) {          // k-truncation (Sec. 2)
+            if (!EMIT) {
+                if (SP2) {
+                    const int64_t q32 = (int64_t)floor(fabs(ch.w) * 4294967296.0);
+                    tl.killed += ch.w < 0.0 ? -q32 : q32;
+                } else {
+                    tl.killed += ch.sg;
+                }
+            }
+            continue;
+        }
+        if (EMIT) {
+            const int64_t li = first_rec + nrec;
+            if (li < cap) {
+                const int64_t o = base + li;
+                out.x0[o] = cur.xe[0] + (d.vfac * ch.k[0]) * (d.dt - cur.te);
+                out.k0[o] = ch.k[0];
+                if (DIM == 2) {
+                    out.x1[o] = cur.xe[1] + (d.vfac * ch.k[1]) * (d.dt - cur.te);
+                    out.k1[o] = ch.k[1];
+                }
+                if (SP2) out.w[o] = ch.w; else out.sg[o] = (int8_t)ch.sg;
+                out.id[o] = ch.id;
+                if (TAN) {
+                    out.D[o] = ch.D[0];
+                    out.D[d.cap_total + o] = ch.D[1];
+                    out.D[2 * d.cap_total + o] = ch.D[2];
+                }
+            } else {
+                err |= kErrCapacity;
+            }
+        }
+        nrec++;
+        if (sp >= kMaxDepth) {
+            err |= kErrDepth;
+            continue;
+        }
+        ch.x[0] = cur.xe[0];
+        ch.x[1] = cur.xe[1];
+        ch.t0 = cur.te;
+        ch.t = ch.t0;
+        ch.e = 0;
+        ch.in_ev = 0;
+        ch.m = 0;
+        ch.side = 0;
+        ch.depth = cur.depth + 1;
+        if (!EMIT && ch.depth > tl.maxdepth) tl.maxdepth = ch.depth;
+        stack[sp++] = cur;
+        cur = ch;
+    }
+    return nrec;
+}
+
+template <int DIM, bool SP2, bool TAN>
+__global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advance)
+{
+    __shared__ int64_t s_t;
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_excl;
+    __shared__ int64_t s_tal[5];
+
+    Ctl *ctl = d.ctl;
+    const uint32_t step = ctl->step;
+    const uint32_t epoch = 2u * step + (uint32_t)ghost + 1u;
+    const int B = d.B;
+    const int64_t *plan = d.tileB + (int64_t)ghost * (B + 1);
+    const int64_t ntiles = plan[B];
+    int64_t *Ncur = ghost ? d.NG : d.N;
+    const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
+    uint64_t *st = ghost ? d.stBg : d.stB;
+    const uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
+    const double *evx0 = ghost ? d.gev_x0 : d.ev_x0;
+    const double *evx1 = ghost ? d.gev_x1 : d.ev_x1;
+    const int pass = ghost ? kPassFamilyG : kPassFamily;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint32_t err = 0;
+
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[pass], 1u);
+        if (tid < 5) s_tal[tid] = 0;
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= ntiles) break;
+        const int b = segment_of(plan, B, t);
+        const int64_t first = plan[b];
+        const int64_t tl_i = t - first;
+        const int64_t last = plan[b + 1] - 1;
+        const InstParam &P = d.ip[b];
+        const int64_t base = ghost ? P.gbase : P.base;
+        const int64_t cap = ghost ? P.gcap : P.cap;
+        const int64_t nev = d.evc[(int64_t)ghost * B + b];
+        const int64_t n_before = Ncur[b];
+        const int64_t j = tl_i * kTileB + tid;
+        const bool ok = j < nev;
+
+        Node root;
+        root.x[0] = root.x[1] = root.k[0] = root.k[1] = 0.0;
+        root.t0 = 0.0;
+        root.w = 0.0;
+        root.D[0] = root.D[1] = root.D[2] = 0.0;
+        root.id = 0;
+        root.sg = 0;
+        if (ok) {
+            const int64_t pos = base + j;
+            const int64_t i = base + (int64_t)evi[pos];
+            root.x[0] = evx0[pos];
+            root.k[0] = E.k0[i];
+            if (DIM == 2) { root.x[1] = evx1[pos]; root.k[1] = E.k1[i]; }
+            root.id = E.id[i];
+            if (SP2) root.w = E.w[i]; else root.sg = (int32_t)E.sg[i];
+            if (TAN) {
+                root.D[0] = E.D[i];
+                root.D[1] = E.D[d.cap_total + i];
+                root.D[2] = E.D[2 * d.cap_total + i];
+            }
+        }
+        Tally tal{0, 0, 0, 0, 0};
+        uint32_t cnt = 0;
+        if (ok) cnt = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, tal, err);
+
+        // ordered exclusive scan of the record counts over the tile
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) s_wsum[wv] = incl;
+        __syncthreads();
+        uint32_t woff = 0, agg = 0;
+        for (int q = 0; q < 4; ++q) {
+            if (q < wv) woff += s_wsum[q];
+            agg += s_wsum[q];
+        }
+        if (tid == 0) {
+            uint32_t excl = 0;
+            if (tl_i == 0) {
+                lb_publish(st + t, epoch, 2u, agg);
+            } else {
+                lb_publish(st + t, epoch, 1u, agg);
+                excl = lb_lookback(st, t, first, epoch);
+                lb_publish(st + t, epoch, 2u, excl + agg);
+            }
+            if (t == last) d.chc[(int64_t)ghost * B + b] = (int64_t)(excl + agg);
+            s_excl = excl;
+        }
+        __syncthreads();
+        const int64_t my_first = n_before + (int64_t)s_excl + (int64_t)(woff + incl - cnt);
+        if (ok && cnt > 0)
+            walk_family<DIM, SP2, TAN, true>(d, P, step, root, E, base, my_first, cap, tal, err);
+
+        // per-instance tallies
+        if (tal.events) atomicAdd((unsigned long long *)&s_tal[0], (unsigned long long)tal.events);
+        if (tal.pairs) atomicAdd((unsigned long long *)&s_tal[1], (unsigned long long)tal.pairs);
+        if (tal.killed) atomicAdd((unsigned long long *)&s_tal[2], (unsigned long long)tal.killed);
+        if (tal.cap) atomicAdd((unsigned long long *)&s_tal[3], (unsigned long long)tal.cap);
+        if (tal.maxdepth) atomicMax((unsigned long long *)&s_tal[4], (unsigned long long)tal.maxdepth);
+        __syncthreads();
+        if (tid == 0) {
+            int64_t *T = d.tally + (int64_t)b * kTalCount;
+            if (s_tal[0]) atomicAdd((unsigned long long *)&T[kTalEvents], (unsigned long long)s_tal[0]);
+            if (s_tal[1]) atomicAdd((unsigned long long *)&T[kTalPairs], (unsigned long long)s_tal[1]);
+            if (s_tal[2]) atomicAdd((unsigned long long *)&T[kTalKilled], (unsigned long long)s_tal[2]);
+            if (s_tal[3]) atomicAdd((unsigned long long *)&T[kTalEventCap], (unsigned long long)s_tal[3]);
+            if (s_tal[4]) atomicMax((unsigned long long *)&T[kTalMaxDepth], (unsigned long long)s_tal[4]);
+        }
+        __syncthreads();
+    }
+    if (err) atomicOr(&ctl->err, err);
+
+    if (last_block_done(&ctl->done[pass])) {
+        int64_t *chc = d.chc + (int64_t)ghost * B;
+        int64_t *evc = d.evc + (int64_t)ghost * B;
+        for (int b = tid; b < B; b += kThreads) {
+            const InstParam &P = d.ip[b];
+            const int64_t cap = ghost ? P.gcap : P.cap;
+            int64_t n = Ncur[b] + chc[b];
+            if (n > cap) {
+                atomicOr(&ctl->err, kErrCapacity);
+                n = cap;
+            }
+            Ncur[b] = n;
+            chc[b] = 0;
+            evc[b] = 0;
+        }
+        __syncthreads();
+        block_plan(d.tileA + (int64_t)ghost * (B + 1), Ncur, B, kTileA);
+        if (tid == 0) {
+            ctl->ticket[pass] = 0u;
+            ctl->done[pass] = 0u;
+            if (advance) ctl->step = step + 1u;
+        }
+    }
+}
+
+}  // namespace wbrw

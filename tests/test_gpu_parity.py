@@ -1,0 +1,168 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle
+on the same seeded inputs.  Counts, signs, ids, per-cell sums, tallies and
+densities must be bit-exact; positions and wave vectors too (both sides run the
+same IEEE operation sequences; the stated bound of 1e-12 relative is checked
+as a fallback message only)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1709_02121_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as O
+    O.build()
+    return O
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def assert_same_ensemble(a, b, fields=("x", "k", "sign", "id"), what=""):
+    for f in fields:
+        if f not in a or f not in b:
+            continue
+        x, y = np.asarray(a[f]), np.asarray(b[f])
+        assert x.shape == y.shape, (what, f, x.shape, y.shape)
+        if np.array_equal(x, y):
+            continue
+        if x.dtype.kind == "f":
+            rel = np.max(np.abs(x - y) / np.maximum(np.abs(y), 1e-300))
+            bad = np.flatnonzero(x != y)
+            raise AssertionError(f"{what}: {f} differs at {bad[:5]} (max rel {rel:.3e})")
+        bad = np.flatnonzero(x != y)
+        raise AssertionError(f"{what}: {f} differs at {bad[:5]}: {x[bad[:5]]} vs {y[bad[:5]]}")
+
+
+def compare(gpu, ref, what, B=1):
+    for b in range(B):
+        st_g, st_o = gpu.stats(b), ref.stats(b)
+        assert st_g["n"] == st_o["n"], (what, b, st_g["n"], st_o["n"])
+        for key in ("events", "pairs", "killed", "escaped", "max_depth", "event_cap_hits"):
+            assert st_g[key] == st_o[key], (what, b, key, st_g[key], st_o[key])
+        assert_same_ensemble(gpu.particles(b), ref.particles(b), what=f"{what} b={b}")
+
+
+def test_init_parity(P, O):
+    cfg = W.gaussian_barrier_small(N0=np.array([20000]))
+    say("init parity: 1D, N0=20000")
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    compare(g, r, "init")
+    cfg4 = W.helium_soft_coulomb(N0=np.array([5003]))
+    say("init parity: 2D (4D phase space), N0=5003")
+    compare(P.Simulation(cfg4), O.OracleSim(cfg4), "init4d")
+
+
+@pytest.mark.parametrize("n0", [1, 2047, 2048, 2049, 20000])
+def test_one_step_parity(P, O, n0):
+    cfg = W.gaussian_barrier_small(N0=np.array([n0]))
+    say(f"one step parity: N0={n0}")
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.step(1)
+    r.step(1)
+    compare(g, r, f"step1 n0={n0}")
+
+
+def test_gaussian_barrier_full_workload(P, O):
+    """1e4 particles, 100 steps, annihilation every 10 (240 x 128 grid)."""
+    cfg = W.gaussian_barrier_small()
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    for ep in range(10):
+        g.step(10)
+        r.step(10)
+        if ep in (0, 9):
+            compare(g, r, f"before annihilation {ep}")
+        g.annihilate()
+        r.annihilate()
+        say(f"barrier 1e4: epoch {ep} n={r.count()}")
+        if ep in (0, 4, 9):
+            compare(g, r, f"after annihilation {ep}")
+    dg = g.density().cpu().numpy()
+    dr = r.density()
+    assert np.array_equal(dg, dr)
+    st = g.stats()
+    assert st["step"] == 100
+
+
+def test_wider_grid_and_many_tiles(P, O):
+    """2000 x 512 grid, 2e5 particles (100 streaming tiles), 30 steps."""
+    cfg = W.scaled(W.gaussian_barrier_large("sp1"), N0=200_000, capacity=2_000_000)
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.run(30, 10)
+    r.run(30, 10)
+    say(f"wide grid: n={r.count()}")
+    compare(g, r, "wide")
+    assert np.array_equal(g.density().cpu().numpy(), r.density())
+
+
+def test_batched_equals_oracle(P, O):
+    cfg = W.batched_barriers(B=6, N0=np.array([0, 1, 3000, 2049, 700, 9000], dtype=np.int64))
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.run(25, 10)
+    r.run(25, 10)
+    say("batched B=6 done")
+    compare(g, r, "batched", B=6)
+    # instance 0 has N0 = 0: its density (sum / N0) is undefined (NaN) on both sides
+    dg, dr = g.density().cpu().numpy(), r.density()
+    assert np.all(np.isnan(dg[0])) and np.all(np.isnan(dr[0]))
+    assert np.array_equal(dg[1:], dr[1:])
+
+
+def test_helium_4d_parity(P, O):
+    cfg = W.helium_soft_coulomb(N0=np.array([6000]))
+    cfg["grid"] = {"x_lo": -10.0, "x_hi": 10.0, "nx": 24, "k_lo": -4.0, "k_hi": 4.0, "nk": 24}
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    for ep in range(2):
+        g.step(10)
+        r.step(10)
+        compare(g, r, f"4d before annihilation {ep}")
+        g.annihilate()
+        r.annihilate()
+        say(f"4d: epoch {ep} n={r.count()}")
+        compare(g, r, f"4d after annihilation {ep}")
+    for axis in (0, 1):
+        assert np.array_equal(g.density(axis=axis).cpu().numpy(), r.density(axis=axis))
+
+
+def test_graph_replay_matches_plain(P, O):
+    """The step + annihilation epoch captured once and replayed: every replay,
+    separated by host synchronisation and eager work, matches eager launches."""
+    import torch
+    cfg = W.batched_barriers(B=3, N0=np.array([500, 4000, 1200], dtype=np.int64))
+    s = torch.cuda.Stream()
+    a, b = P.Simulation(cfg), P.Simulation(cfg, stream=s)
+    for ep in range(4):
+        a.run(10, 10, use_graph=False)
+        b.run(10, 10, use_graph=True)
+        b.synchronize()
+        for i in range(3):
+            assert_same_ensemble(a.particles(i), b.particles(i), what=f"graph replay {ep}")
+        assert np.array_equal(a.density().cpu().numpy(), b.density().cpu().numpy())
+    say("graph replay done")
+    r = O.OracleSim(cfg)
+    r.run(40, 10)
+    compare(b, r, "graph vs oracle", B=3)
+
+
+def test_capacity_overflow_is_reported(P):
+    cfg = W.gaussian_barrier_small(N0=np.array([5000]), capacity=5200)
+    g = P.Simulation(cfg)
+    g.step(10)
+    code, _ = g.stats_code()
+    assert code == P.ECAPACITY
