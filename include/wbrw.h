@@ -185,6 +185,23 @@ int wbrw_density(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, do
 int wbrw_density_tangent(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi,
                          double *d_out);
 
+/* Backward pass of the density (track_tangent only): grad_out[b*3 + c] =
+ * sum_j g[b*nbins + j] d rho_bj / d theta_c, accumulated directly from the
+ * per-particle likelihood-ratio tangents of real particles and ghosts in bin
+ * j, theta = (H, w, x0).  g, grad_out: device, caller-owned.  Same binning as
+ * wbrw_density.  No synchronisation. */
+int wbrw_density_vjp(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi,
+                     const double *g, double *grad_out);
+
+/* Checkpoint / resume.  wbrw_snapshot_size synchronises and gives the bytes a
+ * snapshot of the current state needs (every instance's particles and ghosts,
+ * counts, tallies, the step counter).  wbrw_snapshot copies that state into a
+ * caller-owned device buffer (synchronises).  wbrw_restore makes a handle with
+ * the same configuration continue exactly from a snapshot. */
+int wbrw_snapshot_size(wbrw_t h, size_t *bytes);
+int wbrw_snapshot(wbrw_t h, void *dst, size_t bytes);
+int wbrw_restore(wbrw_t h, const void *src, size_t bytes);
+
 /* Synchronises the stream, then writes instance b's statistics.  Returns a
  * sticky device error (WBRW_ECAPACITY, WBRW_EDEPTH) if one was raised. */
 int wbrw_stats(wbrw_t h, int32_t b, wbrw_stats_t *out);

@@ -103,12 +103,17 @@ def lib():
         L.wbrw_export.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp]
         L.wbrw_destroy.argtypes = [vp]
         L.wbrw_profile.argtypes = [vp, i32]
+        L.wbrw_density_vjp.argtypes = [vp, i32, i32, C.c_double, C.c_double, vp, vp]
+        L.wbrw_snapshot_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.wbrw_snapshot.argtypes = [vp, vp, C.c_size_t]
+        L.wbrw_restore.argtypes = [vp, vp, C.c_size_t]
         L.wbrw_profile_read.argtypes = [vp, vp, vp]
         L.wbrw_strerror.restype = C.c_char_p
         L.wbrw_strerror.argtypes = [C.c_int]
         for f in ("wbrw_workspace_size", "wbrw_init", "wbrw_step", "wbrw_annihilate", "wbrw_run",
                   "wbrw_density", "wbrw_density_tangent", "wbrw_stats", "wbrw_count",
-                  "wbrw_export", "wbrw_destroy", "wbrw_profile", "wbrw_profile_read"):
+                  "wbrw_export", "wbrw_destroy", "wbrw_profile", "wbrw_profile_read",
+                  "wbrw_density_vjp", "wbrw_snapshot_size", "wbrw_snapshot", "wbrw_restore"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -266,6 +271,32 @@ class Simulation:
         cur = self.torch.cuda.current_stream(self.device)
         if cur.cuda_stream != self.stream.cuda_stream:
             cur.wait_stream(self.stream)
+
+    def density_vjp(self, g, axis=0, nbins=None, lo=None, hi=None):
+        """sum_j g[b, j] d rho[b, j] / d theta for every instance, shape (B, 3)."""
+        t = self.torch
+        d = self.cfg["density"]
+        nbins = d["nbins"] if nbins is None else nbins
+        lo = d["lo"] if lo is None else lo
+        hi = d["hi"] if hi is None else hi
+        with t.cuda.stream(self.stream):
+            g = g.to(device=self.device, dtype=t.float64).reshape(self.B, nbins).contiguous()
+            out = t.empty((self.B, 3), dtype=t.float64, device=self.device)
+        _check(lib().wbrw_density_vjp(self.h, axis, nbins, lo, hi, C.c_void_p(g.data_ptr()),
+                                      C.c_void_p(out.data_ptr())), "wbrw_density_vjp")
+        self._order_for_caller()
+        return out
+
+    def snapshot(self):
+        """Device copy of the current state (a torch uint8 tensor)."""
+        n = C.c_size_t()
+        _check(lib().wbrw_snapshot_size(self.h, C.byref(n)), "wbrw_snapshot_size")
+        buf = self.torch.empty(int(n.value), dtype=self.torch.uint8, device=self.device)
+        _check(lib().wbrw_snapshot(self.h, C.c_void_p(buf.data_ptr()), int(n.value)), "wbrw_snapshot")
+        return buf
+
+    def restore(self, buf):
+        _check(lib().wbrw_restore(self.h, C.c_void_p(buf.data_ptr()), buf.numel()), "wbrw_restore")
 
     def stats(self, b=0):
         st = Stats()

@@ -35,7 +35,7 @@ struct Layout {
            tileG = 0, tally = 0, ev_idx = 0, ev_x0 = 0, ev_x1 = 0, gev_idx = 0, gev_x0 = 0,
            gev_x1 = 0, stA = 0, stAg = 0, stB = 0, stBg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
-           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0;
+           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
     int64_t tilesA = 0, tilesAg = 0, tilesB = 0, tilesBg = 0, tilesS = 0, tilesP = 0;
 };
@@ -188,6 +188,7 @@ Layout make_layout(const wbrw_config *c)
         L.bscan_tiles = take(cur, (BB + 1) * 8);
     }
     L.dacc = take(cur, BB * MB * 8);
+    L.vjp = take(cur, BB * 3 * 8);
     L.zero_end = (cur + kAlign - 1) / kAlign * kAlign;
     L.total = L.zero_end;
     return L;
@@ -716,6 +717,180 @@ int wbrw_density_tangent(wbrw_t h, int32_t axis, int32_t nbins, double lo, doubl
     const int outb = std::max(1, std::min(h->cus * 4, (int)ceil_div((int64_t)h->B * 3 * nbins, kThreads)));
     hipLaunchKernelGGL((k_density_out<false, true>), dim3(outb), dim3(kThreads), 0, s, d, nbins, dxb, d_out);
     return launch_check();
+}
+
+int wbrw_density_vjp(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, const double *g,
+                     double *grad_out)
+{
+    if (!h || !g || !grad_out || !h->tangent || nbins < 1 || !(hi > lo) || axis != 0) return WBRW_EINVAL;
+    const double dxb = (hi - lo) / (double)nbins;
+    const Dev &d = h->d;
+    hipStream_t s = h->stream;
+    double *acc = at<double>(h->ws, h->L.vjp);
+    stage_begin(h, WBRW_STAGE_DENSITY);
+    hipLaunchKernelGGL(k_vjp, dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, nbins, lo, dxb, g, acc);
+    hipLaunchKernelGGL(k_vjp, dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 1, nbins, lo, dxb, g, acc);
+    hipLaunchKernelGGL(k_vjp_out, dim3(1), dim3(kThreads), 0, s, d, dxb, acc, grad_out);
+    stage_end(h);
+    return launch_check();
+}
+
+// ---- snapshots ------------------------------------------------------------
+namespace {
+
+struct SnapHeader {
+    uint64_t magic, total;
+    int32_t B, dim, strategy, tangent;
+    Ctl ctl;
+};
+
+// bytes per particle of the real / ghost ensembles in a snapshot
+size_t real_bytes(const wbrw_handle *h)
+{
+    return 8 * 2 * h->dim + (h->strategy == WBRW_SP2 ? 8 : 1) + 8 + (h->tangent ? 24 : 0);
+}
+size_t ghost_bytes(const wbrw_handle *h) { return h->tangent ? 8 * 2 + 1 + 8 + 24 : 0; }
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int snap_counts(wbrw_t h, std::vector<int64_t> &N, std::vector<int64_t> &NG, Ctl &c, size_t &total)
+{
+    HIPCHK(hipStreamSynchronize(h->stream));
+    N.resize(h->B);
+    NG.assign(h->B, 0);
+    HIPCHK(hipMemcpy(N.data(), h->d.N, 8 * h->B, hipMemcpyDeviceToHost));
+    if (h->tangent) HIPCHK(hipMemcpy(NG.data(), h->d.NG, 8 * h->B, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    int64_t nr = 0, ng = 0;
+    for (int b = 0; b < h->B; ++b) { nr += N[b]; ng += NG[b]; }
+    total = align_up(sizeof(SnapHeader)) + align_up(16 * (size_t)h->B) +
+            align_up(8 * (size_t)h->B * kTalCount) + 16 * kAlign +
+            (size_t)nr * real_bytes(h) + (size_t)ng * ghost_bytes(h);
+    return WBRW_OK;
+}
+
+// Copies the fields of one ensemble between the workspace and a packed
+// snapshot region: field-major, instances in order.
+int copy_fields(wbrw_t h, int ghost, char *packed, const std::vector<int64_t> &N, bool to_snap,
+                uint32_t set, size_t &cursor)
+{
+    const Ens E = ghost ? h->d.gens[set] : h->d.ens[set];
+    const int64_t tot = ghost ? h->d.gcap_total : h->d.cap_total;
+    struct F { char *base; size_t esz; int64_t stride; };
+    std::vector<F> f;
+    f.push_back({(char *)E.x0, 8, 0});
+    if (!ghost && h->dim == 2) f.push_back({(char *)E.x1, 8, 0});
+    f.push_back({(char *)E.k0, 8, 0});
+    if (!ghost && h->dim == 2) f.push_back({(char *)E.k1, 8, 0});
+    if (E.sg) f.push_back({(char *)E.sg, 1, 0});
+    if (E.w) f.push_back({(char *)E.w, 8, 0});
+    f.push_back({(char *)E.id, 8, 0});
+    if (E.D) for (int c = 0; c < 3; ++c) f.push_back({(char *)(E.D + c * tot), 8, 0});
+    for (const F &fld : f) {
+        cursor = align_up(cursor);
+        for (int b = 0; b < h->B; ++b) {
+            const int64_t base = ghost ? h->ip[b].gbase : h->ip[b].base;
+            const size_t n = (size_t)N[b] * fld.esz;
+            if (n) {
+                char *ws = fld.base + (size_t)base * fld.esz;
+                if (to_snap) HIPCHK(hipMemcpyAsync(packed + cursor, ws, n, hipMemcpyDeviceToDevice, h->stream));
+                else HIPCHK(hipMemcpyAsync(ws, packed + cursor, n, hipMemcpyDeviceToDevice, h->stream));
+            }
+            cursor += n;
+        }
+    }
+    return WBRW_OK;
+}
+
+}  // namespace
+
+int wbrw_snapshot_size(wbrw_t h, size_t *bytes)
+{
+    if (!h || !bytes) return WBRW_EINVAL;
+    std::vector<int64_t> N, NG;
+    Ctl c;
+    const int rc = snap_counts(h, N, NG, c, *bytes);
+    return rc;
+}
+
+int wbrw_snapshot(wbrw_t h, void *dst, size_t bytes)
+{
+    if (!h || !dst) return WBRW_EINVAL;
+    std::vector<int64_t> N, NG;
+    Ctl c;
+    size_t total = 0;
+    int rc = snap_counts(h, N, NG, c, total);
+    if (rc) return rc;
+    if (bytes < total) return WBRW_EINVAL;
+    if (c.err) return (c.err & kErrCapacity) ? WBRW_ECAPACITY : WBRW_EDEPTH;
+    SnapHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    hd.magic = 0x5742525753534e50ull;
+    hd.total = total;
+    hd.B = h->B;
+    hd.dim = h->dim;
+    hd.strategy = h->strategy;
+    hd.tangent = h->tangent;
+    hd.ctl = c;
+    char *p = (char *)dst;
+    size_t cur = 0;
+    std::vector<int64_t> counts(2 * h->B);
+    for (int b = 0; b < h->B; ++b) { counts[b] = N[b]; counts[h->B + b] = NG[b]; }
+    HIPCHK(hipMemcpy(p, &hd, sizeof(hd), hipMemcpyHostToDevice));
+    cur = align_up(sizeof(SnapHeader));
+    HIPCHK(hipMemcpy(p + cur, counts.data(), 16 * h->B, hipMemcpyHostToDevice));
+    cur = align_up(cur + 16 * h->B);
+    HIPCHK(hipMemcpyAsync(p + cur, h->d.tally, 8 * (size_t)h->B * kTalCount, hipMemcpyDeviceToDevice, h->stream));
+    cur = align_up(cur + 8 * (size_t)h->B * kTalCount);
+    rc = copy_fields(h, 0, p, N, true, c.cur, cur);
+    if (!rc && h->tangent) rc = copy_fields(h, 1, p, NG, true, c.gcur, cur);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return WBRW_OK;
+}
+
+int wbrw_restore(wbrw_t h, const void *src, size_t bytes)
+{
+    if (!h || !src) return WBRW_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    SnapHeader hd;
+    if (bytes < sizeof(hd)) return WBRW_EINVAL;
+    HIPCHK(hipMemcpy(&hd, src, sizeof(hd), hipMemcpyDeviceToHost));
+    if (hd.magic != 0x5742525753534e50ull || hd.B != h->B || hd.dim != h->dim ||
+        hd.strategy != h->strategy || hd.tangent != h->tangent || hd.total > bytes)
+        return WBRW_EINVAL;
+    const char *p = (const char *)src;
+    size_t cur = align_up(sizeof(SnapHeader));
+    std::vector<int64_t> counts(2 * h->B), N(h->B), NG(h->B);
+    HIPCHK(hipMemcpy(counts.data(), p + cur, 16 * h->B, hipMemcpyDeviceToHost));
+    cur = align_up(cur + 16 * h->B);
+    for (int b = 0; b < h->B; ++b) {
+        N[b] = counts[b];
+        NG[b] = counts[h->B + b];
+        if (N[b] > h->ip[b].cap || (h->tangent && NG[b] > h->ip[b].gcap)) return WBRW_EINVAL;
+    }
+    HIPCHK(hipMemcpyAsync(h->d.tally, p + cur, 8 * (size_t)h->B * kTalCount, hipMemcpyDeviceToDevice, h->stream));
+    cur = align_up(cur + 8 * (size_t)h->B * kTalCount);
+    // restore into set 0 / ghost set 0 and reset the control block
+    int rc = copy_fields(h, 0, (char *)p, N, false, 0u, cur);
+    if (!rc && h->tangent) rc = copy_fields(h, 1, (char *)p, NG, false, 0u, cur);
+    if (rc) return rc;
+    Ctl c;
+    std::memset(&c, 0, sizeof(c));
+    c.step = hd.ctl.step;
+    c.ann_seq = hd.ctl.ann_seq;
+    std::vector<int64_t> plan, gplan;
+    plan_host(plan, N.data(), h->B, kTileA);
+    plan_host(gplan, NG.data(), h->B, kTileA);
+    HIPCHK(hipMemcpyAsync(h->d.N, N.data(), 8 * h->B, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d.tileA, plan.data(), 8 * (h->B + 1), hipMemcpyHostToDevice, h->stream));
+    if (h->tangent) {
+        HIPCHK(hipMemcpyAsync(h->d.NG, NG.data(), 8 * h->B, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d.tileA + h->B + 1, gplan.data(), 8 * (h->B + 1), hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHK(hipMemcpyAsync(h->d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return WBRW_OK;
 }
 
 int wbrw_stats(wbrw_t h, int32_t b, wbrw_stats_t *out)

@@ -152,9 +152,10 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
             if (TAN) {
                 atomicAdd(&d.occ[cbase + nu], 1);
                 const int64_t nc = d.Nh * (int64_t)B;
+                const int64_t ds = ghost ? d.gcap_total : d.cap_total;
                 atomicAdd(&d.Tcell[cbase + nu], E.D[i]);
-                atomicAdd(&d.Tcell[nc + cbase + nu], E.D[d.cap_total + i]);
-                atomicAdd(&d.Tcell[2 * nc + cbase + nu], E.D[2 * d.cap_total + i]);
+                atomicAdd(&d.Tcell[nc + cbase + nu], E.D[ds + i]);
+                atomicAdd(&d.Tcell[2 * nc + cbase + nu], E.D[2 * ds + i]);
             }
         }
         if (esc) atomicAdd((unsigned long long *)&s_esc, (unsigned long long)esc);
@@ -361,9 +362,10 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
             const int64_t bin = (int64_t)q;
             if (TAN) {
                 double *acc = d.dTacc + (int64_t)b * 3 * d.max_bins;
+                const int64_t ds = ghost ? d.gcap_total : d.cap_total;
                 atomicAdd(&acc[bin], E.D[i]);
-                atomicAdd(&acc[d.max_bins + bin], E.D[d.cap_total + i]);
-                atomicAdd(&acc[2 * d.max_bins + bin], E.D[2 * d.cap_total + i]);
+                atomicAdd(&acc[d.max_bins + bin], E.D[ds + i]);
+                atomicAdd(&acc[2 * d.max_bins + bin], E.D[2 * ds + i]);
             } else {
                 int64_t v;
                 if (SP2) v = (int64_t)(E.w[i] * 4294967296.0); else v = (int64_t)E.sg[i];
@@ -401,6 +403,73 @@ __global__ __launch_bounds__(kThreads) void k_density_out(Dev d, int nbins, doub
             out[g] = v / denom;
             *acc = 0;
         }
+    }
+}
+
+// Vector-Jacobian product of the density: grad[b][c] += sum over particles
+// (real, then ghosts in a second launch) of D_c g[b][bin(x)], divided by
+// N0_b dxb in k_vjp_out.  This is the backward pass of the differentiation
+// form: the likelihood-ratio scores are already accumulated per particle.
+__global__ __launch_bounds__(kThreads) void k_vjp(Dev d, int ghost, int nbins, double lo, double dxb,
+                                                  const double *g, double *acc)
+{
+    __shared__ int64_t s_t;
+    __shared__ double s_sum[3][kThreads / 64];
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
+    const int64_t ntiles = plan[B];
+    const int64_t *Ncur = ghost ? d.NG : d.N;
+    const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
+    const int64_t ds = ghost ? d.gcap_total : d.cap_total;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (;;) {
+        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        if (t >= ntiles) break;
+        const int b = segment_of(plan, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t base = ghost ? P.gbase : P.base;
+        const int64_t n = Ncur[b];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            if (li >= n) continue;
+            const int64_t i = base + li;
+            const double q = (E.x0[i] - lo) / dxb;
+            if (!(q >= 0.0 && q < (double)nbins)) continue;
+            const double gv = g[(int64_t)b * nbins + (int64_t)q];
+            a0 += E.D[i] * gv;
+            a1 += E.D[ds + i] * gv;
+            a2 += E.D[2 * ds + i] * gv;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            a0 += __shfl_down(a0, o, 64);
+            a1 += __shfl_down(a1, o, 64);
+            a2 += __shfl_down(a2, o, 64);
+        }
+        if (lane == 0) { s_sum[0][wv] = a0; s_sum[1][wv] = a1; s_sum[2][wv] = a2; }
+        __syncthreads();
+        if (tid < 3) {
+            double v = 0.0;
+            for (int q = 0; q < kThreads / 64; ++q) v += s_sum[tid][q];
+            atomicAdd(&acc[(int64_t)b * 3 + tid], v);
+        }
+        __syncthreads();
+    }
+    if (last_block_done(&ctl->done[kPassTiles])) {
+        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_vjp_out(Dev d, double dxb, double *acc, double *out)
+{
+    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < (int64_t)d.B * 3;
+         g += (int64_t)gridDim.x * kThreads) {
+        const double denom = (double)d.ip[g / 3].N0 * dxb;
+        out[g] = acc[g] / denom;
+        acc[g] = 0.0;
     }
 }
 

@@ -105,40 +105,63 @@ __global__ __launch_bounds__(kThreads) void k_stream(Dev d, int ghost)
         const double thr_lo = P.thr_lo, thr_hi = P.thr_hi, g0 = P.gamma0;
         const uint32_t key = P.key;
 
-        double xs0[kPPT], xs1[kPPT];
+        // All loads of the thread's kPPT particles are issued before any
+        // compute or store, so every wave keeps 3*kPPT (4D: 5*kPPT) loads in
+        // flight; full tiles need no bounds checks.
+        const int64_t li0 = tl * kTileA + tid;
+        const bool full = (tl + 1) * kTileA <= n;
+        double xs0[kPPT], xs1[kPPT], kv0[kPPT], kv1[kPPT];
+        uint64_t idv[kPPT];
+        if (full) {
+#pragma unroll
+            for (int j = 0; j < kPPT; ++j) {
+                const int64_t i = base + li0 + (int64_t)j * kThreads;
+                xs0[j] = E.x0[i];
+                kv0[j] = E.k0[i];
+                idv[j] = E.id[i];
+                if (DIM == 2) { xs1[j] = E.x1[i]; kv1[j] = E.k1[i]; }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPPT; ++j) {
+                const int64_t li = li0 + (int64_t)j * kThreads;
+                const int64_t i = base + (li < n ? li : 0);
+                xs0[j] = E.x0[i];
+                kv0[j] = E.k0[i];
+                idv[j] = E.id[i];
+                if (DIM == 2) { xs1[j] = E.x1[i]; kv1[j] = E.k1[i]; }
+            }
+        }
         uint32_t rank[kPPT];
         uint32_t evbits = 0;
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = tl * kTileA + (int64_t)j * kThreads + tid;
+            const bool valid = full || (li0 + (int64_t)j * kThreads < n);
             bool ev = false;
-            xs0[j] = 0.0;
-            xs1[j] = 0.0;
-            if (li < n) {
-                const int64_t i = base + li;
-                const double x = E.x0[i];
-                const double k = E.k0[i];
-                const uint64_t id = E.id[i];
-                double y = 0.0, ky = 0.0;
-                if (DIM == 2) { y = E.x1[i]; ky = E.k1[i]; }
-                const W4 r = draw(id, step, kTagStep, 0u, 0u, d.seed, key);
-                const double u = unit53(r.a, r.b);
-                if (u < thr_lo) {
-                    ev = true;
-                } else if (u <= thr_hi) {
-                    const double tau = -ln_series(1.0 - u) / g0;
-                    const double te = 0.0 + tau;
-                    ev = (te <= d.dt);
-                }
-                E.x0[i] = x + (d.vfac * k) * d.dt;
-                if (DIM == 2) E.x1[i] = y + (d.vfac * ky) * d.dt;
-                xs0[j] = x;
-                xs1[j] = y;
+            const W4 r = draw(idv[j], step, kTagStep, 0u, 0u, d.seed, key);
+            const double u = unit53(r.a, r.b);
+            if (u < thr_lo) {
+                ev = true;
+            } else if (u <= thr_hi) {
+                const double tau = -ln_series(1.0 - u) / g0;
+                const double te = 0.0 + tau;
+                ev = (te <= d.dt);
             }
+            ev = ev && valid;
             const uint64_t m = __ballot(ev);
             rank[j] = lane_rank(m);
             if (lane == 0) s_wcnt[j * 4 + wv] = (uint32_t)__popcll(m);
             evbits |= (ev ? 1u : 0u) << j;
+        }
+        // free flight to the end of the step
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = li0 + (int64_t)j * kThreads;
+            if (full || li < n) {
+                const int64_t i = base + li;
+                E.x0[i] = xs0[j] + (d.vfac * kv0[j]) * d.dt;
+                if (DIM == 2) E.x1[i] = xs1[j] + (d.vfac * kv1[j]) * d.dt;
+            }
         }
         __syncthreads();
         if (tid == 0) {
@@ -209,7 +232,7 @@ struct Tally {
 template <int DIM, bool SP2, bool TAN, bool EMIT>
 __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step, Node cur,
                                 const Ens &out, int64_t base, int64_t first_rec, int64_t cap,
-                                Tally &tl, uint32_t &err)
+                                int64_t dstride, Tally &tl, uint32_t &err)
 {
     Node stack[kMaxDepth];
     int sp = 0;
@@ -341,8 +364,8 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
                 out.id[o] = ch.id;
                 if (TAN) {
                     out.D[o] = ch.D[0];
-                    out.D[d.cap_total + o] = ch.D[1];
-                    out.D[2 * d.cap_total + o] = ch.D[2];
+                    out.D[dstride + o] = ch.D[1];
+                    out.D[2 * dstride + o] = ch.D[2];
                 }
             } else {
                 err |= kErrCapacity;
@@ -390,6 +413,7 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advan
     const double *evx0 = ghost ? d.gev_x0 : d.ev_x0;
     const double *evx1 = ghost ? d.gev_x1 : d.ev_x1;
     const int pass = ghost ? kPassFamilyG : kPassFamily;
+    const int64_t dstride = ghost ? d.gcap_total : d.cap_total;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t err = 0;
 
@@ -428,13 +452,13 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advan
             if (SP2) root.w = E.w[i]; else root.sg = (int32_t)E.sg[i];
             if (TAN) {
                 root.D[0] = E.D[i];
-                root.D[1] = E.D[d.cap_total + i];
-                root.D[2] = E.D[2 * d.cap_total + i];
+                root.D[1] = E.D[dstride + i];
+                root.D[2] = E.D[2 * dstride + i];
             }
         }
         Tally tal{0, 0, 0, 0, 0};
         uint32_t cnt = 0;
-        if (ok) cnt = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, tal, err);
+        if (ok) cnt = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal, err);
 
         // ordered exclusive scan of the record counts over the tile
         uint32_t incl = cnt;
@@ -465,7 +489,7 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advan
         __syncthreads();
         const int64_t my_first = n_before + (int64_t)s_excl + (int64_t)(woff + incl - cnt);
         if (ok && cnt > 0)
-            walk_family<DIM, SP2, TAN, true>(d, P, step, root, E, base, my_first, cap, tal, err);
+            walk_family<DIM, SP2, TAN, true>(d, P, step, root, E, base, my_first, cap, dstride, tal, err);
 
         // per-instance tallies
         if (tal.events) atomicAdd((unsigned long long *)&s_tal[0], (unsigned long long)tal.events);

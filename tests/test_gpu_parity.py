@@ -34,7 +34,7 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def assert_same_ensemble(a, b, fields=("x", "k", "sign", "id"), what=""):
+def assert_same_ensemble(a, b, fields=("x", "k", "sign", "w", "id"), what=""):
     for f in fields:
         if f not in a or f not in b:
             continue
@@ -51,10 +51,13 @@ def assert_same_ensemble(a, b, fields=("x", "k", "sign", "id"), what=""):
 
 
 def compare(gpu, ref, what, B=1):
+    keys = ["events", "pairs", "killed", "escaped", "max_depth", "event_cap_hits"]
+    if gpu.cfg["strategy"] == "sp2":
+        keys += ["S_plus", "S_minus", "N_plus", "N_minus"]
     for b in range(B):
         st_g, st_o = gpu.stats(b), ref.stats(b)
         assert st_g["n"] == st_o["n"], (what, b, st_g["n"], st_o["n"])
-        for key in ("events", "pairs", "killed", "escaped", "max_depth", "event_cap_hits"):
+        for key in keys:
             assert st_g[key] == st_o[key], (what, b, key, st_g[key], st_o[key])
         assert_same_ensemble(gpu.particles(b), ref.particles(b), what=f"{what} b={b}")
 
@@ -166,3 +169,103 @@ def test_capacity_overflow_is_reported(P):
     g.step(10)
     code, _ = g.stats_code()
     assert code == P.ECAPACITY
+
+
+def test_sp2_bootstrap_parity(P, O):
+    """Weighted pairs, then the signed residual bootstrap and the rounded
+    histogram: integer classes, copies, cell values and ensembles bit-exact."""
+    cfg = W.gaussian_barrier_small(N0=np.array([6000]), strategy="sp2")
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    for ep in range(3):
+        g.step(10)
+        r.step(10)
+        compare(g, r, f"sp2 before annihilation {ep}")
+        g.annihilate()
+        r.annihilate()
+        say(f"sp2: epoch {ep} n={r.count()} N+={r.stats()['N_plus']} N-={r.stats()['N_minus']}")
+        compare(g, r, f"sp2 after annihilation {ep}")
+    assert np.array_equal(g.density().cpu().numpy(), r.density())
+
+
+def test_sp2_batched_and_wide(P, O):
+    cfg = W.batched_barriers(B=3, N0=np.array([2500, 40000, 9000], dtype=np.int64), strategy="sp2")
+    cfg["grid"] = {"x_lo": -200.0, "x_hi": 200.0, "nx": 2000, "k_lo": -8.0, "k_hi": 8.0, "nk": 512}
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.run(20, 10)
+    r.run(20, 10)
+    say("sp2 batched done")
+    compare(g, r, "sp2 batched", B=3)
+
+
+def _close(a, b, what, rtol=1e-9):
+    scale = max(np.max(np.abs(b)), 1e-300) if np.size(b) else 1.0
+    err = np.max(np.abs(a - b)) if np.size(b) else 0.0
+    assert err <= rtol * scale, f"{what}: max abs err {err:.3e} vs scale {scale:.3e}"
+
+
+def test_tangent_parity(P, O):
+    """Likelihood-ratio tangents: the real ensemble stays bit-exact, ghosts
+    (integer creation rule) match exactly in count, position and id, and the
+    tangents (order-dependent floating sums per cell) agree to 1e-9 relative."""
+    cfg = W.gaussian_barrier_small(N0=np.array([5000]), gamma0=0.45, track_tangent=1)
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    for ep in range(3):
+        g.step(10)
+        r.step(10)
+        g.annihilate()
+        r.annihilate()
+        say(f"tangent: epoch {ep} n={r.count()} ghosts={r.count(ghost=True)}")
+        compare(g, r, f"tangent real {ep}")
+        pg, pr = g.particles(), r.particles()
+        _close(pg["D"], pr["D"], f"real tangents {ep}")
+        assert g.count(ghost=True) == r.count(ghost=True)
+        gg, gr = g.particles(ghost=True), r.particles(ghost=True)
+        assert_same_ensemble(gg, gr, what=f"ghosts {ep}")
+        _close(gg["D"], gr["D"], f"ghost tangents {ep}")
+    g.step(5)
+    r.step(5)
+    compare(g, r, "tangent mid-epoch")
+    _close(g.particles(ghost=True)["D"], r.particles(ghost=True)["D"], "ghost tangents mid-epoch")
+    _close(g.density_tangent().cpu().numpy(), r.density_tangent(), "tangent density")
+
+
+def test_density_vjp_and_autograd_match_oracle(P, O):
+    """Backward kernel: g . d rho / d theta from the per-particle tangents equals
+    the oracle's tangent density contracted with g (1e-9 relative); the
+    torch.autograd.Function returns the same gradient."""
+    import torch
+    from paper_1709_02121_amd import autograd as A
+    cfg = W.gaussian_barrier_small(N0=np.array([4000]), gamma0=0.45, track_tangent=1)
+    cfg["init"] = dict(cfg["init"], mean_x=[-4.0, 0.0])
+    x = -60 + 0.25 + 0.5 * np.arange(240)
+    g = 0.5 * (1 + np.tanh(x / 2.0))
+    r = O.OracleSim(cfg)
+    r.run(30, 10)
+    ref = r.density_tangent()[0] @ g
+    sim = P.Simulation(cfg)
+    sim.run(30, 10)
+    got = sim.density_vjp(torch.tensor(g)).cpu().numpy()[0]
+    _close(got, ref, "vjp")
+    theta = torch.tensor([0.3, 1.0, 0.0], dtype=torch.float64, requires_grad=True)
+    rho = A.density(theta, cfg, steps=30, annihilate_every=10, snapshot_every=10)
+    assert np.array_equal(rho.detach().cpu().numpy(), r.density()[0])
+    (rho * torch.tensor(g, device=rho.device)).sum().backward()
+    _close(theta.grad.numpy(), ref, "autograd")
+
+
+def test_snapshot_restore_continues_exactly(P, O):
+    cfg = W.gaussian_barrier_small(N0=np.array([3000]), gamma0=0.45, track_tangent=1)
+    a = P.Simulation(cfg)
+    a.run(15, 10)
+    snap = a.snapshot()
+    a.run(15, 10)
+    b = P.Simulation(cfg)
+    b.restore(snap)
+    b.run(15, 10)
+    for ghost in (False, True):
+        pa, pb = a.particles(ghost=ghost), b.particles(ghost=ghost)
+        assert_same_ensemble(pa, pb, what=f"restore ghost={ghost}")
+        assert np.array_equal(pa["D"], pb["D"]) or np.allclose(pa["D"], pb["D"], rtol=1e-12, atol=0)
+    r = O.OracleSim(cfg)
+    r.run(30, 10)
+    compare(b, r, "restore vs oracle")
