@@ -139,14 +139,26 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
         const int64_t n = Ncur[b];
         const int64_t cbase = (int64_t)b * d.Nh;
         int64_t esc = 0;
-#pragma unroll 4
+        const int64_t li0 = (t - plan[b]) * kTileA + tid;
+        double xa[kPPT], xb[kPPT], ka[kPPT], kb[kPPT];
+        int sv[kPPT];
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {      // loads first: kPPT in flight per thread
+            const int64_t li = li0 + (int64_t)j * kThreads;
+            const int64_t i = base + (li < n ? li : 0);
+            xa[j] = E.x0[i];
+            ka[j] = E.k0[i];
+            xb[j] = DIM == 2 ? E.x1[i] : 0.0;
+            kb[j] = DIM == 2 ? E.k1[i] : 0.0;
+            sv[j] = ghost ? 0 : (int)E.sg[i];
+        }
+#pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            const int64_t li = li0 + (int64_t)j * kThreads;
             if (li >= n) continue;
             const int64_t i = base + li;
-            const int64_t nu = cell_index<DIM>(d, E.x0[i], DIM == 2 ? E.x1[i] : 0.0, E.k0[i],
-                                               DIM == 2 ? E.k1[i] : 0.0);
-            const int s = ghost ? 0 : (int)E.sg[i];
+            const int64_t nu = cell_index<DIM>(d, xa[j], xb[j], ka[j], kb[j]);
+            const int s = sv[j];
             if (nu < 0) { esc += s; continue; }
             if (!ghost) atomicAdd(&d.cnt[cbase + nu], s);
             if (TAN) {
@@ -352,12 +364,21 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t n = Ncur[b];
-#pragma unroll 4
+        const int64_t li0 = (t - plan[b]) * kTileA + tid;
+        double xv[kPPT], wv[kPPT];
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {      // loads first
+            const int64_t li = li0 + (int64_t)j * kThreads;
+            const int64_t i = base + (li < n ? li : 0);
+            xv[j] = X[i];
+            if (!TAN) wv[j] = SP2 ? E.w[i] : (double)E.sg[i];
+        }
+#pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            const int64_t li = li0 + (int64_t)j * kThreads;
             if (li >= n) continue;
             const int64_t i = base + li;
-            const double q = (X[i] - lo) / dxb;
+            const double q = (xv[j] - lo) / dxb;
             if (!(q >= 0.0 && q < (double)nbins)) continue;
             const int64_t bin = (int64_t)q;
             if (TAN) {
@@ -368,7 +389,7 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
                 atomicAdd(&acc[2 * d.max_bins + bin], E.D[2 * ds + i]);
             } else {
                 int64_t v;
-                if (SP2) v = (int64_t)(E.w[i] * 4294967296.0); else v = (int64_t)E.sg[i];
+                if (SP2) v = (int64_t)(wv[j] * 4294967296.0); else v = (int64_t)wv[j];
                 atomicAdd((unsigned long long *)&d.dacc[(int64_t)b * d.max_bins + bin],
                           (unsigned long long)v);
             }
