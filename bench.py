@@ -39,11 +39,14 @@ def stream_bytes_per_particle_step(dim):
     return dim * 8 * 2 + 8 + dim * 8
 
 
-def run_form(P, torch, cfg, steps, warmup, every=ANN_EVERY, use_graph=False, density=True):
-    """Runs warmup then `steps` timed steps; returns a dict of measurements."""
+def run_form(P, torch, cfg, steps, warmup, every=ANN_EVERY, use_graph=False, density=True,
+             autotune=False):
+    """Runs warmup (and the autotuner), then `steps` timed steps; returns a dict
+    of measurements."""
     s = torch.cuda.Stream()
     sim = P.Simulation(cfg, stream=s)
     done = 0
+    tuned = None
 
     def advance(n):
         nonlocal done
@@ -56,6 +59,12 @@ def run_form(P, torch, cfg, steps, warmup, every=ANN_EVERY, use_graph=False, den
                     sim.density()
 
     advance(warmup)
+    if autotune:
+        tuned = sim.autotune(1)
+        done = sim.stats(0)["step"]
+        # re-align with the annihilation schedule before timing
+        while every and done % every:
+            advance(1)
     s.synchronize()
     ps0 = sum(sim.stats(b)["particle_steps"] for b in range(sim.B))
     sim.profile(True)
@@ -73,7 +82,8 @@ def run_form(P, torch, cfg, steps, warmup, every=ANN_EVERY, use_graph=False, den
     stats = [sim.stats(b) for b in range(sim.B)]
     ps = sum(st["particle_steps"] for st in stats) - ps0
     out = {"wall_s": wall, "particle_steps": int(ps), "rate": ps / wall,
-           "n_end": int(sum(st["n"] for st in stats)), "profile": prof, "sim": sim}
+           "n_end": int(sum(st["n"] for st in stats)), "profile": prof, "sim": sim,
+           "tuned": tuned}
     return out
 
 
@@ -137,6 +147,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first copy 1 GiB device to device (a reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -156,6 +168,15 @@ def main():
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
 
+    if args.calibrate:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del a, b
     cfg = W.gaussian_barrier_large("sp1")
     main_res = run_form(P, torch, cfg, args.steps, args.warmup)
     roof = roofline_of(main_res, 1)
@@ -177,10 +198,13 @@ def main():
                 ("helium_4d", lambda: W.helium_soft_coulomb(), 10, 0)):
             try:
                 torch.cuda.empty_cache()
-                r = run_form(P, torch, maker(), steps, warm, use_graph=(name == "batched_256"))
+                batched = name == "batched_256"
+                r = run_form(P, torch, maker(), steps, warm, use_graph=batched, autotune=batched)
                 r.pop("sim")
                 forms[name] = {"value": round(r["rate"], 1), "steps": steps,
                                "particle_steps": r["particle_steps"], "n_end": r["n_end"]}
+                if r["tuned"]:
+                    forms[name]["autotuned_grid"] = r["tuned"]
                 if name == "helium_4d":
                     rf = roofline_of(r, 2)
                     forms[name]["stream_frac_hbm"] = rf["frac"] if rf else None

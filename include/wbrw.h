@@ -166,9 +166,11 @@ int wbrw_step(wbrw_t h, int32_t nsteps);
  * order: ascending cell, then index within the cell.  No synchronisation. */
 int wbrw_annihilate(wbrw_t h);
 
-/* Runs nsteps steps with an annihilation after every annihilate_every steps
- * (counted from step 0; 0 = never).  With use_graph != 0 the step + annihilation
- * epoch is captured once into a hipGraph and replayed.  No synchronisation. */
+/* Runs nsteps steps with an annihilation after every step whose number is a
+ * multiple of annihilate_every (steps counted from 0 at wbrw_init; 0 = never).
+ * With use_graph != 0 (and a non-NULL stream) whole epochs of
+ * annihilate_every steps + annihilation are captured once into a hipGraph and
+ * replayed.  No synchronisation. */
 int wbrw_run(wbrw_t h, int32_t nsteps, int32_t annihilate_every, int32_t use_graph);
 
 /* Position density (Eq. estimator with an indicator observable):
@@ -215,6 +217,14 @@ int wbrw_count(wbrw_t h, int32_t b, int32_t ghost, int64_t *n);
  * n must equal the current count (wbrw_count).  Enqueued copies, no sync. */
 int wbrw_export(wbrw_t h, int32_t b, int32_t ghost, int64_t n, double *x, double *k,
                 int8_t *sign, double *w, uint64_t *id, double *D);
+
+/* Autotuner.  Runs 2 * candidates * steps_per_candidate time steps of the
+ * handle's own ensemble (they are real steps: results do not depend on launch
+ * shapes) while timing the streaming and family kernels at several persistent
+ * grid sizes (blocks per compute unit), then keeps the fastest of each.
+ * chosen (host, may be NULL) receives {stream blocks, family blocks}.
+ * Synchronises. */
+int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen);
 
 /* Per-stage timing with hip events recorded on the handle's stream around
  * every kernel of a stage (enable != 0 starts a fresh measurement; enable == 0

@@ -103,6 +103,7 @@ def lib():
         L.wbrw_export.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp]
         L.wbrw_destroy.argtypes = [vp]
         L.wbrw_profile.argtypes = [vp, i32]
+        L.wbrw_autotune.argtypes = [vp, i32, vp]
         L.wbrw_density_vjp.argtypes = [vp, i32, i32, C.c_double, C.c_double, vp, vp]
         L.wbrw_snapshot_size.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.wbrw_snapshot.argtypes = [vp, vp, C.c_size_t]
@@ -113,7 +114,8 @@ def lib():
         for f in ("wbrw_workspace_size", "wbrw_init", "wbrw_step", "wbrw_annihilate", "wbrw_run",
                   "wbrw_density", "wbrw_density_tangent", "wbrw_stats", "wbrw_count",
                   "wbrw_export", "wbrw_destroy", "wbrw_profile", "wbrw_profile_read",
-                  "wbrw_density_vjp", "wbrw_snapshot_size", "wbrw_snapshot", "wbrw_restore"):
+                  "wbrw_density_vjp", "wbrw_snapshot_size", "wbrw_snapshot", "wbrw_restore",
+                  "wbrw_autotune"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -286,6 +288,14 @@ class Simulation:
                                       C.c_void_p(out.data_ptr())), "wbrw_density_vjp")
         self._order_for_caller()
         return out
+
+    def autotune(self, steps_per_candidate=1):
+        """Times the step kernels at several grid sizes on real steps (results are
+        unchanged by the choice) and keeps the fastest; returns the grid sizes."""
+        out = np.zeros(2, dtype=np.int32)
+        _check(lib().wbrw_autotune(self.h, int(steps_per_candidate), out.ctypes.data_as(C.c_void_p)),
+               "wbrw_autotune")
+        return {"stream_blocks": int(out[0]), "family_blocks": int(out[1])}
 
     def snapshot(self):
         """Device copy of the current state (a torch uint8 tensor)."""

@@ -208,6 +208,7 @@ struct wbrw_handle {
     hipGraphExec_t gexec = nullptr;
     int graph_every = -1;
     int sticky = WBRW_OK;
+    int64_t host_step = 0;   // steps enqueued so far (mirror of the device counter)
     bool prof = false;
     struct Mark { int stage; hipEvent_t a, b; };
     std::vector<Mark> marks;
@@ -342,6 +343,7 @@ void enqueue_step_dim(wbrw_t h)
 int enqueue_step(wbrw_t h)
 {
     if (h->dim == 1) enqueue_step_dim<1>(h); else enqueue_step_dim<2>(h);
+    h->host_step += 1;
     return launch_check();
 }
 
@@ -652,26 +654,39 @@ int wbrw_run(wbrw_t h, int32_t nsteps, int32_t every, int32_t use_graph)
 {
     if (!h || nsteps < 0 || every < 0) return WBRW_EINVAL;
     if (every == 0) return wbrw_step(h, nsteps);
-    const int epochs = nsteps / every, rest = nsteps % every;
+    int left = nsteps;
+    // eager steps up to the next multiple of `every` (counted from step 0)
+    while (left > 0 && (h->host_step % every) != 0) {
+        int rc = enqueue_step(h);
+        if (!rc && h->host_step % every == 0) rc = enqueue_annihilate(h);
+        if (rc) return rc;
+        --left;
+    }
+    const int epochs = left / every;
     if (use_graph && h->stream != nullptr && epochs > 0) {
         if (h->graph_every != every) {
             if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
             hipGraph_t g;
             const bool prof = h->prof;
             h->prof = false;
+            const int64_t hs = h->host_step;
             HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
             int rc = WBRW_OK;
             for (int i = 0; i < every && !rc; ++i) rc = enqueue_step(h);
             if (!rc) rc = enqueue_annihilate(h);
             hipError_t e = hipStreamEndCapture(h->stream, &g);
             h->prof = prof;
+            h->host_step = hs;   // capture enqueued nothing
             if (rc) return rc;
             HIPCHK(e);
             HIPCHK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
             (void)hipGraphDestroy(g);
             h->graph_every = every;
         }
-        for (int ep = 0; ep < epochs; ++ep) HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+        for (int ep = 0; ep < epochs; ++ep) {
+            HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+            h->host_step += every;
+        }
     } else {
         for (int ep = 0; ep < epochs; ++ep) {
             int rc = wbrw_step(h, every);
@@ -679,7 +694,7 @@ int wbrw_run(wbrw_t h, int32_t nsteps, int32_t every, int32_t use_graph)
             if (rc) return rc;
         }
     }
-    return wbrw_step(h, rest);
+    return wbrw_step(h, left - epochs * every);
 }
 
 int wbrw_density(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, double *d_out)
@@ -890,6 +905,7 @@ int wbrw_restore(wbrw_t h, const void *src, size_t bytes)
     }
     HIPCHK(hipMemcpyAsync(h->d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    h->host_step = hd.ctl.step;
     return WBRW_OK;
 }
 
@@ -973,6 +989,72 @@ int wbrw_export(wbrw_t h, int32_t b, int32_t ghost, int64_t n, double *x, double
             HIPCHK(hipMemcpy2DAsync(D + c3, 24, E.D + c3 * tot + base, 8, 8, n, kd, s));
     }
     HIPCHK(hipStreamSynchronize(s));
+    return WBRW_OK;
+}
+
+int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen)
+{
+    if (!h || steps_per_candidate < 1) return WBRW_EINVAL;
+    const int occ_s = h->grid[G_STREAM] / std::max(1, h->cus);
+    const int occ_f = h->grid[G_FAMILY] / std::max(1, h->cus);
+    std::vector<int> cand;
+    for (int per : {1, 2, 3, 4, 6, 8, 12, 16})
+        if (per <= std::max(occ_s, occ_f)) cand.push_back(per);
+    if (cand.empty()) cand.push_back(1);
+    const bool prof = h->prof;
+    const std::vector<wbrw_handle::Mark> saved = h->marks;
+    h->marks.clear();
+    double best_s = 1e300, best_f = 1e300;
+    int pick_s = h->grid[G_STREAM], pick_f = h->grid[G_FAMILY];
+    for (int pass = 0; pass < 2; ++pass) {     // the first pass warms caches and code
+        for (int per : cand) {
+            const int gs = std::min(per, std::max(1, occ_s)) * h->cus;
+            const int gf = std::min(per, std::max(1, occ_f)) * h->cus;
+            h->grid[G_STREAM] = gs;
+            h->grid[G_FAMILY] = gf;
+            int64_t before = 0, after = 0;
+            int64_t tal[kTalCount];
+            HIPCHK(hipStreamSynchronize(h->stream));
+            for (int b = 0; b < h->B; ++b) {
+                HIPCHK(hipMemcpy(tal, h->d.tally + (int64_t)b * kTalCount, sizeof(tal), hipMemcpyDeviceToHost));
+                before += tal[kTalPSteps];
+            }
+            h->prof = true;
+            for (int i = 0; i < steps_per_candidate; ++i) {
+                const int rc = enqueue_step(h);
+                if (rc) { h->prof = prof; return rc; }
+            }
+            h->prof = false;
+            HIPCHK(hipStreamSynchronize(h->stream));
+            for (int b = 0; b < h->B; ++b) {
+                HIPCHK(hipMemcpy(tal, h->d.tally + (int64_t)b * kTalCount, sizeof(tal), hipMemcpyDeviceToHost));
+                after += tal[kTalPSteps];
+            }
+            double ts = 0, tf = 0;
+            for (auto &m : h->marks) {
+                float t = 0.f;
+                HIPCHK(hipEventElapsedTime(&t, m.a, m.b));
+                if (m.stage == WBRW_STAGE_STREAM) ts += t;
+                if (m.stage == WBRW_STAGE_FAMILY) tf += t;
+                (void)hipEventDestroy(m.a);
+                (void)hipEventDestroy(m.b);
+            }
+            h->marks.clear();
+            const double ps = (double)std::max<int64_t>(1, after - before);
+            if (pass == 1 && ts / ps < best_s) { best_s = ts / ps; pick_s = gs; }
+            if (pass == 1 && tf / ps < best_f) { best_f = tf / ps; pick_f = gf; }
+        }
+    }
+    h->grid[G_STREAM] = pick_s;
+    h->grid[G_FAMILY] = pick_f;
+    h->marks = saved;
+    h->prof = prof;
+    if (h->graph_every >= 0 && h->gexec) {   // a captured epoch holds the old grids
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+        h->graph_every = -1;
+    }
+    if (chosen) { chosen[0] = pick_s; chosen[1] = pick_f; }
     return WBRW_OK;
 }
 

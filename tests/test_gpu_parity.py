@@ -269,3 +269,18 @@ def test_snapshot_restore_continues_exactly(P, O):
     r = O.OracleSim(cfg)
     r.run(30, 10)
     compare(b, r, "restore vs oracle")
+
+
+def test_autotune_keeps_results(P, O):
+    """The autotuner's steps are real steps; any grid it picks gives the same bits."""
+    cfg = W.batched_barriers(B=4, N0=np.array([3000, 100, 25000, 7000], dtype=np.int64))
+    g = P.Simulation(cfg)
+    chosen = g.autotune(1)
+    n = g.stats()["step"]
+    say(f"autotune: {chosen} after {n} steps")
+    r = O.OracleSim(cfg)
+    r.step(n)
+    compare(g, r, "autotune", B=4)
+    g.run(20, 10)
+    r.run(20, 10)
+    compare(g, r, "after autotune", B=4)
