@@ -76,11 +76,14 @@ typedef struct wbrw_component {
     double center;           /* TABLE: c */
     const double *table;     /* TABLE, host: |F[V](2 q_j)| >= 0 at bin midpoints, table_n values */
     int32_t table_n;         /* TABLE: number of bins, 1 .. 65536 */
-    int32_t reserved;
+    int32_t modulated;       /* GAUSSIAN: 1 = height H (mod_a + mod_b cos(mod_omega t + mod_phase)) */
     double q_lo, q_hi;       /* TABLE: kick range [q_lo, q_hi) */
     const double *H;         /* GAUSSIAN, host [n_instances]: barrier height (any sign, nonzero) */
     const double *width;     /* GAUSSIAN, host [n_instances]: w > 0 */
     const double *center_b;  /* GAUSSIAN, host [n_instances]: x0 */
+    /* Time-varying height (Remark 1, Sec. 2): the kernel is evaluated at the
+     * absolute time of each jump; a given gamma0 must be >= max_t xi_m(t) / 2. */
+    double mod_a, mod_b, mod_omega, mod_phase;
 } wbrw_component;
 
 typedef struct wbrw_config {

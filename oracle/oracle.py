@@ -48,6 +48,9 @@ class Config(C.Structure):
         ("init_mean_k", C.c_double * 2), ("init_sigma_k", C.c_double * 2),
         ("x_lo", C.c_double), ("x_hi", C.c_double), ("k_lo", C.c_double), ("k_hi", C.c_double),
         ("nx", C.c_int32), ("nk", C.c_int32),
+        ("time_dependent", C.c_int32), ("pad1", C.c_int32),
+        ("mod_a", C.c_double * MAXM), ("mod_b", C.c_double * MAXM),
+        ("mod_omega", C.c_double * MAXM), ("mod_phase", C.c_double * MAXM),
     ]
 
 
@@ -168,7 +171,11 @@ class OracleSim:
         H = np.zeros(B * M)
         W = np.ones(B * M)
         X0 = np.zeros(B * M)
+        c.time_dependent = int(any("modulation" in comp for comp in comps))
         for m, comp in enumerate(comps):
+            mod = comp.get("modulation", {"a": 1.0, "b": 0.0, "omega": 0.0, "phase": 0.0})
+            c.mod_a[m], c.mod_b[m] = float(mod["a"]), float(mod["b"])
+            c.mod_omega[m], c.mod_phase[m] = float(mod["omega"]), float(mod["phase"])
             c.comp_kind[m] = KIND[comp["kind"]]
             c.comp_axis[m] = int(comp["axis"])
             if comp["kind"] == "gauss":

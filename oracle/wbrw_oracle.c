@@ -75,6 +75,9 @@ typedef struct {
     double init_mean_x[2], init_sigma_x[2], init_mean_k[2], init_sigma_k[2];
     double x_lo, x_hi, k_lo, k_hi;
     int32_t nx, nk;
+    /* time-dependent Gaussian heights (Remark 1): H_m(t) = H_m (a + b cos(omega t + phase)) */
+    int32_t time_dependent, pad1;
+    double mod_a[ORC_MAXM], mod_b[ORC_MAXM], mod_omega[ORC_MAXM], mod_phase[ORC_MAXM];
 } orc_config;
 
 typedef struct {
@@ -349,6 +352,11 @@ static void setup_instance(orc_sim *S, int b)
             I->center[m] = C->center[b * C->M + m];
             I->xi[m] = (2.0 * fabs(I->H[m])) / C->hbar;
             I->sq[m] = 0.5 / I->width[m];
+            if (C->time_dependent) {   /* the largest xi_m over time bounds gamma0 from below */
+                double amp = fabs(C->mod_a[m]) + fabs(C->mod_b[m]);
+                double xmax = (2.0 * (fabs(I->H[m]) * amp)) / C->hbar;
+                if (xmax > g) g = xmax;
+            }
         } else {
             I->center[m] = C->comp_center[m];
             I->xi[m] = S->xi_table[m];
@@ -458,10 +466,24 @@ static double comp_arg(const orc_sim *S, int m, const double *x, double center)
  * the kick q from G_m/xi_m, the sine of the kernel's phase, the direction
  * sigma = sgn(F[V_m]) sgn(sin) of the "+" offspring, and the acceptance
  * uniform (component 0 shares the draw that produced the life-length). */
-typedef struct { double q, arg, sn, sigma, u_acc; } jump_t;
+typedef struct { double q, arg, sn, sigma, u_acc, c; } jump_t;
+
+/* Pair probability per unit |sin| and sign of F[V_m] at absolute time t:
+ * Remark 1 evaluates the kernel of a time-varying potential at the jump. */
+static void kernel_at(const orc_sim *S, const inst_t *I, int m, double t, double *c, double *sgnV)
+{
+    const orc_config *C = &S->cfg;
+    if (C->comp_kind[m] != KIND_GAUSS) { *c = I->c[m]; *sgnV = C->comp_sgn[m]; return; }
+    if (!C->time_dependent) { *c = I->c[m]; *sgnV = I->H[m] >= 0.0 ? 1.0 : -1.0; return; }
+    double f = C->mod_a[m] + C->mod_b[m] * orc_dcos(C->mod_omega[m] * t + C->mod_phase[m]);
+    double He = I->H[m] * f;
+    double xi = (2.0 * fabs(He)) / C->hbar;
+    *c = xi / (2.0 * I->gamma0);
+    *sgnV = He >= 0.0 ? 1.0 : -1.0;
+}
 
 static void draw_jump(const orc_sim *S, const inst_t *I, uint64_t id, uint32_t e, int m,
-                      const double *xe, double u_acc0, jump_t *J)
+                      const double *xe, double u_acc0, double t_abs, jump_t *J)
 {
     const orc_config *C = &S->cfg;
     uint32_t rq[4];
@@ -469,8 +491,8 @@ static void draw_jump(const orc_sim *S, const inst_t *I, uint64_t id, uint32_t e
     J->q = sample_kick(S, I, m, orc_u01(rq[0], rq[1]), orc_u01(rq[2], rq[3]));
     J->arg = (2.0 * J->q) * comp_arg(S, m, xe, I->center[m]);
     J->sn = orc_dsin(J->arg);
-    double sgnV = (C->comp_kind[m] == KIND_GAUSS) ? (I->H[m] >= 0.0 ? 1.0 : -1.0)
-                                                  : C->comp_sgn[m];
+    double sgnV;
+    kernel_at(S, I, m, t_abs, &J->c, &sgnV);
     J->sigma = (J->sn > 0.0) ? sgnV : -sgnV;
     J->u_acc = u_acc0;
     if (m > 0) {
@@ -518,12 +540,13 @@ static void walk(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth)
             xe[d] = P->x[d] + (S->vfac * P->k[d]) * (te - P->t0);
         for (int m = 0; m < C->M; m++) {
             jump_t J;
-            draw_jump(S, I, P->id, e, m, xe, u_acc0, &J);
+            double t_abs = (double)S->step * dt + te;
+            draw_jump(S, I, P->id, e, m, xe, u_acc0, t_abs, &J);
             double amp = 0.0;
             if (!sp2) {
-                if (!(J.u_acc < I->c[m] * fabs(J.sn))) continue;   /* sp1 box of Alg. 1 */
+                if (!(J.u_acc < J.c * fabs(J.sn))) continue;     /* sp1 box of Alg. 1 */
             } else {
-                amp = P->w * (I->c[m] * fabs(J.sn));             /* wp/sp2 box of Alg. 1 */
+                amp = P->w * (J.c * fabs(J.sn));                 /* wp/sp2 box of Alg. 1 */
             }
             double q = J.q, arg = J.arg, sn = J.sn, sigma = J.sigma;
             I->st.pairs++;
@@ -1048,8 +1071,8 @@ void orc_probe_jump(orc_sim *S, int b, int m, const double *x, uint64_t id, uint
     uint32_t r[4];
     rng4(S->cfg.seed, I->key_inst, id, S->step, TAG_STEP, e, 0, r);
     jump_t J;
-    draw_jump(S, I, id, e, m, x, orc_u01(r[2], r[3]), &J);
-    *accepted = (J.u_acc < I->c[m] * fabs(J.sn)) ? 1 : 0;
+    draw_jump(S, I, id, e, m, x, orc_u01(r[2], r[3]), (double)S->step * S->cfg.dt, &J);
+    *accepted = (J.u_acc < J.c * fabs(J.sn)) ? 1 : 0;
     *kick = J.sigma * J.q;
     *sn_out = J.sn;
 }

@@ -47,10 +47,12 @@ def build(verbose=False):
 class Component(C.Structure):
     _fields_ = [("kind", C.c_int32), ("axis", C.c_int32), ("sign", C.c_double),
                 ("center", C.c_double), ("table", C.POINTER(C.c_double)),
-                ("table_n", C.c_int32), ("reserved", C.c_int32),
+                ("table_n", C.c_int32), ("modulated", C.c_int32),
                 ("q_lo", C.c_double), ("q_hi", C.c_double),
                 ("H", C.POINTER(C.c_double)), ("width", C.POINTER(C.c_double)),
-                ("center_b", C.POINTER(C.c_double))]
+                ("center_b", C.POINTER(C.c_double)),
+                ("mod_a", C.c_double), ("mod_b", C.c_double),
+                ("mod_omega", C.c_double), ("mod_phase", C.c_double)]
 
 
 class Config(C.Structure):
@@ -161,6 +163,11 @@ def make_config(cfg):
         if comp["kind"] == "gauss":
             q.H, q.width, q.center_b = dptr(comp["H"]), dptr(comp["width"]), dptr(comp["center"])
             q.sign = 1.0
+            if "modulation" in comp:
+                mod = comp["modulation"]
+                q.modulated = 1
+                q.mod_a, q.mod_b = float(mod["a"]), float(mod["b"])
+                q.mod_omega, q.mod_phase = float(mod["omega"]), float(mod["phase"])
         else:
             t = np.ascontiguousarray(comp["table"], dtype=np.float64)
             q.table = dptr(t)

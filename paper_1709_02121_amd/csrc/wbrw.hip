@@ -63,8 +63,21 @@ int validate(const wbrw_config *c)
     if (c->max_density_bins < 1) return WBRW_EINVAL;
     if (c->track_tangent) {
         if (c->strategy != WBRW_SP1 || c->dim != 1 || c->n_components != 1 ||
-            c->comp[0].kind != WBRW_KERNEL_GAUSSIAN || c->ghost_capacity < 1)
+            c->comp[0].kind != WBRW_KERNEL_GAUSSIAN || c->ghost_capacity < 1 || c->comp[0].modulated)
             return WBRW_EINVAL;
+    }
+    for (int m = 0; m < c->n_components; ++m) {
+        const wbrw_component &q = c->comp[m];
+        if (!q.modulated) continue;
+        if (q.kind != WBRW_KERNEL_GAUSSIAN || !std::isfinite(q.mod_a) || !std::isfinite(q.mod_b) ||
+            !std::isfinite(q.mod_omega) || !std::isfinite(q.mod_phase))
+            return WBRW_EINVAL;
+        // a given gamma0 must keep the pair probability <= 1 at every time
+        if (c->gamma0 > 0 && q.H)
+            for (int b = 0; b < c->n_instances; ++b)
+                if ((2.0 * (std::fabs(q.H[b]) * (std::fabs(q.mod_a) + std::fabs(q.mod_b)))) / c->hbar >
+                    2.0 * c->gamma0 * (1.0 + 1e-12))
+                    return WBRW_EINVAL;
     }
     if (!(c->gamma0 > 0) && !(c->gamma_scale > 0)) return WBRW_EINVAL;
     for (int m = 0; m < c->n_components; ++m) {
@@ -256,6 +269,14 @@ void derive(const wbrw_config *c, int b, const std::vector<double> &xi_tab,
             xi = (2.0 * std::fabs(P.H[m])) / c->hbar;   // (1/(pi hbar)) int |F[V](s)| ds = 2|H|/hbar
             P.sq[m] = 0.5 / P.width[m];
             P.sgnV[m] = P.H[m] >= 0.0 ? 1.0 : -1.0;
+            P.ma[m] = q.modulated ? q.mod_a : 1.0;
+            P.mb[m] = q.modulated ? q.mod_b : 0.0;
+            P.mw[m] = q.modulated ? q.mod_omega : 0.0;
+            P.mp[m] = q.modulated ? q.mod_phase : 0.0;
+            if (q.modulated) {   // the largest xi_m over time bounds a derived gamma0
+                const double xmax = (2.0 * (std::fabs(P.H[m]) * (std::fabs(q.mod_a) + std::fabs(q.mod_b)))) / c->hbar;
+                if (xmax > g) g = xmax;
+            }
         } else {
             xi = xi_tab[m];
             P.center[m] = q.center;
@@ -479,6 +500,9 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.M = h->M;
     d.strategy = h->strategy;
     d.tangent = h->tangent;
+    d.hbar = cfg->hbar;
+    d.tdep = 0;
+    for (int m = 0; m < cfg->n_components; ++m) if (cfg->comp[m].modulated) d.tdep = 1;
     d.nx = cfg->nx;
     d.nk = cfg->nk;
     d.seed = cfg->seed;

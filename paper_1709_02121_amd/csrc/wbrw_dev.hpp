@@ -44,6 +44,8 @@ struct InstParam {
     double H[kMaxM], width[kMaxM];  // Gaussian parameters (tangent scores)
     double center[kMaxM];           // centre of the kernel phase
     double sgnV[kMaxM];             // sign of F[V_m]
+    double ma[kMaxM], mb[kMaxM];    // time-varying height factor a + b cos(omega t + phase)
+    double mw[kMaxM], mp[kMaxM];
     int64_t base, cap;              // particle segment
     int64_t gbase, gcap;            // ghost segment
     int64_t N0;                     // sample size N_alpha
@@ -80,6 +82,8 @@ struct Ctl {
 struct Dev {
     // sizes and constants
     int32_t B, dim, M, strategy, tangent;
+    int32_t tdep;               // some Gaussian height varies in time
+    double hbar;
     int32_t nx, nk;
     uint32_t seed;
     int64_t Nh;                 // cells per instance

@@ -285,7 +285,15 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
         const double q = kick_sample(d, P, m, unit53(rq.a, rq.b), unit53(rq.c, rq.d));
         const double arg = (2.0 * q) * phase_offset(d, m, cur.xe, P.center[m]);
         const double sn = sin_det(arg);
-        const double sigma = (sn > 0.0) ? P.sgnV[m] : -P.sgnV[m];
+        double cm = P.c[m], sgv = P.sgnV[m];
+        if (d.tdep && d.kind[m] == 0) {        // Remark 1: kernel at the absolute jump time
+            const double tabs = (double)step * d.dt + cur.te;
+            const double f = P.ma[m] + P.mb[m] * cos_det(P.mw[m] * tabs + P.mp[m]);
+            const double He = P.H[m] * f;
+            cm = ((2.0 * fabs(He)) / d.hbar) / (2.0 * P.gamma0);
+            sgv = He >= 0.0 ? 1.0 : -1.0;
+        }
+        const double sigma = (sn > 0.0) ? sgv : -sgv;
         double amp = 0.0;
         if (!SP2) {
             double ua = cur.ua0;
@@ -293,13 +301,13 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
                 const W4 ra = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(8 + m), seed, key);
                 ua = unit53(ra.a, ra.b);
             }
-            if (!(ua < P.c[m] * fabs(sn))) {   // no pair: only the survivor continues
+            if (!(ua < cm * fabs(sn))) {       // no pair: only the survivor continues
                 cur.m += 1;
                 cur.side = 0;
                 continue;
             }
         } else {
-            amp = cur.w * (P.c[m] * fabs(sn));
+            amp = cur.w * (cm * fabs(sn));
         }
         const int side = cur.side;
         if (!EMIT && side == 0) tl.pairs++;

@@ -284,3 +284,15 @@ def test_autotune_keeps_results(P, O):
     g.run(20, 10)
     r.run(20, 10)
     compare(g, r, "after autotune", B=4)
+
+
+@pytest.mark.parametrize("strategy", ["sp1", "sp2"])
+def test_time_dependent_potential_parity(P, O, strategy):
+    """Remark 1: kernel evaluated at the absolute jump time (switching left barrier)."""
+    cfg = W.time_dependent_barriers(N0=np.array([5000]), strategy=strategy)
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.run(60, 10)
+    r.run(60, 10)
+    say(f"time-dependent {strategy}: n={r.count()}")
+    compare(g, r, f"time-dependent {strategy}")
+    assert np.array_equal(g.density().cpu().numpy(), r.density())

@@ -165,6 +165,26 @@ def differentiation(**over):
     return _override(cfg, over)
 
 
+def time_dependent_barriers(**over):
+    """Double barrier whose left barrier switches (Sec. 5.6): heights
+    0.8 (0.5 + 0.5 cos(pi + 0.1 t)) at x = -10 and 0.8 at x = +10, both of
+    width 2 (exp(-(x -+ 10)^2/8)); packet from x = -15 (k = 1.5, sigma_x = 1),
+    gamma0 = 1, dt = 0.1, 600 steps, annihilation every 10 on 240 x 128 over
+    [-60,60) x [-8,8).  The switching barrier is placed on the left, as the
+    paper's description of the dynamics has it."""
+    cfg = gaussian_barrier_small()
+    comp_a = _gauss_component(1, 0.8, 2.0, -10.0)
+    comp_a["modulation"] = {"a": 0.5, "b": 0.5, "omega": 0.1, "phase": math.pi}
+    comp_b = _gauss_component(1, 0.8, 2.0, 10.0)
+    cfg.update({
+        "name": "time_dependent_barriers_1e4",
+        "components": [comp_a, comp_b],
+        "gamma0": 1.0,
+        "steps": 600,
+    })
+    return _override(cfg, over)
+
+
 def with_theta(cfg, H=None, width=None, center=None):
     """Copy of a single-Gaussian workload with barrier parameters replaced."""
     c = copy.deepcopy(cfg)
@@ -201,4 +221,5 @@ ALL = {
     "helium_soft_coulomb_1e7": helium_soft_coulomb,
     "batched_barriers_256": batched_barriers,
     "differentiation_1e7": differentiation,
+    "time_dependent_barriers_1e4": time_dependent_barriers,
 }
