@@ -104,6 +104,9 @@ typedef struct wbrw_config {
     const int64_t *capacity;  /* host [n_instances]: most particles an instance may hold, < 2^31 */
     int64_t ghost_capacity;   /* per instance, tangent ghosts (track_tangent only) */
     double init_mean_x[2], init_sigma_x[2], init_mean_k[2], init_sigma_k[2];
+    const double *init_hist;  /* host [n_instances][N_h] or NULL: signed histogram d_nu of the
+                                 initial Wigner function (cell order as the grid), sampled by
+                                 Alg. 3 (Sec. 4.1) instead of the Gaussian f0 */
     double x_lo, x_hi;        /* annihilation grid and K box: every position axis */
     double k_lo, k_hi;        /* ... every wave-vector axis; offspring outside K are removed */
     int32_t nx, nk;           /* cells per position / wave-vector axis */

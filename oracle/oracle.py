@@ -51,6 +51,8 @@ class Config(C.Structure):
         ("time_dependent", C.c_int32), ("pad1", C.c_int32),
         ("mod_a", C.c_double * MAXM), ("mod_b", C.c_double * MAXM),
         ("mod_omega", C.c_double * MAXM), ("mod_phase", C.c_double * MAXM),
+        ("init_kind", C.c_int32), ("pad2", C.c_int32),
+        ("init_hist", C.POINTER(C.c_double)),
     ]
 
 
@@ -207,6 +209,11 @@ class OracleSim:
         g = cfg["grid"]
         c.x_lo, c.x_hi, c.nx = float(g["x_lo"]), float(g["x_hi"]), int(g["nx"])
         c.k_lo, c.k_hi, c.nk = float(g["k_lo"]), float(g["k_hi"]), int(g["nk"])
+        if "init_histogram" in cfg:
+            hist = np.ascontiguousarray(cfg["init_histogram"], dtype=np.float64).ravel()
+            self._keep.append(hist)
+            c.init_kind = 1
+            c.init_hist = hist.ctypes.data_as(C.POINTER(C.c_double))
         self._c = c
         self.h = lib().orc_create(C.byref(c))
 

@@ -46,7 +46,7 @@ typedef __int128 i128;
 #define ORC_EMAX 4096u /* event cap per particle-step (never reached at the configs) */
 
 enum { TAG_STEP = 0, TAG_REGEN = 1, TAG_INIT = 2, TAG_BOOT = 3, TAG_ROUND = 4,
-       TAG_CHILD = 5, TAG_GHOST = 6 };
+       TAG_CHILD = 5, TAG_GHOST = 6, TAG_HIST = 7 };
 enum { KIND_GAUSS = 0, KIND_TABLE = 1 };
 enum { STRAT_SP1 = 0, STRAT_SP2 = 1 };
 
@@ -78,6 +78,10 @@ typedef struct {
     /* time-dependent Gaussian heights (Remark 1): H_m(t) = H_m (a + b cos(omega t + phase)) */
     int32_t time_dependent, pad1;
     double mod_a[ORC_MAXM], mod_b[ORC_MAXM], mod_omega[ORC_MAXM], mod_phase[ORC_MAXM];
+    /* initial data: 0 = Gaussian f0 sampled exactly; 1 = signed histogram d_nu on
+     * the grid ([B][N_h] values of the Wigner function), sampled by Alg. 3 */
+    int32_t init_kind, pad2;
+    const double *init_hist;
 } orc_config;
 
 typedef struct {
@@ -396,6 +400,8 @@ static void init_instance(orc_sim *S, int b)
     }
 }
 
+static void init_from_histogram(orc_sim *S, int b);
+
 orc_sim *orc_create(const orc_config *cfg)
 {
     orc_sim *S = (orc_sim *)calloc(1, sizeof(orc_sim));
@@ -413,7 +419,8 @@ orc_sim *orc_create(const orc_config *cfg)
     S->I = (inst_t *)calloc((size_t)cfg->B, sizeof(inst_t));
     for (int b = 0; b < cfg->B; b++) {
         setup_instance(S, b);
-        init_instance(S, b);
+        if (cfg->init_kind == 1) init_from_histogram(S, b);
+        else init_instance(S, b);
     }
     return S;
 }
@@ -749,6 +756,34 @@ static void regenerate(orc_sim *S, inst_t *I, const int64_t *cnt, const int64_t 
     I->real = out;
     ens_free(&I->ghost);
     I->ghost = gout;
+}
+
+/* Alg. 3 (Sec. 4.1): importance sampling from a signed histogram d_nu.
+ * Step 1 (rounding): m = N_alpha mu(D_nu) |d_nu|, n = [m] + p with p = 1 iff
+ * u < m - [m] (one uniform per cell, tag 7 at step 0); step 2: sign
+ * sgn(d_nu); step 3: uniform in the cell (the same placement, ids and order as
+ * a regeneration). */
+static void init_from_histogram(orc_sim *S, int b)
+{
+    const orc_config *C = &S->cfg;
+    inst_t *I = &S->I[b];
+    int64_t nc = n_cells(S);
+    double dx = (C->x_hi - C->x_lo) / (double)C->nx;
+    double dk = (C->k_hi - C->k_lo) / (double)C->nk;
+    double mu = C->dim == 1 ? dx * dk : ((dx * dx) * dk) * dk;
+    int64_t *cnt = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+    for (int64_t nu = 0; nu < nc; nu++) {
+        double dv = C->init_hist[(int64_t)b * nc + nu];
+        if (dv == 0.0) continue;
+        double m = ((double)I->N0 * mu) * fabs(dv);
+        double fl = floor(m);
+        uint32_t r[4];
+        rng4(C->seed, I->key_inst, (uint64_t)nu, 0, TAG_HIST, 0, 0, r);
+        int64_t n = (int64_t)fl + (orc_u01(r[0], r[1]) < m - fl ? 1 : 0);
+        cnt[nu] = dv > 0.0 ? n : -n;
+    }
+    regenerate(S, I, cnt, NULL, NULL);
+    free(cnt);
 }
 
 /* sp1 annihilation: Eq. signed_histogram, n_nu = n_nu^+ - n_nu^- exactly,

@@ -67,6 +67,7 @@ class Config(C.Structure):
                 ("ghost_capacity", C.c_int64),
                 ("init_mean_x", C.c_double * 2), ("init_sigma_x", C.c_double * 2),
                 ("init_mean_k", C.c_double * 2), ("init_sigma_k", C.c_double * 2),
+                ("init_hist", C.POINTER(C.c_double)),
                 ("x_lo", C.c_double), ("x_hi", C.c_double),
                 ("k_lo", C.c_double), ("k_hi", C.c_double),
                 ("nx", C.c_int32), ("nk", C.c_int32)]
@@ -193,6 +194,8 @@ def make_config(cfg):
     g = cfg["grid"]
     c.x_lo, c.x_hi, c.nx = float(g["x_lo"]), float(g["x_hi"]), int(g["nx"])
     c.k_lo, c.k_hi, c.nk = float(g["k_lo"]), float(g["k_hi"]), int(g["nk"])
+    if "init_histogram" in cfg:
+        c.init_hist = dptr(np.ravel(cfg["init_histogram"]))
     return c, keep
 
 

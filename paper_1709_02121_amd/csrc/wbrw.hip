@@ -35,7 +35,7 @@ struct Layout {
            tileG = 0, tally = 0, ev_idx = 0, ev_x0 = 0, ev_x1 = 0, gev_idx = 0, gev_x0 = 0,
            gev_x1 = 0, stA = 0, stAg = 0, stB = 0, stBg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
-           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0;
+           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
     int64_t tilesA = 0, tilesAg = 0, tilesB = 0, tilesBg = 0, tilesS = 0, tilesP = 0;
 };
@@ -158,6 +158,7 @@ Layout make_layout(const wbrw_config *c)
     for (int m = 0; m < c->n_components; ++m)
         if (c->comp[m].kind == WBRW_KERNEL_TABLE) L.tab[m] = take(cur, ((size_t)c->comp[m].table_n + 1) * 8);
     L.off = take(cur, BB * Nh * 8);
+    if (c->init_hist) L.hist = take(cur, BB * Nh * 8);
     if (sp2) {
         L.bA = take(cur, C * 8);
         L.bcopies = take(cur, C * 4);
@@ -642,6 +643,28 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         if (cfg->comp[m].kind == WBRW_KERNEL_TABLE &&
             hipMemcpyAsync((void *)d.tab[m].cum, cums[m].data(), 8 * cums[m].size(), hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(WBRW_EHIP);
+    if (cfg->init_hist) {
+        // Alg. 3 from the caller's signed histogram: rounding, scan, placement
+        double *hd = at<double>(w, L.hist);
+        if (hipMemcpyAsync(hd, cfg->init_hist, 8 * (size_t)h->B * L.Nh, hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(WBRW_EHIP);
+        const double mu = cfg->dim == 1 ? d.dx * d.dk : ((d.dx * d.dx) * d.dk) * d.dk;
+        const int nb = std::max(1, std::min(h->cus * 8, (int)ceil_div((int64_t)h->B * L.Nh, kThreads)));
+        hipLaunchKernelGGL(k_hist_round, dim3(nb), dim3(kThreads), 0, s, d, (const double *)hd, mu);
+        hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
+        if (h->dim == 1) {
+            if (h->strategy == WBRW_SP2) hipLaunchKernelGGL((k_regen<1, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+            else if (h->tangent) hipLaunchKernelGGL((k_regen<1, false, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+            else hipLaunchKernelGGL((k_regen<1, false, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+        } else {
+            if (h->strategy == WBRW_SP2) hipLaunchKernelGGL((k_regen<2, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+            else hipLaunchKernelGGL((k_regen<2, false, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+        }
+        if (launch_check()) return fail(WBRW_EHIP);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(WBRW_EHIP);
+        *out = h;
+        return WBRW_OK;
+    }
     const int init_blocks = std::max<int64_t>(1, std::min<int64_t>(plan[h->B], (int64_t)h->cus * 16));
     if (h->dim == 1)
         hipLaunchKernelGGL(k_init<1>, dim3(init_blocks), dim3(kThreads), 0, s, d,

@@ -114,6 +114,28 @@ __global__ __launch_bounds__(kThreads) void k_init(Dev d, double mx0, double mx1
 }
 
 // ---------------------------------------------------------------------------
+// Alg. 3 (Sec. 4.1), signed initial data: n_nu = [m] + p with
+// m = N_alpha mu(D_nu) |d_nu| and p = 1 iff u < m - [m] (one uniform per cell),
+// sign sgn(d_nu); k_scan and k_regen then place the particles uniformly.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_hist_round(Dev d, const double *hist, double mu)
+{
+    const int64_t plane = (int64_t)d.B * d.Nh;
+    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < plane;
+         g += (int64_t)gridDim.x * kThreads) {
+        const double dv = hist[g];
+        if (dv == 0.0) { d.cnt[g] = 0; continue; }
+        const int64_t b = g / d.Nh, nu = g - b * d.Nh;
+        const InstParam &P = d.ip[b];
+        const double m = ((double)P.N0 * mu) * fabs(dv);
+        const double fl = floor(m);
+        const W4 u = draw((uint64_t)nu, 0u, kTagHist, 0u, 0u, d.seed, P.key);
+        const int64_t n = (int64_t)fl + (unit53(u.a, u.b) < m - fl ? 1 : 0);
+        d.cnt[g] = (int32_t)(dv > 0.0 ? n : -n);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // sp1 annihilation, pass 1: binning with exact integer sums per cell.
 // ---------------------------------------------------------------------------
 template <int DIM, bool TAN>

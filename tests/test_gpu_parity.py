@@ -296,3 +296,14 @@ def test_time_dependent_potential_parity(P, O, strategy):
     say(f"time-dependent {strategy}: n={r.count()}")
     compare(g, r, f"time-dependent {strategy}")
     assert np.array_equal(g.density().cpu().numpy(), r.density())
+
+
+def test_signed_histogram_init_parity(P, O):
+    """Alg. 3 initial sampling of signed data (cat state), then steps with the barrier."""
+    cfg = W.cat_state_barrier(N0=30_000)
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    compare(g, r, "histogram init")
+    g.run(20, 10)
+    r.run(20, 10)
+    say(f"cat state: n={r.count()}")
+    compare(g, r, "histogram init + steps")

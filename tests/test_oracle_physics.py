@@ -246,3 +246,36 @@ def test_time_dependent_potential_matches_schroedinger(oracle_mod):
         got = d[(c >= a) & (c < b)].sum() * 0.5
         exact = rho[(x >= a) & (x < b)].sum() * dx
         assert abs(got - exact) < 0.04, (a, b, got, exact)
+
+
+def test_signed_histogram_sampling_cat_state(oracle_mod):
+    """Alg. 3 with signed data: a cat state whose Wigner function is negative on
+    interference fringes.  The signed k-marginal of the sample matches |phi(k)|^2
+    (FFT of psi), and after free flight to T = 8, where the packets overlap, the
+    density matches |psi(x, T)|^2; dropping the signs gives errors of O(1)."""
+    L, n = 400.0, 16384
+    x = -L / 2 + np.arange(n) * L / n
+    psi = (np.exp(-(x + 20) ** 2 / 4) + np.exp(-(x + 10) ** 2 / 4)) * np.exp(1.5j * x)
+    kk = 2 * np.pi * np.fft.fftfreq(n, d=L / n)
+    phi = np.abs(np.fft.fft(psi)) ** 2
+    order = np.argsort(kk)
+    kk, phi = kk[order], phi[order]
+    phi = phi / (phi.sum() * (kk[1] - kk[0]))
+    psiT = np.fft.ifft(np.exp(-0.5j * (2 * np.pi * np.fft.fftfreq(n, d=L / n)) ** 2 * 8.0) * np.fft.fft(psi))
+    rhoT = np.abs(psiT) ** 2
+    rhoT /= rhoT.sum() * (L / n)
+    cfg = W.cat_state_barrier(N0=200_000, seed=4, gamma0=0.3)
+    cfg = W.with_theta(cfg, H=0.0)
+    s = oracle_mod.OracleSim(cfg)
+    p = s.particles()
+    assert np.any(p["sign"] < 0)
+    kb = np.linspace(-8, 8, 513)
+    kc = 0.5 * (kb[1:] + kb[:-1])
+    h, _ = np.histogram(p["k"][0], kb, weights=p["sign"].astype(float))
+    dens_k = h / 200_000 / (kb[1] - kb[0])
+    sel = (kc > -1) & (kc < 4)
+    assert np.abs(dens_k - np.interp(kc, kk, phi))[sel].sum() * (kb[1] - kb[0]) < 0.01
+    s.step(80)
+    d = s.density()[0]
+    c = -60 + 0.25 + 0.5 * np.arange(240)
+    assert np.abs(d - np.interp(c, x, rhoT)).sum() * 0.5 < 0.04

@@ -185,6 +185,36 @@ def time_dependent_barriers(**over):
     return _override(cfg, over)
 
 
+def cat_state_wigner(x, k, sep=10.0, center=-15.0, k0=1.5, sigma=1.0):
+    """Wigner function (hbar = 1, integral 1) of the normalised superposition of
+    two Gaussian packets of width sigma at center -+ sep/2 with wave number k0;
+    its interference term makes it negative on fringes of period 2 pi / sep in k."""
+    a, b = center - sep / 2, center + sep / 2
+    g = lambda c: np.exp(-(x - c) ** 2 / (2 * sigma ** 2) - 2 * sigma ** 2 * (k - k0) ** 2) / np.pi
+    overlap = np.exp(-sep ** 2 / (8 * sigma ** 2))
+    cross = 2.0 * np.exp(-(x - center) ** 2 / (2 * sigma ** 2) - 2 * sigma ** 2 * (k - k0) ** 2) \
+        * np.cos(sep * (k - k0)) / np.pi
+    return (g(a) + g(b) + cross) / (2.0 * (1.0 + overlap))
+
+
+def cat_state_barrier(N0=200_000, **over):
+    """Signed initial data: the cat state above tabulated at the centres of a
+    240 x 512 grid over [-60,60) x [-8,8) (dk = 1/32 resolves the fringes of
+    period 0.63) and sampled by importance sampling from the histogram (Alg. 3);
+    Gaussian barrier 0.3 exp(-x^2/2); dt = 0.1."""
+    cfg = gaussian_barrier_small(N0=np.array([N0]))
+    cfg["grid"] = dict(cfg["grid"], nk=512)
+    g = cfg["grid"]
+    dx = (g["x_hi"] - g["x_lo"]) / g["nx"]
+    dk = (g["k_hi"] - g["k_lo"]) / g["nk"]
+    xc = g["x_lo"] + (np.arange(g["nx"]) + 0.5) * dx
+    kc = g["k_lo"] + (np.arange(g["nk"]) + 0.5) * dk
+    hist = cat_state_wigner(xc[None, :], kc[:, None])      # [nk][nx]: cell nu = ix + nx ik
+    cfg.update({"name": "cat_state_barrier", "init_histogram": hist.reshape(1, -1),
+                "capacity_factor": 12.0})
+    return _override(cfg, over)
+
+
 def with_theta(cfg, H=None, width=None, center=None):
     """Copy of a single-Gaussian workload with barrier parameters replaced."""
     c = copy.deepcopy(cfg)
@@ -222,4 +252,5 @@ ALL = {
     "batched_barriers_256": batched_barriers,
     "differentiation_1e7": differentiation,
     "time_dependent_barriers_1e4": time_dependent_barriers,
+    "cat_state_barrier": cat_state_barrier,
 }
