@@ -84,6 +84,14 @@ typedef struct wbrw_component {
     /* Time-varying height (Remark 1, Sec. 2): the kernel is evaluated at the
      * absolute time of each jump; a given gamma0 must be >= max_t xi_m(t) / 2. */
     double mod_a, mod_b, mod_omega, mod_phase;
+    /* GAUSSIAN kick sampler: 0 = majorant |F[V](2q)| with pair probability
+     * xi_hat |sin| / (2 gamma0) (Remark 3, Sec. 4.2); 1 = Alg. 4 (Sec. 4.2): pair
+     * probability xi(x)/gamma0 from xi tabulated on 4097 points over |x - x0| in
+     * [0, 8w] (midpoint quadrature, 8192 nodes) with linear interpolation, and
+     * the kick by rejection from V_W^+(x, .) (at most 256 proposals; sp1 only,
+     * static height, no tangents). */
+    int32_t sampler;
+    int32_t reserved2;
 } wbrw_component;
 
 typedef struct wbrw_config {

@@ -53,6 +53,7 @@ class Config(C.Structure):
         ("mod_omega", C.c_double * MAXM), ("mod_phase", C.c_double * MAXM),
         ("init_kind", C.c_int32), ("pad2", C.c_int32),
         ("init_hist", C.POINTER(C.c_double)),
+        ("sampler", C.c_int32 * MAXM),
     ]
 
 
@@ -180,6 +181,7 @@ class OracleSim:
             c.mod_omega[m], c.mod_phase[m] = float(mod["omega"]), float(mod["phase"])
             c.comp_kind[m] = KIND[comp["kind"]]
             c.comp_axis[m] = int(comp["axis"])
+            c.sampler[m] = 1 if comp.get("sampler", "majorant") == "rejection" else 0
             if comp["kind"] == "gauss":
                 H[m::M] = comp["H"]
                 W[m::M] = comp["width"]

@@ -46,7 +46,10 @@ typedef __int128 i128;
 #define ORC_EMAX 4096u /* event cap per particle-step (never reached at the configs) */
 
 enum { TAG_STEP = 0, TAG_REGEN = 1, TAG_INIT = 2, TAG_BOOT = 3, TAG_ROUND = 4,
-       TAG_CHILD = 5, TAG_GHOST = 6, TAG_HIST = 7 };
+       TAG_CHILD = 5, TAG_GHOST = 6, TAG_HIST = 7, TAG_REJECT = 8 };
+#define ORC_XI_N 4096      /* xi(r) grid intervals over r in [0, 8w] (Alg. 4 sampler) */
+#define ORC_XI_Q 8192      /* midpoint quadrature nodes over q in [-8/w, 8/w) */
+#define ORC_REJECT_MAX 256 /* proposals per kick before the pair is dropped */
 enum { KIND_GAUSS = 0, KIND_TABLE = 1 };
 enum { STRAT_SP1 = 0, STRAT_SP2 = 1 };
 
@@ -82,6 +85,9 @@ typedef struct {
      * the grid ([B][N_h] values of the Wigner function), sampled by Alg. 3 */
     int32_t init_kind, pad2;
     const double *init_hist;
+    /* kick sampler per component: 0 = majorant of Remark 3; 1 = Alg. 4
+     * (xi(x) on a grid with linear interpolation, rejection from V_W^+) */
+    int32_t sampler[ORC_MAXM];
 } orc_config;
 
 typedef struct {
@@ -319,6 +325,8 @@ typedef struct {
     double gamma0;
     int64_t N0;
     uint32_t key_inst;
+    double *xi_tab[ORC_MAXM];   /* Alg. 4 sampler: xi at r_j = j h, j = 0..ORC_XI_N */
+    double xi_h[ORC_MAXM];
     ens_t real, ghost;
     orc_stats st;
 } inst_t;
@@ -344,6 +352,37 @@ typedef struct {
 /* Pinned by tests/test_oracle_physics.py (pair rate against the closed-form */
 /* xi(x), the printed 1.5 xi_check = 0.8706, and the Ehrenfest drift).        */
 /* ------------------------------------------------------------------------ */
+/* xi(r) = (1/2) int |V_W(x, q)| dq for the Gaussian barrier (Sec. 4.2), on
+ * r_j = j h, h = 8w / ORC_XI_N, by the midpoint rule over q in [-8/w, 8/w)
+ * with ORC_XI_Q nodes; Alg. 4 then interpolates it linearly. */
+static void build_xi_table(inst_t *I, int m, double hbar)
+{
+    double w = I->width[m], H = fabs(I->H[m]);
+    double h = (8.0 * w) / (double)ORC_XI_N;
+    double qlo = -8.0 / w, dq = (16.0 / w) / (double)ORC_XI_Q;
+    double pref = ((H * w) * sqrt(2.0 * PI_D)) / (PI_D * hbar);   /* (1/2)(2/(pi hbar)) F[V] prefactor */
+    I->xi_h[m] = h;
+    I->xi_tab[m] = (double *)malloc((ORC_XI_N + 1) * sizeof(double));
+    for (int j = 0; j <= ORC_XI_N; j++) {
+        double r = (double)j * h, acc = 0.0;
+        for (int i = 0; i < ORC_XI_Q; i++) {
+            double q = qlo + ((double)i + 0.5) * dq;
+            acc += exp(-2.0 * ((w * w) * (q * q))) * fabs(sin(2.0 * q * r));
+        }
+        I->xi_tab[m][j] = (pref * acc) * dq;
+    }
+}
+
+/* linear interpolation of xi at distance |r| from the centre; constant beyond the grid */
+static double xi_interp(const inst_t *I, int m, double r)
+{
+    double a = fabs(r) / I->xi_h[m];
+    if (!(a < (double)ORC_XI_N)) return I->xi_tab[m][ORC_XI_N];
+    int j = (int)a;
+    double t = a - (double)j;
+    return I->xi_tab[m][j] + t * (I->xi_tab[m][j + 1] - I->xi_tab[m][j]);
+}
+
 static void setup_instance(orc_sim *S, int b)
 {
     const orc_config *C = &S->cfg;
@@ -370,6 +409,8 @@ static void setup_instance(orc_sim *S, int b)
     /* gamma0: given, else the smallest value with pair probability <= 1 */
     I->gamma0 = (C->gamma0 > 0.0) ? C->gamma0 : C->gamma_scale * (g / 2.0);
     for (int m = 0; m < C->M; m++) I->c[m] = I->xi[m] / (2.0 * I->gamma0);
+    for (int m = 0; m < C->M; m++)
+        if (C->sampler[m] == 1 && C->comp_kind[m] == KIND_GAUSS) build_xi_table(I, m, C->hbar);
     I->N0 = C->N0[b];
     I->key_inst = (uint32_t)(C->instance_offset + b);
     I->st.gamma0 = I->gamma0;
@@ -428,7 +469,11 @@ orc_sim *orc_create(const orc_config *cfg)
 void orc_destroy(orc_sim *S)
 {
     if (!S) return;
-    for (int b = 0; b < S->cfg.B; b++) { ens_free(&S->I[b].real); ens_free(&S->I[b].ghost); }
+    for (int b = 0; b < S->cfg.B; b++) {
+        ens_free(&S->I[b].real);
+        ens_free(&S->I[b].ghost);
+        for (int m = 0; m < ORC_MAXM; m++) free(S->I[b].xi_tab[m]);
+    }
     for (int m = 0; m < ORC_MAXM; m++) free(S->cum[m]);
     free(S->I);
     free(S);
@@ -516,6 +561,28 @@ static int in_kbox(const orc_sim *S, const double *k)
     return 1;
 }
 
+/* Alg. 4: a kick from V_W^+(x, .)/xi(x) by rejection.  Proposal q from the
+ * Gaussian g = G/xi_hat (Box-Muller), accepted iff u < [sgnV sin(2 q r)]^+.
+ * Proposal i of (particle, event e, component m) draws from tag 8 with event
+ * field e + 4096 i.  Returns 0 if ORC_REJECT_MAX proposals were rejected. */
+static int reject_kick(const orc_sim *S, const inst_t *I, uint64_t id, uint32_t e, int m,
+                       double r, double *q_out)
+{
+    const orc_config *C = &S->cfg;
+    double sgnV = I->H[m] >= 0.0 ? 1.0 : -1.0;
+    for (uint32_t i = 0; i < ORC_REJECT_MAX; i++) {
+        uint32_t ra[4], rb[4];
+        uint32_t ev = e + (i << 12);
+        rng4(C->seed, I->key_inst, id, S->step, TAG_REJECT, ev, (uint32_t)m, ra);
+        rng4(C->seed, I->key_inst, id, S->step, TAG_REJECT, ev, (uint32_t)(4 + m), rb);
+        double R = sqrt(-2.0 * orc_dlog(1.0 - orc_u01(ra[0], ra[1])));
+        double q = (R * orc_dcos(TWO_PI * orc_u01(ra[2], ra[3]))) * I->sq[m];
+        double p = sgnV * orc_dsin((2.0 * q) * r);
+        if (orc_u01(rb[0], rb[1]) < p) { *q_out = q; return 1; }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Alg. 1 for one particle over the rest of the current step, emitting its   */
 /* offspring (and theirs) in depth-first preorder: for each jump in time      */
@@ -548,12 +615,31 @@ static void walk(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth)
         for (int m = 0; m < C->M; m++) {
             jump_t J;
             double t_abs = (double)S->step * dt + te;
-            draw_jump(S, I, P->id, e, m, xe, u_acc0, t_abs, &J);
             double amp = 0.0;
-            if (!sp2) {
-                if (!(J.u_acc < J.c * fabs(J.sn))) continue;     /* sp1 box of Alg. 1 */
+            if (C->sampler[m] == 1) {
+                /* Alg. 1 sp1 box with Pr = xi(x)/gamma0 and Alg. 4 for the kick */
+                double r = comp_arg(S, m, xe, I->center[m]);
+                double u_acc = u_acc0;
+                if (m > 0) {
+                    uint32_t ra[4];
+                    rng4(C->seed, I->key_inst, P->id, S->step, TAG_STEP, e, (uint32_t)(8 + m), ra);
+                    u_acc = orc_u01(ra[0], ra[1]);
+                }
+                if (!(u_acc < xi_interp(I, m, r) / I->gamma0)) continue;
+                double qk;
+                if (!reject_kick(S, I, P->id, e, m, r, &qk)) continue;
+                J.q = qk;
+                J.arg = (2.0 * qk) * r;
+                J.sn = 1.0;
+                J.sigma = 1.0;
+                J.c = I->c[m];
             } else {
-                amp = P->w * (J.c * fabs(J.sn));                 /* wp/sp2 box of Alg. 1 */
+                draw_jump(S, I, P->id, e, m, xe, u_acc0, t_abs, &J);
+                if (!sp2) {
+                    if (!(J.u_acc < J.c * fabs(J.sn))) continue; /* sp1 box of Alg. 1 */
+                } else {
+                    amp = P->w * (J.c * fabs(J.sn));             /* wp/sp2 box of Alg. 1 */
+                }
             }
             double q = J.q, arg = J.arg, sn = J.sn, sigma = J.sigma;
             I->st.pairs++;

@@ -52,7 +52,8 @@ class Component(C.Structure):
                 ("H", C.POINTER(C.c_double)), ("width", C.POINTER(C.c_double)),
                 ("center_b", C.POINTER(C.c_double)),
                 ("mod_a", C.c_double), ("mod_b", C.c_double),
-                ("mod_omega", C.c_double), ("mod_phase", C.c_double)]
+                ("mod_omega", C.c_double), ("mod_phase", C.c_double),
+                ("sampler", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class Config(C.Structure):
@@ -161,6 +162,7 @@ def make_config(cfg):
         q = c.comp[m]
         q.kind = KERNEL[comp["kind"]]
         q.axis = int(comp["axis"])
+        q.sampler = 1 if comp.get("sampler", "majorant") == "rejection" else 0
         if comp["kind"] == "gauss":
             q.H, q.width, q.center_b = dptr(comp["H"]), dptr(comp["width"]), dptr(comp["center"])
             q.sign = 1.0

@@ -35,7 +35,7 @@ struct Layout {
            tileG = 0, tally = 0, ev_idx = 0, ev_x0 = 0, ev_x1 = 0, gev_idx = 0, gev_x0 = 0,
            gev_x1 = 0, stA = 0, stAg = 0, stB = 0, stBg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
-           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0;
+           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0, xitab = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
     int64_t tilesA = 0, tilesAg = 0, tilesB = 0, tilesBg = 0, tilesS = 0, tilesP = 0;
 };
@@ -68,6 +68,9 @@ int validate(const wbrw_config *c)
     }
     for (int m = 0; m < c->n_components; ++m) {
         const wbrw_component &q = c->comp[m];
+        if (q.sampler != 0 && (q.sampler != 1 || q.kind != WBRW_KERNEL_GAUSSIAN ||
+                               c->strategy != WBRW_SP1 || q.modulated || c->track_tangent))
+            return WBRW_EINVAL;
         if (!q.modulated) continue;
         if (q.kind != WBRW_KERNEL_GAUSSIAN || !std::isfinite(q.mod_a) || !std::isfinite(q.mod_b) ||
             !std::isfinite(q.mod_omega) || !std::isfinite(q.mod_phase))
@@ -159,6 +162,9 @@ Layout make_layout(const wbrw_config *c)
         if (c->comp[m].kind == WBRW_KERNEL_TABLE) L.tab[m] = take(cur, ((size_t)c->comp[m].table_n + 1) * 8);
     L.off = take(cur, BB * Nh * 8);
     if (c->init_hist) L.hist = take(cur, BB * Nh * 8);
+    bool alg4 = false;
+    for (int m = 0; m < c->n_components; ++m) alg4 = alg4 || c->comp[m].sampler == 1;
+    if (alg4) L.xitab = take(cur, BB * (size_t)c->n_components * (kXiN + 1) * 8);
     if (sp2) {
         L.bA = take(cur, C * 8);
         L.bcopies = take(cur, C * 4);
@@ -252,6 +258,26 @@ int persistent_blocks(K kernel, int cus)
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) != hipSuccess || per < 1) per = 1;
     return per * cus;
+}
+
+// Alg. 4 sampler: xi(r) = (1/2) int |V_W| dq for the Gaussian barrier on
+// r_j = j h, h = 8w / kXiN, by the midpoint rule over q in [-8/w, 8/w).
+void xi_table(double H, double w, double hbar, double *tab, double &h_out)
+{
+    const double pi = 0x1.921fb54442d18p+1;
+    const double h = (8.0 * w) / (double)kXiN;
+    const double qlo = -8.0 / w, dq = (16.0 / w) / (double)kXiQ;
+    const double pref = ((std::fabs(H) * w) * std::sqrt(2.0 * pi)) / (pi * hbar);
+    for (int j = 0; j <= kXiN; ++j) {
+        const double r = (double)j * h;
+        double acc = 0.0;
+        for (int i = 0; i < kXiQ; ++i) {
+            const double q = qlo + ((double)i + 0.5) * dq;
+            acc += std::exp(-2.0 * ((w * w) * (q * q))) * std::fabs(std::sin(2.0 * q * r));
+        }
+        tab[j] = (pref * acc) * dq;
+    }
+    h_out = h;
 }
 
 // derived per-instance constants (Remark 3: xi_m and the pair probability)
@@ -527,6 +553,7 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         const wbrw_component &q = cfg->comp[m];
         d.kind[m] = q.kind;
         d.axis[m] = q.axis;
+        d.sampler[m] = q.sampler;
         if (q.kind != WBRW_KERNEL_TABLE) continue;
         std::vector<double> &cm = cums[m];
         cm.resize((size_t)q.table_n + 1);
@@ -572,6 +599,16 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
             G.id = at<uint64_t>(w, L.gens[s][6]);
             G.D = at<double>(w, L.gens[s][7]);
         }
+    }
+    std::vector<double> xitabs;
+    if (L.xitab) {
+        xitabs.assign((size_t)h->B * h->M * (kXiN + 1), 0.0);
+        for (int b = 0; b < h->B; ++b)
+            for (int m = 0; m < h->M; ++m)
+                if (cfg->comp[m].sampler == 1)
+                    xi_table(cfg->comp[m].H[b], cfg->comp[m].width[b], cfg->hbar,
+                             &xitabs[((size_t)b * h->M + m) * (kXiN + 1)], h->ip[b].xi_h[m]);
+        d.xi_tab = at<double>(w, L.xitab);
     }
     d.ip = at<InstParam>(w, L.ip);
     d.ctl = at<Ctl>(w, L.ctl);
@@ -639,6 +676,9 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         if (hipMemcpyAsync(d.tileA + h->B + 1, gplan.data(), 8 * (h->B + 1), hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(WBRW_EHIP);
     }
+    if (L.xitab &&
+        hipMemcpyAsync((void *)d.xi_tab, xitabs.data(), 8 * xitabs.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(WBRW_EHIP);
     for (int m = 0; m < h->M; ++m)
         if (cfg->comp[m].kind == WBRW_KERNEL_TABLE &&
             hipMemcpyAsync((void *)d.tab[m].cum, cums[m].data(), 8 * cums[m].size(), hipMemcpyHostToDevice, s) != hipSuccess)

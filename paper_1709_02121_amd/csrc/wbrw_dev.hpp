@@ -21,6 +21,9 @@ constexpr int kTileS = kThreads * kPPT; // cells per scan tile
 constexpr int kTileR = kThreads * 4;    // regenerated particles per tile
 constexpr int kMaxDepth = 16;           // deepest family tree walked within one step
 constexpr uint32_t kEventCap = 4096u;   // jumps per particle-step
+constexpr int kXiN = 4096;              // xi(r) grid intervals (Alg. 4 sampler)
+constexpr int kXiQ = 8192;              // quadrature nodes for xi(r)
+constexpr uint32_t kRejectMax = 256u;   // rejection proposals per kick
 
 enum : uint32_t { kErrCapacity = 1u, kErrDepth = 2u };
 
@@ -44,6 +47,7 @@ struct InstParam {
     double H[kMaxM], width[kMaxM];  // Gaussian parameters (tangent scores)
     double center[kMaxM];           // centre of the kernel phase
     double sgnV[kMaxM];             // sign of F[V_m]
+    double xi_h[kMaxM];             // Alg. 4 sampler: xi grid spacing in |x - x0|
     double ma[kMaxM], mb[kMaxM];    // time-varying height factor a + b cos(omega t + phase)
     double mw[kMaxM], mp[kMaxM];
     int64_t base, cap;              // particle segment
@@ -90,7 +94,8 @@ struct Dev {
     int64_t cap_total, gcap_total;
     double dt, vfac;
     double x_lo, x_hi, k_lo, k_hi, dx, dk;
-    int32_t kind[kMaxM], axis[kMaxM];
+    int32_t kind[kMaxM], axis[kMaxM], sampler[kMaxM];
+    const double *xi_tab;       // [B][M][kXiN + 1] xi(r) tables of the Alg. 4 sampler
     Table tab[kMaxM];
     // buffers
     Ens ens[2], gens[2];

@@ -56,6 +56,34 @@ __device__ __forceinline__ double kick_sample(const Dev &d, const InstParam &P, 
     return T.q_lo + ((double)lo + u2) * T.dq;
 }
 
+// Alg. 4: xi(|r|) by linear interpolation on its grid (constant beyond it)
+__device__ __forceinline__ double xi_lerp(const double *tab, double h, double r)
+{
+    const double a = fabs(r) / h;
+    if (!(a < (double)kXiN)) return tab[kXiN];
+    const int j = (int)a;
+    const double t = a - (double)j;
+    return tab[j] + t * (tab[j + 1] - tab[j]);
+}
+
+// Alg. 4: kick from V_W^+(x, .)/xi(x) by rejection (proposal from the Gaussian
+// majorant, accept iff u < [sgnV sin(2 q r)]^+); false if every proposal failed.
+__device__ __forceinline__ bool reject_kick(const Dev &d, const InstParam &P, uint64_t id,
+                                            uint32_t step, uint32_t e, int m, double r, double &q_out)
+{
+    const double sgv = P.H[m] >= 0.0 ? 1.0 : -1.0;
+    for (uint32_t i = 0; i < kRejectMax; ++i) {
+        const uint32_t ev = e + (i << 12);
+        const W4 a = draw(id, step, kTagReject, ev, (uint32_t)m, d.seed, P.key);
+        const W4 b = draw(id, step, kTagReject, ev, (uint32_t)(4 + m), d.seed, P.key);
+        const double R = sqrt(-2.0 * ln_series(1.0 - unit53(a.a, a.b)));
+        const double q = (R * cos_det(kTwoPi * unit53(a.c, a.d))) * P.sq[m];
+        const double p = sgv * sin_det((2.0 * q) * r);
+        if (unit53(b.a, b.b) < p) { q_out = q; return true; }
+    }
+    return false;
+}
+
 template <int DIM>
 __device__ __forceinline__ bool in_kbox(const Dev &d, const double *k)
 {
@@ -281,11 +309,34 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
             continue;
         }
         const int m = cur.m;
-        const W4 rq = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(1 + m), seed, key);
-        const double q = kick_sample(d, P, m, unit53(rq.a, rq.b), unit53(rq.c, rq.d));
-        const double arg = (2.0 * q) * phase_offset(d, m, cur.xe, P.center[m]);
-        const double sn = sin_det(arg);
-        double cm = P.c[m], sgv = P.sgnV[m];
+        double q, arg, sn, cm = P.c[m], sgv = P.sgnV[m];
+        bool alg4 = false;
+        if (d.sampler[m] == 1) {
+            // Alg. 1 sp1 box with Pr = xi(x)/gamma0, kick by Alg. 4
+            const double r = phase_offset(d, m, cur.xe, P.center[m]);
+            double ua = cur.ua0;
+            if (m > 0) {
+                const W4 ra = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(8 + m), seed, key);
+                ua = unit53(ra.a, ra.b);
+            }
+            const double *tab = d.xi_tab + ((int64_t)(&P - d.ip) * d.M + m) * (kXiN + 1);
+            double qk = 0.0;
+            if (!(ua < xi_lerp(tab, P.xi_h[m], r) / P.gamma0) || !reject_kick(d, P, cur.id, step, cur.e, m, r, qk)) {
+                cur.m += 1;
+                cur.side = 0;
+                continue;
+            }
+            q = qk;
+            arg = (2.0 * qk) * r;
+            sn = 1.0;
+            sgv = 1.0;
+            alg4 = true;
+        } else {
+            const W4 rq = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(1 + m), seed, key);
+            q = kick_sample(d, P, m, unit53(rq.a, rq.b), unit53(rq.c, rq.d));
+            arg = (2.0 * q) * phase_offset(d, m, cur.xe, P.center[m]);
+            sn = sin_det(arg);
+        }
         if (d.tdep && d.kind[m] == 0) {        // Remark 1: kernel at the absolute jump time
             const double tabs = (double)step * d.dt + cur.te;
             const double f = P.ma[m] + P.mb[m] * cos_det(P.mw[m] * tabs + P.mp[m]);
@@ -295,7 +346,7 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
         }
         const double sigma = (sn > 0.0) ? sgv : -sgv;
         double amp = 0.0;
-        if (!SP2) {
+        if (!SP2 && !alg4) {
             double ua = cur.ua0;
             if (m > 0) {
                 const W4 ra = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(8 + m), seed, key);
@@ -306,7 +357,7 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
                 cur.side = 0;
                 continue;
             }
-        } else {
+        } else if (SP2) {
             amp = cur.w * (cm * fabs(sn));
         }
         const int side = cur.side;

@@ -307,3 +307,16 @@ def test_signed_histogram_init_parity(P, O):
     r.run(20, 10)
     say(f"cat state: n={r.count()}")
     compare(g, r, "histogram init + steps")
+
+
+def test_alg4_rejection_sampler_parity(P, O):
+    """Alg. 4 kick sampler (xi(x) table + rejection): same tables, loops and bits."""
+    cfg = W.gaussian_barrier_small(N0=np.array([6000]))
+    cfg["init"] = dict(cfg["init"], mean_x=[-4.0, 0.0])
+    cfg["components"][0]["sampler"] = "rejection"
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.run(30, 10)
+    r.run(30, 10)
+    say(f"alg4: n={r.count()} pairs={r.stats()['pairs']}")
+    compare(g, r, "alg4 sampler")
+    assert np.array_equal(g.density().cpu().numpy(), r.density())

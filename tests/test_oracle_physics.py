@@ -36,11 +36,12 @@ def xi_closed_form(x, H, w, x0, hbar=1.0, nterms=200):
     return (H / hbar) * (2 / np.pi - (4 / np.pi) * np.sum(np.exp(-2 * n * n * r * r / (w * w)) / (4 * n * n - 1)))
 
 
-def static_cfg(H=0.3, w=1.0, x0=0.0, hbar=1.0, dt=1.0, gamma0=0.0):
+def static_cfg(H=0.3, w=1.0, x0=0.0, hbar=1.0, dt=1.0, gamma0=0.0, sampler="majorant"):
     """Workload whose k-box is so thin that every offspring is removed, so the
     pairs tally counts first-generation pairs of static (k = 0) parents."""
     cfg = W.gaussian_barrier_small(N0=np.array([1]), dt=dt, hbar=hbar, gamma0=gamma0)
     cfg = W.with_theta(cfg, H=H, width=w, center=x0)
+    cfg["components"][0]["sampler"] = sampler
     cfg["grid"] = {"x_lo": -1000.0, "x_hi": 1000.0, "nx": 10, "k_lo": -1e-9, "k_hi": 1e-9, "nk": 1}
     return cfg
 
@@ -54,10 +55,14 @@ def pairs_of_static_parents(O, cfg, x, n):
     return st["pairs"]
 
 
+@pytest.mark.parametrize("sampler", ["majorant", "rejection"])
 @pytest.mark.parametrize("x", [0.1, 0.4, 1.0, 2.5])
-def test_pair_rate_matches_closed_form_xi(oracle_mod, x):
+def test_pair_rate_matches_closed_form_xi(oracle_mod, x, sampler):
+    """Majorant sampler: probability xi_hat |sin| / (2 gamma0) per jump; Alg. 4
+    sampler: xi(x)/gamma0 from the interpolated quadrature table and a kick by
+    rejection.  Both must give the rate xi(x)."""
     n, T = 200_000, 1.0
-    pairs = pairs_of_static_parents(oracle_mod, static_cfg(dt=T), x, n)
+    pairs = pairs_of_static_parents(oracle_mod, static_cfg(dt=T, sampler=sampler), x, n)
     expect = n * T * xi_closed_form(x, 0.3, 1.0, 0.0)
     assert abs(pairs - expect) < 4.5 * np.sqrt(expect) + 1, (pairs, expect)
 
@@ -195,10 +200,12 @@ def _schroedinger_density(T, H=0.3, w=1.0, x0=0.0, L=400.0, n=16384, dts=0.005):
     return x, np.abs(psi) ** 2
 
 
-def test_density_matches_schroedinger(oracle_mod):
+@pytest.mark.parametrize("sampler", ["majorant", "rejection"])
+def test_density_matches_schroedinger(oracle_mod, sampler):
     x, rho = _schroedinger_density(20.0)
     dx = x[1] - x[0]
     cfg = W.gaussian_barrier_small(N0=np.array([100_000]), seed=1)
+    cfg["components"][0]["sampler"] = sampler
     s = oracle_mod.OracleSim(cfg)
     s.run(200, 10)
     d = s.density()[0]
