@@ -337,7 +337,7 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
             arg = (2.0 * q) * phase_offset(d, m, cur.xe, P.center[m]);
             sn = sin_det(arg);
         }
-        if (d.tdep && d.kind[m] == 0) {        // Remark 1: kernel at the absolute jump time
+        if (d.tdep && d.kind[m] == 0 && !alg4) {   // Remark 1: kernel at the absolute jump time
             const double tabs = (double)step * d.dt + cur.te;
             const double f = P.ma[m] + P.mb[m] * cos_det(P.mw[m] * tabs + P.mp[m]);
             const double He = P.H[m] * f;
