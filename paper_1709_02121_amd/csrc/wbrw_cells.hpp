@@ -20,6 +20,30 @@
 
 namespace wbrw {
 
+// Run aggregation over a wavefront: lanes hold consecutive elements, and a
+// run is a maximal group of consecutive lanes with equal key.  On return the
+// last lane of each run holds in v the sum of its run and gets true; keys < 0
+// never commit.  Must be called by all 64 lanes.
+template <typename T>
+__device__ __forceinline__ T run_sum(int64_t key, T v, bool &commit)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t kprev = __shfl_up(key, 1, 64);
+    const int64_t knext = __shfl_down(key, 1, 64);
+    const bool head = lane == 0 || kprev != key;
+    const bool tail = lane == 63 || knext != key;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int start = 63 - __builtin_clzll(heads & upto);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T u = __shfl_up(v, o, 64);
+        if (lane - o >= start) v += u;
+    }
+    commit = tail && key >= 0;
+    return v;
+}
+
 constexpr int64_t kOffMask = (1ll << 62) - 1;
 constexpr int64_t kOffNeg = 1ll << 62;
 
@@ -176,20 +200,34 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
         }
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
+            // lanes hold consecutive particles, which after an annihilation
+            // are in cell order: sum equal-cell runs in registers, then one
+            // atomic per run
             const int64_t li = li0 + (int64_t)j * kThreads;
-            if (li >= n) continue;
-            const int64_t i = base + li;
-            const int64_t nu = cell_index<DIM>(d, xa[j], xb[j], ka[j], kb[j]);
-            const int s = sv[j];
-            if (nu < 0) { esc += s; continue; }
-            if (!ghost) atomicAdd(&d.cnt[cbase + nu], s);
+            const bool live = li < n;
+            const int64_t i = base + (live ? li : 0);
+            const int64_t nu = live ? cell_index<DIM>(d, xa[j], xb[j], ka[j], kb[j]) : -1;
+            const int s = live ? sv[j] : 0;
+            if (live && nu < 0) esc += s;
+            bool commit;
+            if (!ghost) {
+                const int ns = run_sum<int>(nu, nu >= 0 ? s : 0, commit);
+                if (commit && ns != 0) atomicAdd(&d.cnt[cbase + nu], ns);
+            }
             if (TAN) {
-                atomicAdd(&d.occ[cbase + nu], 1);
-                const int64_t nc = d.Nh * (int64_t)B;
+                const bool in = nu >= 0;
                 const int64_t ds = ghost ? d.gcap_total : d.cap_total;
-                atomicAdd(&d.Tcell[cbase + nu], E.D[i]);
-                atomicAdd(&d.Tcell[nc + cbase + nu], E.D[ds + i]);
-                atomicAdd(&d.Tcell[2 * nc + cbase + nu], E.D[2 * ds + i]);
+                const int no = run_sum<int>(nu, in ? 1 : 0, commit);
+                const double t0 = run_sum<double>(nu, in ? E.D[i] : 0.0, commit);
+                const double t1 = run_sum<double>(nu, in ? E.D[ds + i] : 0.0, commit);
+                const double t2 = run_sum<double>(nu, in ? E.D[2 * ds + i] : 0.0, commit);
+                if (commit) {
+                    const int64_t nc = d.Nh * (int64_t)B;
+                    atomicAdd(&d.occ[cbase + nu], no);
+                    atomicAdd(&d.Tcell[cbase + nu], t0);
+                    atomicAdd(&d.Tcell[nc + cbase + nu], t1);
+                    atomicAdd(&d.Tcell[2 * nc + cbase + nu], t2);
+                }
             }
         }
         if (esc) atomicAdd((unsigned long long *)&s_esc, (unsigned long long)esc);
@@ -248,17 +286,12 @@ __global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
         __syncthreads();
         uint32_t woff = 0, agg = 0;
         for (int q = 0; q < 4; ++q) { if (q < wv) woff += s_wsum[q]; agg += s_wsum[q]; }
-        if (tid == 0) {
-            uint32_t excl = 0;
-            if (tl == 0) {
-                lb_publish(d.stS + t, epoch, 2u, agg);
-            } else {
-                lb_publish(d.stS + t, epoch, 1u, agg);
-                excl = lb_lookback(d.stS, t, (int64_t)b * tiles_per, epoch);
-                lb_publish(d.stS + t, epoch, 2u, excl + agg);
+        if (wv == 0) {
+            const uint32_t excl = tile_prefix(d.stS, t, (int64_t)b * tiles_per, epoch, agg);
+            if (lane == 0) {
+                if (tl == tiles_per - 1) d.Nnew[b] = (int64_t)(excl + agg);
+                s_excl = excl;
             }
-            if (tl == tiles_per - 1) d.Nnew[b] = (int64_t)(excl + agg);
-            s_excl = excl;
         }
         __syncthreads();
         int64_t run = (int64_t)s_excl + (int64_t)(woff + incl - sum);
@@ -367,7 +400,15 @@ template <int DIM, bool SP2, bool TAN>
 __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int axis, int nbins,
                                                           double lo, double dxb)
 {
+    // Each block keeps a private histogram of the instance it is working on
+    // in LDS and adds its non-zero bins to the global accumulator when its
+    // tiles move on to the next instance and when it runs out of tiles.
+    // Integer weights (signs, 32.32 fixed-point weights) sum exactly in any
+    // order.  Histograms wider than the LDS array go straight to HBM.
+    constexpr int kLds = 4096;
     __shared__ int64_t s_t;
+    __shared__ uint64_t s_raw[kLds];
+    double *s_d = reinterpret_cast<double *>(s_raw);
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
@@ -375,7 +416,29 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
     const int64_t *Ncur = ghost ? d.NG : d.N;
     const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
     const double *X = (axis == 1) ? E.x1 : E.x0;
+    const int64_t ds = ghost ? d.gcap_total : d.cap_total;
     const int tid = threadIdx.x;
+    const int width = TAN ? 3 * nbins : nbins;
+    const bool priv = width <= kLds;
+    if (priv)
+        for (int j = tid; j < width; j += kThreads) s_raw[j] = 0ull;
+    int cb = -1;
+    auto flush = [&](int fb) {
+        __syncthreads();
+        for (int j = tid; j < width; j += kThreads) {
+            const uint64_t v = s_raw[j];
+            if (v == 0ull) continue;
+            const double f = s_d[j];
+            s_raw[j] = 0ull;
+            if (TAN) {
+                const int c = j / nbins, bin = j - c * nbins;
+                atomicAdd(d.dTacc + (int64_t)fb * 3 * d.max_bins + (int64_t)c * d.max_bins + bin, f);
+            } else {
+                atomicAdd((unsigned long long *)&d.dacc[(int64_t)fb * d.max_bins + j], (unsigned long long)v);
+            }
+        }
+        __syncthreads();
+    };
     for (;;) {
         if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
         __syncthreads();
@@ -383,6 +446,10 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
         __syncthreads();
         if (t >= ntiles) break;
         const int b = segment_of(plan, B, t);
+        if (priv && b != cb) {
+            if (cb >= 0) flush(cb);
+            cb = b;
+        }
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t n = Ncur[b];
@@ -398,25 +465,41 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const int64_t li = li0 + (int64_t)j * kThreads;
-            if (li >= n) continue;
-            const int64_t i = base + li;
+            const bool live = li < n;
+            const int64_t i = base + (live ? li : 0);
             const double q = (xv[j] - lo) / dxb;
-            if (!(q >= 0.0 && q < (double)nbins)) continue;
-            const int64_t bin = (int64_t)q;
+            const int64_t bin = (live && q >= 0.0 && q < (double)nbins) ? (int64_t)q : -1;
+            bool commit;
             if (TAN) {
-                double *acc = d.dTacc + (int64_t)b * 3 * d.max_bins;
-                const int64_t ds = ghost ? d.gcap_total : d.cap_total;
-                atomicAdd(&acc[bin], E.D[i]);
-                atomicAdd(&acc[d.max_bins + bin], E.D[ds + i]);
-                atomicAdd(&acc[2 * d.max_bins + bin], E.D[2 * ds + i]);
+                const bool in = bin >= 0;
+                const double t0 = run_sum<double>(bin, in ? E.D[i] : 0.0, commit);
+                const double t1 = run_sum<double>(bin, in ? E.D[ds + i] : 0.0, commit);
+                const double t2 = run_sum<double>(bin, in ? E.D[2 * ds + i] : 0.0, commit);
+                if (!commit) continue;
+                if (priv) {
+                    atomicAdd(&s_d[bin], t0);
+                    atomicAdd(&s_d[nbins + bin], t1);
+                    atomicAdd(&s_d[2 * nbins + bin], t2);
+                } else {
+                    double *acc = d.dTacc + (int64_t)b * 3 * d.max_bins;
+                    atomicAdd(&acc[bin], t0);
+                    atomicAdd(&acc[d.max_bins + bin], t1);
+                    atomicAdd(&acc[2 * d.max_bins + bin], t2);
+                }
             } else {
-                int64_t v;
-                if (SP2) v = (int64_t)(wv[j] * 4294967296.0); else v = (int64_t)wv[j];
-                atomicAdd((unsigned long long *)&d.dacc[(int64_t)b * d.max_bins + bin],
-                          (unsigned long long)v);
+                int64_t v = 0;
+                if (bin >= 0) v = SP2 ? (int64_t)(wv[j] * 4294967296.0) : (int64_t)wv[j];
+                v = run_sum<int64_t>(bin, v, commit);
+                if (!commit || v == 0) continue;
+                if (priv)
+                    atomicAdd((unsigned long long *)&s_raw[bin], (unsigned long long)v);
+                else
+                    atomicAdd((unsigned long long *)&d.dacc[(int64_t)b * d.max_bins + bin],
+                              (unsigned long long)v);
             }
         }
     }
+    if (priv && cb >= 0) flush(cb);
     if (last_block_done(&ctl->done[kPassTiles])) {
         if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
     }

@@ -180,6 +180,54 @@ __device__ __forceinline__ uint32_t lb_lookback(uint64_t *st, int64_t t, int64_t
     return excl;
 }
 
+// Wave-parallel look-back: the 64 lanes of one wavefront examine 64
+// predecessors per round, wait until each has published, and sum back to the
+// nearest inclusive prefix.  Returns the exclusive prefix to every lane.
+__device__ __forceinline__ uint32_t lb_lookback_wave(uint64_t *st, int64_t t, int64_t first, uint32_t epoch)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t excl = 0;
+    for (int64_t top = t - 1; top >= first; top -= 64) {
+        const int64_t p = top - lane;
+        uint32_t flag = 2u, val = 0u;   // lanes past the segment start act as a zero prefix
+        if (p >= first) {
+            for (;;) {
+                const uint64_t w = __hip_atomic_load(st + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t hi = (uint32_t)(w >> 32);
+                if ((hi >> 2) == epoch && (hi & 3u) != 0u) {
+                    flag = hi & 3u;
+                    val = (uint32_t)w;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        const uint64_t incl = __ballot(flag == 2u);
+        const int stop = incl ? (__ffsll((unsigned long long)incl) - 1) : 64;
+        uint32_t v = lane <= stop ? val : 0u;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        excl += v;
+        if (incl) break;
+    }
+    return excl;
+}
+
+// Publishes tile t's aggregate, looks back over its segment [first, t) and
+// publishes its inclusive prefix.  Called by all lanes of wavefront 0.
+__device__ __forceinline__ uint32_t tile_prefix(uint64_t *st, int64_t t, int64_t first, uint32_t epoch,
+                                                uint32_t agg)
+{
+    const int lane = threadIdx.x & 63;
+    if (t == first) {
+        if (lane == 0) lb_publish(st + t, epoch, 2u, agg);
+        return 0u;
+    }
+    if (lane == 0) lb_publish(st + t, epoch, 1u, agg);
+    const uint32_t excl = lb_lookback_wave(st, t, first, epoch);
+    if (lane == 0) lb_publish(st + t, epoch, 2u, excl + agg);
+    return excl;
+}
+
 // The calling block is the last of the grid to finish (all other blocks'
 // global writes are visible afterwards).  Must be called by every thread.
 __device__ __forceinline__ bool last_block_done(uint32_t *done_ctr)

@@ -498,17 +498,12 @@ __global__ __launch_bounds__(kThreads) void k_ghosts(Dev d)
         __syncthreads();
         uint32_t woff = 0, agg = 0;
         for (int q = 0; q < 4; ++q) { if (q < wv) woff += s_wsum[q]; agg += s_wsum[q]; }
-        if (tid == 0) {
-            uint32_t excl = 0;
-            if (tl == 0) {
-                lb_publish(d.stG + t, epoch, 2u, agg);
-            } else {
-                lb_publish(d.stG + t, epoch, 1u, agg);
-                excl = lb_lookback(d.stG, t, (int64_t)b * tiles_per, epoch);
-                lb_publish(d.stG + t, epoch, 2u, excl + agg);
+        if (wv == 0) {
+            const uint32_t excl = tile_prefix(d.stG, t, (int64_t)b * tiles_per, epoch, agg);
+            if (lane == 0) {
+                if (tl == tiles_per - 1) d.NGnew[b] = (int64_t)(excl + agg);
+                s_excl = excl;
             }
-            if (tl == tiles_per - 1) d.NGnew[b] = (int64_t)(excl + agg);
-            s_excl = excl;
         }
         __syncthreads();
         int64_t gi = (int64_t)s_excl + (int64_t)(woff + incl - sum);

@@ -192,19 +192,16 @@ __global__ __launch_bounds__(kThreads) void k_stream(Dev d, int ghost)
             }
         }
         __syncthreads();
-        if (tid == 0) {
+        if (wv == 0) {
             uint32_t acc = 0;
-            for (int q = 0; q < kPPT * 4; ++q) { s_woff[q] = acc; acc += s_wcnt[q]; }
-            uint32_t excl = 0;
-            if (tl == 0) {
-                lb_publish(st + t, epoch, 2u, acc);
-            } else {
-                lb_publish(st + t, epoch, 1u, acc);
-                excl = lb_lookback(st, t, first, epoch);
-                lb_publish(st + t, epoch, 2u, excl + acc);
+            if (lane == 0)
+                for (int q = 0; q < kPPT * 4; ++q) { s_woff[q] = acc; acc += s_wcnt[q]; }
+            acc = __shfl(acc, 0, 64);
+            const uint32_t excl = tile_prefix(st, t, first, epoch, acc);
+            if (lane == 0) {
+                if (t == last) d.evc[(int64_t)ghost * B + b] = (int64_t)(excl + acc);
+                s_excl = excl;
             }
-            if (t == last) d.evc[(int64_t)ghost * B + b] = (int64_t)(excl + acc);
-            s_excl = excl;
         }
         __syncthreads();
         const uint32_t ex = s_excl;
@@ -533,17 +530,12 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advan
             if (q < wv) woff += s_wsum[q];
             agg += s_wsum[q];
         }
-        if (tid == 0) {
-            uint32_t excl = 0;
-            if (tl_i == 0) {
-                lb_publish(st + t, epoch, 2u, agg);
-            } else {
-                lb_publish(st + t, epoch, 1u, agg);
-                excl = lb_lookback(st, t, first, epoch);
-                lb_publish(st + t, epoch, 2u, excl + agg);
+        if (wv == 0) {
+            const uint32_t excl = tile_prefix(st, t, first, epoch, agg);
+            if (lane == 0) {
+                if (t == last) d.chc[(int64_t)ghost * B + b] = (int64_t)(excl + agg);
+                s_excl = excl;
             }
-            if (t == last) d.chc[(int64_t)ghost * B + b] = (int64_t)(excl + agg);
-            s_excl = excl;
         }
         __syncthreads();
         const int64_t my_first = n_before + (int64_t)s_excl + (int64_t)(woff + incl - cnt);

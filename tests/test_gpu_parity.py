@@ -265,7 +265,8 @@ def test_snapshot_restore_continues_exactly(P, O):
     for ghost in (False, True):
         pa, pb = a.particles(ghost=ghost), b.particles(ghost=ghost)
         assert_same_ensemble(pa, pb, what=f"restore ghost={ghost}")
-        assert np.array_equal(pa["D"], pb["D"]) or np.allclose(pa["D"], pb["D"], rtol=1e-12, atol=0)
+        # tangents are summed per cell with floating atomics: equal to rounding
+        _close(pa["D"], pb["D"], f"restore tangents ghost={ghost}")
     r = O.OracleSim(cfg)
     r.run(30, 10)
     compare(b, r, "restore vs oracle")
@@ -290,6 +291,8 @@ def test_autotune_keeps_results(P, O):
 def test_time_dependent_potential_parity(P, O, strategy):
     """Remark 1: kernel evaluated at the absolute jump time (switching left barrier)."""
     cfg = W.time_dependent_barriers(N0=np.array([5000]), strategy=strategy)
+    # weighted pairs at every jump: 2M gamma0 = 4 growth rate, ~e^4 per epoch
+    cfg["capacity_factor"] = 8.0 if strategy == "sp1" else 200.0
     g, r = P.Simulation(cfg), O.OracleSim(cfg)
     g.run(60, 10)
     r.run(60, 10)
