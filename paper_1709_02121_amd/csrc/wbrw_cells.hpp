@@ -2,9 +2,10 @@
 //
 // Annihilation (Sec. 4.3, Eq. signed_histogram; Alg. 3 step 3):
 //   k_bin     one pass over the particles: cell index on the uniform grid
-//             D_nu = X_nu1 x K_nu2 (escaped sign tallied), integer atomic add of
-//             the sign into the instance's count grid: the per-cell sums
-//             n_nu^+ - n_nu^- are exact and order independent;
+//             D_nu = X_nu1 x K_nu2 (escaped sign tallied), signs summed per
+//             cell in LDS per tile, then integer atomic adds into the
+//             instance's count grid: the per-cell sums n_nu^+ - n_nu^- are
+//             exact and order independent;
 //   k_scan    ordered exclusive scan of |n_nu| per instance (decoupled
 //             look-back), which is also the output layout: ascending cell,
 //             then index within the cell;
@@ -165,8 +166,17 @@ __global__ __launch_bounds__(kThreads) void k_hist_round(Dev d, const double *hi
 template <int DIM, bool TAN>
 __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
 {
+    // Without tangents the signs of a tile are first summed per cell in an
+    // LDS hash table (open addressing on the cell index, 8 probes), and each
+    // distinct cell of the tile costs one global atomic.  A cell-ordered
+    // ensemble straddles cell boundaries after a few steps of drift, so
+    // equal cells are close in the array but not adjacent; the table finds
+    // them anyway.  A particle whose probes all fail adds directly.
+    constexpr int kSlots = 4096;
     __shared__ int64_t s_t;
     __shared__ int64_t s_esc;
+    __shared__ int32_t s_key[TAN ? 1 : kSlots];
+    __shared__ int32_t s_val[TAN ? 1 : kSlots];
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
@@ -174,6 +184,8 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     const int64_t *Ncur = ghost ? d.NG : d.N;
     const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
     const int tid = threadIdx.x;
+    if (!TAN)
+        for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
     for (;;) {
         if (tid == 0) { s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u); s_esc = 0; }
         __syncthreads();
@@ -200,21 +212,35 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
         }
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            // lanes hold consecutive particles, which after an annihilation
-            // are in cell order: sum equal-cell runs in registers, then one
-            // atomic per run
             const int64_t li = li0 + (int64_t)j * kThreads;
             const bool live = li < n;
             const int64_t i = base + (live ? li : 0);
             const int64_t nu = live ? cell_index<DIM>(d, xa[j], xb[j], ka[j], kb[j]) : -1;
             const int s = live ? sv[j] : 0;
             if (live && nu < 0) esc += s;
-            bool commit;
-            if (!ghost) {
-                const int ns = run_sum<int>(nu, nu >= 0 ? s : 0, commit);
-                if (commit && ns != 0) atomicAdd(&d.cnt[cbase + nu], ns);
-            }
-            if (TAN) {
+            if (!TAN) {
+                if (nu < 0 || s == 0) continue;
+                const int key = (int)nu;
+                const uint32_t h = ((uint32_t)key * 2654435761u) >> 20;
+                bool done = false;
+                for (int pr = 0; pr < 8 && !done; ++pr) {
+                    const int slot = (int)((h + (uint32_t)pr) & (uint32_t)(kSlots - 1));
+                    int k = __hip_atomic_load(&s_key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (k == -1) k = atomicCAS(&s_key[slot], -1, key);
+                    if (k == -1 || k == key) {
+                        atomicAdd(&s_val[slot], s);
+                        done = true;
+                    }
+                }
+                if (!done) atomicAdd(&d.cnt[cbase + nu], s);
+            } else {
+                // lanes hold consecutive particles: sum equal-cell runs in
+                // registers, then one atomic per run
+                bool commit;
+                if (!ghost) {
+                    const int ns = run_sum<int>(nu, nu >= 0 ? s : 0, commit);
+                    if (commit && ns != 0) atomicAdd(&d.cnt[cbase + nu], ns);
+                }
                 const bool in = nu >= 0;
                 const int64_t ds = ghost ? d.gcap_total : d.cap_total;
                 const int no = run_sum<int>(nu, in ? 1 : 0, commit);
@@ -232,6 +258,16 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
         }
         if (esc) atomicAdd((unsigned long long *)&s_esc, (unsigned long long)esc);
         __syncthreads();
+        if (!TAN) {
+            for (int j = tid; j < kSlots; j += kThreads) {
+                const int k = s_key[j];
+                if (k < 0) continue;
+                const int v = s_val[j];
+                if (v != 0) atomicAdd(&d.cnt[cbase + k], v);
+                s_key[j] = -1;
+                s_val[j] = 0;
+            }
+        }
         if (tid == 0 && s_esc)
             atomicAdd((unsigned long long *)&d.tally[(int64_t)b * kTalCount + kTalEscaped],
                       (unsigned long long)s_esc);

@@ -16,8 +16,11 @@
 // each jump in time order, each component in order, the "+" offspring, its own
 // family, then the "-" offspring and its family.  Offspring are new particles
 // of the system with their own lineage ids and exponential clocks (Alg. 1
-// rule 3).  The walk runs twice: once to count records, then (after an ordered
-// scan with look-back fixes the output offset) to write them.  Records hold
+// rule 3).  A first walk counts the records and keeps the first two in LDS;
+// after an ordered scan with look-back fixes the output offset, families of
+// at most two records (nearly all) are copied out and only larger ones are
+// walked again to write them.  A child whose first clock draw falls past the
+// end of the step is a leaf and never enters the walk's stack.  Records hold
 // the end-of-step state, so no generation is revisited in a later launch.
 #pragma once
 #include "wbrw_dev.hpp"
@@ -254,10 +257,26 @@ struct Tally {
     int32_t maxdepth;
 };
 
+// The first kStash records of each thread's family, kept in LDS by the
+// counting walk: a family with at most kStash records (most of them: one
+// pair) is copied out after the scan instead of being walked a second time.
+constexpr int kStash = 2;
+template <int DIM, bool SP2, bool TAN>
+struct Stash {
+    double x0[kStash][kTileB], k0[kStash][kTileB];
+    double x1[DIM == 2 ? kStash : 1][DIM == 2 ? kTileB : 1];
+    double k1[DIM == 2 ? kStash : 1][DIM == 2 ? kTileB : 1];
+    double w[SP2 ? kStash : 1][SP2 ? kTileB : 1];
+    double D[TAN ? 3 * kStash : 1][TAN ? kTileB : 1];
+    uint64_t id[kStash][kTileB];
+    int8_t sg[kStash][kTileB];
+};
+
 template <int DIM, bool SP2, bool TAN, bool EMIT>
 __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step, Node cur,
                                 const Ens &out, int64_t base, int64_t first_rec, int64_t cap,
-                                int64_t dstride, Tally &tl, uint32_t &err)
+                                int64_t dstride, Tally &tl, uint32_t &err,
+                                Stash<DIM, SP2, TAN> *sh)
 {
     Node stack[kMaxDepth];
     int sp = 0;
@@ -426,8 +445,33 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
             } else {
                 err |= kErrCapacity;
             }
+        } else if (nrec < (uint32_t)kStash) {
+            const int r = (int)nrec, l = threadIdx.x;
+            sh->x0[r][l] = cur.xe[0] + (d.vfac * ch.k[0]) * (d.dt - cur.te);
+            sh->k0[r][l] = ch.k[0];
+            if (DIM == 2) {
+                sh->x1[r][l] = cur.xe[1] + (d.vfac * ch.k[1]) * (d.dt - cur.te);
+                sh->k1[r][l] = ch.k[1];
+            }
+            if (SP2) sh->w[r][l] = ch.w; else sh->sg[r][l] = (int8_t)ch.sg;
+            sh->id[r][l] = ch.id;
+            if (TAN) {
+                sh->D[3 * r][l] = ch.D[0];
+                sh->D[3 * r + 1][l] = ch.D[1];
+                sh->D[3 * r + 2][l] = ch.D[2];
+            }
         }
         nrec++;
+        ch.depth = cur.depth + 1;
+        if (!EMIT && ch.depth > tl.maxdepth) tl.maxdepth = ch.depth;
+        {
+            // The child's first clock draw, exactly as its own walk would take
+            // it: most children do not jump before the end of the step, and
+            // then there is nothing to walk and the parent stays off the stack.
+            const W4 r0 = draw(ch.id, step, kTagStep, 0u, 0u, seed, key);
+            const double tau0 = -ln_series(1.0 - unit53(r0.a, r0.b)) / P.gamma0;
+            if (!(cur.te + tau0 <= d.dt)) continue;
+        }
         if (sp >= kMaxDepth) {
             err |= kErrDepth;
             continue;
@@ -440,8 +484,6 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
         ch.in_ev = 0;
         ch.m = 0;
         ch.side = 0;
-        ch.depth = cur.depth + 1;
-        if (!EMIT && ch.depth > tl.maxdepth) tl.maxdepth = ch.depth;
         stack[sp++] = cur;
         cur = ch;
     }
@@ -455,6 +497,7 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advan
     __shared__ uint32_t s_wsum[4];
     __shared__ uint32_t s_excl;
     __shared__ int64_t s_tal[5];
+    __shared__ Stash<DIM, SP2, TAN> s_stash;
 
     Ctl *ctl = d.ctl;
     const uint32_t step = ctl->step;
@@ -514,7 +557,8 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advan
         }
         Tally tal{0, 0, 0, 0, 0};
         uint32_t cnt = 0;
-        if (ok) cnt = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal, err);
+        if (ok) cnt = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal, err,
+                                                        &s_stash);
 
         // ordered exclusive scan of the record counts over the tile
         uint32_t incl = cnt;
@@ -539,8 +583,29 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advan
         }
         __syncthreads();
         const int64_t my_first = n_before + (int64_t)s_excl + (int64_t)(woff + incl - cnt);
-        if (ok && cnt > 0)
-            walk_family<DIM, SP2, TAN, true>(d, P, step, root, E, base, my_first, cap, dstride, tal, err);
+        if (ok && cnt > (uint32_t)kStash) {
+            walk_family<DIM, SP2, TAN, true>(d, P, step, root, E, base, my_first, cap, dstride, tal, err,
+                                             &s_stash);
+        } else if (ok) {
+            for (uint32_t r = 0; r < cnt; ++r) {
+                const int64_t li = my_first + r;
+                if (li >= cap) { err |= kErrCapacity; continue; }
+                const int64_t o = base + li;
+                E.x0[o] = s_stash.x0[r][tid];
+                E.k0[o] = s_stash.k0[r][tid];
+                if (DIM == 2) {
+                    E.x1[o] = s_stash.x1[r][tid];
+                    E.k1[o] = s_stash.k1[r][tid];
+                }
+                if (SP2) E.w[o] = s_stash.w[r][tid]; else E.sg[o] = s_stash.sg[r][tid];
+                E.id[o] = s_stash.id[r][tid];
+                if (TAN) {
+                    E.D[o] = s_stash.D[3 * r][tid];
+                    E.D[dstride + o] = s_stash.D[3 * r + 1][tid];
+                    E.D[2 * dstride + o] = s_stash.D[3 * r + 2][tid];
+                }
+            }
+        }
 
         // per-instance tallies
         if (tal.events) atomicAdd((unsigned long long *)&s_tal[0], (unsigned long long)tal.events);
