@@ -369,21 +369,27 @@ void enqueue_step_dim(wbrw_t h)
     const Dev &d = h->d;
     hipStream_t s = h->stream;
     const bool tan = h->tangent != 0;
+    // stage marks bracket the main kernels only; the one-block closing
+    // launches run between them
     stage_begin(h, WBRW_STAGE_STREAM);
     hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
+    hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 0);
     stage_begin(h, WBRW_STAGE_FAMILY);
     if (h->strategy == WBRW_SP2)
-        hipLaunchKernelGGL((k_family<DIM, true, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0, 1);
+        hipLaunchKernelGGL((k_family<DIM, true, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     else if (tan)
-        hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0, 0);
+        hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     else
-        hipLaunchKernelGGL((k_family<DIM, false, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0, 1);
+        hipLaunchKernelGGL((k_family<DIM, false, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
+    hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 0, tan ? 0 : 1);
     if (tan) {
         stage_begin(h, WBRW_STAGE_GHOST);
         hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 1);
-        hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1, 1);
+        hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 1, 1);
         stage_end(h);
     }
 }
@@ -407,9 +413,11 @@ int enqueue_annihilate_dim(wbrw_t h)
         if (rc) return rc;
         stage_begin(h, WBRW_STAGE_SCAN);
         hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
         stage_end(h);
         stage_begin(h, WBRW_STAGE_REGEN);
         hipLaunchKernelGGL((k_regen<DIM, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+        hipLaunchKernelGGL(k_close_regen, dim3(1), dim3(kThreads), 0, s, d);
         stage_end(h);
         return launch_check();
     }
@@ -420,12 +428,15 @@ int enqueue_annihilate_dim(wbrw_t h)
         stage_end(h);
         stage_begin(h, WBRW_STAGE_SCAN);
         hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 0);
+        hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
         stage_end(h);
         stage_begin(h, WBRW_STAGE_REGEN);
         hipLaunchKernelGGL((k_regen<DIM, false, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+        hipLaunchKernelGGL(k_close_regen, dim3(1), dim3(kThreads), 0, s, d);
         stage_end(h);
         stage_begin(h, WBRW_STAGE_GHOST);
         hipLaunchKernelGGL(k_ghosts, dim3(h->grid[G_GHOST]), dim3(kThreads), 0, s, d);
+        hipLaunchKernelGGL(k_close_ghosts, dim3(1), dim3(kThreads), 0, s, d);
         stage_end(h);
         return launch_check();
     }
@@ -434,9 +445,11 @@ int enqueue_annihilate_dim(wbrw_t h)
     stage_end(h);
     stage_begin(h, WBRW_STAGE_SCAN);
     hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
+    hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
     stage_end(h);
     stage_begin(h, WBRW_STAGE_REGEN);
     hipLaunchKernelGGL((k_regen<DIM, false, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_close_regen, dim3(1), dim3(kThreads), 0, s, d);
     stage_end(h);
     return launch_check();
 }
@@ -692,6 +705,7 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         const int nb = std::max(1, std::min(h->cus * 8, (int)ceil_div((int64_t)h->B * L.Nh, kThreads)));
         hipLaunchKernelGGL(k_hist_round, dim3(nb), dim3(kThreads), 0, s, d, (const double *)hd, mu);
         hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
         if (h->dim == 1) {
             if (h->strategy == WBRW_SP2) hipLaunchKernelGGL((k_regen<1, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
             else if (h->tangent) hipLaunchKernelGGL((k_regen<1, false, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
@@ -700,6 +714,7 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
             if (h->strategy == WBRW_SP2) hipLaunchKernelGGL((k_regen<2, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
             else hipLaunchKernelGGL((k_regen<2, false, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
         }
+        hipLaunchKernelGGL(k_close_regen, dim3(1), dim3(kThreads), 0, s, d);
         if (launch_check()) return fail(WBRW_EHIP);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(WBRW_EHIP);
         *out = h;

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     if (!TAN)
         for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
     for (;;) {
-        if (tid == 0) { s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u); s_esc = 0; }
+        if (tid == 0) { s_t = next_tile(&ctl->ticket[kPassTiles], ntiles); s_esc = 0; }
         __syncthreads();
         const int64_t t = s_t;
         if (t >= ntiles) break;
@@ -273,9 +273,6 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                       (unsigned long long)s_esc);
         __syncthreads();
     }
-    if (last_block_done(&ctl->done[kPassTiles])) {
-        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -295,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
     const int64_t ntiles = tiles_per * B;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassScan], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassScan], ntiles);
         __syncthreads();
         const int64_t t = s_t;
         if (t >= ntiles) break;
@@ -342,17 +339,21 @@ __global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
         }
         __syncthreads();
     }
-    if (last_block_done(&ctl->done[kPassScan])) {
-        for (int b = tid; b < B; b += kThreads) {
-            if (d.Nnew[b] > d.ip[b].cap) {
-                atomicOr(&ctl->err, kErrCapacity);
-                d.Nnew[b] = d.ip[b].cap;
-            }
+}
+
+// After k_scan (one block): capacity clamp and the regeneration-tile plan.
+__global__ __launch_bounds__(kThreads) void k_close_scan(Dev d)
+{
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    for (int b = threadIdx.x; b < B; b += kThreads) {
+        if (d.Nnew[b] > d.ip[b].cap) {
+            atomicOr(&ctl->err, kErrCapacity);
+            d.Nnew[b] = d.ip[b].cap;
         }
-        __syncthreads();
-        block_plan(d.tileR, d.Nnew, B, kTileR);
-        if (tid == 0) { ctl->ticket[kPassScan] = 0u; ctl->done[kPassScan] = 0u; }
     }
+    __syncthreads();
+    block_plan(d.tileR, d.Nnew, B, kTileR);
 }
 
 // largest cell nu with (off[nu] & mask) <= o
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(kThreads) void k_regen(Dev d)
     const Ens O = pick_set(d, 0, ctl->cur ^ 1u);
     const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassRegen], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassRegen], ntiles);
         __syncthreads();
         const int64_t t = s_t;
         __syncthreads();
@@ -416,16 +417,20 @@ __global__ __launch_bounds__(kThreads) void k_regen(Dev d)
             }
         }
     }
-    if (last_block_done(&ctl->done[kPassRegen])) {
-        for (int b = tid; b < B; b += kThreads) d.N[b] = d.Nnew[b];
-        __syncthreads();
-        block_plan(d.tileA, d.N, B, kTileA);
-        if (tid == 0) {
-            ctl->cur ^= 1u;
-            ctl->ann_seq += 1u;
-            ctl->ticket[kPassRegen] = 0u;
-            ctl->done[kPassRegen] = 0u;
-        }
+}
+
+// After k_regen (one block): the new counts and tile plan; the regenerated
+// buffer set becomes the active one.
+__global__ __launch_bounds__(kThreads) void k_close_regen(Dev d)
+{
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    for (int b = threadIdx.x; b < B; b += kThreads) d.N[b] = d.Nnew[b];
+    __syncthreads();
+    block_plan(d.tileA, d.N, B, kTileA);
+    if (threadIdx.x == 0) {
+        ctl->cur ^= 1u;
+        ctl->ann_seq += 1u;
     }
 }
 
@@ -476,7 +481,7 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
         __syncthreads();
     };
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
         __syncthreads();
         const int64_t t = s_t;
         __syncthreads();
@@ -536,9 +541,6 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
         }
     }
     if (priv && cb >= 0) flush(cb);
-    if (last_block_done(&ctl->done[kPassTiles])) {
-        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
-    }
 }
 
 // out[b][j] = acc / (N0_b dxb); the accumulator is cleared.
@@ -586,7 +588,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp(Dev d, int ghost, int nbins, d
     const int64_t ds = ghost ? d.gcap_total : d.cap_total;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
         __syncthreads();
         const int64_t t = s_t;
         if (t >= ntiles) break;
@@ -619,9 +621,6 @@ __global__ __launch_bounds__(kThreads) void k_vjp(Dev d, int ghost, int nbins, d
             atomicAdd(&acc[(int64_t)b * 3 + tid], v);
         }
         __syncthreads();
-    }
-    if (last_block_done(&ctl->done[kPassTiles])) {
-        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
     }
 }
 

@@ -14,7 +14,7 @@ namespace wbrw {
 
 constexpr int kMaxM = 4;
 constexpr int kThreads = 256;           // threads per block in every kernel
-constexpr int kPPT = 8;                 // particles (or cells) per thread in streaming passes
+constexpr int kPPT = 16;                // particles (or cells) per thread in streaming passes
 constexpr int kTileA = kThreads * kPPT; // particles per streaming tile
 constexpr int kTileB = kThreads;        // event-parents per family tile
 constexpr int kTileS = kThreads * kPPT; // cells per scan tile
@@ -33,7 +33,7 @@ enum : int {
     kTalSplus, kTalSminus, kTalNplus, kTalNminus, kTalPSteps, kTalCount = 16
 };
 
-// ticket / done slots
+// ticket counters of the persistent passes
 enum : int {
     kPassStream = 0, kPassFamily = 1, kPassStreamG = 2, kPassFamilyG = 3,
     kPassScan = 4, kPassRegen = 5, kPassTiles = 6, kPassGhost = 7, kPassCount = 8
@@ -79,8 +79,7 @@ struct Ctl {
     uint32_t err;              // sticky error bits
     uint32_t ann_seq;          // annihilations so far (look-back epoch of the scans)
     uint32_t pad[3];
-    uint32_t ticket[kPassCount];
-    uint32_t done[kPassCount];
+    uint32_t ticket[kPassCount];   // zero between launches (see next_tile)
 };
 
 struct Dev {
@@ -228,20 +227,19 @@ __device__ __forceinline__ uint32_t tile_prefix(uint64_t *st, int64_t t, int64_t
     return excl;
 }
 
-// The calling block is the last of the grid to finish (all other blocks'
-// global writes are visible afterwards).  Must be called by every thread.
-__device__ __forceinline__ bool last_block_done(uint32_t *done_ctr)
+// Next tile of a persistent pass, for thread 0 of a block.  Every block
+// draws until it gets a ticket >= ntiles, so one launch hands out exactly
+// ntiles + gridDim.x tickets, and the block that draws the last of them
+// clears the counter for the next launch (which sees it after the kernel
+// boundary).  No block waits for the others at the end, and no device-wide
+// fence is needed.  Work that needs every block's results runs in a separate
+// one-block launch.
+__device__ __forceinline__ int64_t next_tile(uint32_t *ctr, int64_t ntiles)
 {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t prev = atomicAdd(done_ctr, 1u);
-        s_last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (s_last) __threadfence();
-    return s_last != 0;
+    const uint32_t t = atomicAdd(ctr, 1u);
+    if ((int64_t)t == ntiles + (int64_t)gridDim.x - 1)
+        __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (int64_t)t;
 }
 
 // plan[b] = sum_{b' < b} ceil(cnt[b'] / tile), plan[B] = total; one block.

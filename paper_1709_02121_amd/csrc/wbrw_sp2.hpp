@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
     const Ens E = pick_set(d, 0, ctl->cur);
     const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
         if (tid < 5) s_acc[tid] = 0ull;
         __syncthreads();
         const int64_t t = s_t;
@@ -105,9 +105,6 @@ __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
         }
         __syncthreads();
     }
-    if (last_block_done(&ctl->done[kPassTiles])) {
-        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
-    }
 }
 
 // ---- stage 2: kept copies k_i, residuals r_i, per-tile residual sums --------
@@ -122,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
     const int tid = threadIdx.x;
     const int64_t C = d.cap_total;
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
         if (tid < 6) s_acc[tid] = 0ull;
         __syncthreads();
         const int64_t t = s_t;
@@ -173,9 +170,6 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
             }
         }
         __syncthreads();
-    }
-    if (last_block_done(&ctl->done[kPassTiles])) {
-        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
     }
 }
 
@@ -229,11 +223,14 @@ __global__ __launch_bounds__(kThreads) void k_sp2_tilescan(Dev d)
         }
         __syncthreads();
     }
-    if (last_block_done(&ctl->done[kPassScan])) {
-        block_plan(d.tileD, d.Nnew, B, kTileR);
-        block_plan(d.tileD + (B + 1), d.NGnew, B, kTileR);
-        if (tid == 0) { ctl->ticket[kPassScan] = 0u; ctl->done[kPassScan] = 0u; }
-    }
+}
+
+// After k_sp2_tilescan (one block): the draw-tile plans of both classes.
+__global__ __launch_bounds__(kThreads) void k_close_sp2_tilescan(Dev d)
+{
+    const int B = d.B;
+    block_plan(d.tileD, d.Nnew, B, kTileR);
+    block_plan(d.tileD + (B + 1), d.NGnew, B, kTileR);
 }
 
 // ---- stage 4: per-particle exclusive prefixes P_0, P_1 (128-bit) -----------
@@ -248,7 +245,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
     const int64_t C = d.cap_total;
     const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
         __syncthreads();
         const int64_t t = s_t;
         if (t >= ntiles) break;
@@ -300,9 +297,6 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
         }
         __syncthreads();
     }
-    if (last_block_done(&ctl->done[kPassTiles])) {
-        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
-    }
 }
 
 // ---- stage 5: the N_r i.i.d. draws of each class (Alg. 2 step 2) ------------
@@ -316,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
     const int64_t C = d.cap_total;
     const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
         __syncthreads();
         const int64_t t = s_t;
         __syncthreads();
@@ -345,9 +339,6 @@ __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
             atomicAdd(&d.bcopies[P.base + lo], 1);
         }
     }
-    if (last_block_done(&ctl->done[kPassTiles])) {
-        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
-    }
 }
 
 // ---- stage 6: filtered counts per cell and class ---------------------------
@@ -361,7 +352,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
     const int tid = threadIdx.x;
     const int64_t plane = (int64_t)B * d.Nh;
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassTiles], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
         __syncthreads();
         const int64_t t = s_t;
         __syncthreads();
@@ -378,9 +369,6 @@ __global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
             if (c < 0 || cp == 0) continue;
             atomicAdd(&d.ntil[(int64_t)c * plane + (int64_t)b * d.Nh + d.bcell[i]], cp);
         }
-    }
-    if (last_block_done(&ctl->done[kPassTiles])) {
-        if (tid == 0) { ctl->ticket[kPassTiles] = 0u; ctl->done[kPassTiles] = 0u; }
     }
 }
 
@@ -446,6 +434,7 @@ int enqueue_sp2_bootstrap(const Dev &d, hipStream_t s, int grid, int grid_scan)
     hipLaunchKernelGGL(k_sp2_classify<DIM>, dim3(grid), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_resid, dim3(grid), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_tilescan, dim3(std::min(d.B, grid_scan)), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_close_sp2_tilescan, dim3(1), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_prefix, dim3(grid), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_draw, dim3(grid), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_cells, dim3(grid), dim3(kThreads), 0, s, d);
@@ -475,7 +464,7 @@ __global__ __launch_bounds__(kThreads) void k_ghosts(Dev d)
     const int64_t nc = d.Nh * (int64_t)B;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[kPassGhost], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassGhost], ntiles);
         __syncthreads();
         const int64_t t = s_t;
         if (t >= ntiles) break;
@@ -534,20 +523,22 @@ __global__ __launch_bounds__(kThreads) void k_ghosts(Dev d)
         }
         __syncthreads();
     }
-    if (last_block_done(&ctl->done[kPassGhost])) {
-        for (int b = tid; b < B; b += kThreads) {
-            int64_t n = d.NGnew[b];
-            if (n > d.ip[b].gcap) { atomicOr(&ctl->err, kErrCapacity); n = d.ip[b].gcap; }
-            d.NG[b] = n;
-        }
-        __syncthreads();
-        block_plan(d.tileA + (B + 1), d.NG, B, kTileA);
-        if (tid == 0) {
-            ctl->gcur ^= 1u;
-            ctl->ticket[kPassGhost] = 0u;
-            ctl->done[kPassGhost] = 0u;
-        }
+}
+
+// After k_ghosts (one block): ghost counts with the capacity clamp, their tile
+// plan, and the ghost buffer flip.
+__global__ __launch_bounds__(kThreads) void k_close_ghosts(Dev d)
+{
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    for (int b = threadIdx.x; b < B; b += kThreads) {
+        int64_t n = d.NGnew[b];
+        if (n > d.ip[b].gcap) { atomicOr(&ctl->err, kErrCapacity); n = d.ip[b].gcap; }
+        d.NG[b] = n;
     }
+    __syncthreads();
+    block_plan(d.tileA + (B + 1), d.NG, B, kTileA);
+    if (threadIdx.x == 0) ctl->gcur ^= 1u;
 }
 
 }  // namespace wbrw

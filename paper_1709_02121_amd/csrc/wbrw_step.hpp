@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_stream(Dev d, int ghost)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[pass], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[pass], ntiles);
         __syncthreads();
         const int64_t t = s_t;
         if (t >= ntiles) break;
@@ -196,10 +196,17 @@ __global__ __launch_bounds__(kThreads) void k_stream(Dev d, int ghost)
         }
         __syncthreads();
         if (wv == 0) {
-            uint32_t acc = 0;
-            if (lane == 0)
-                for (int q = 0; q < kPPT * 4; ++q) { s_woff[q] = acc; acc += s_wcnt[q]; }
-            acc = __shfl(acc, 0, 64);
+            // exclusive scan of the kPPT x 4 wave counts, in (j, wave) order
+            static_assert(kPPT * 4 <= 64, "one lane per (particle slot, wave)");
+            const uint32_t c = lane < kPPT * 4 ? s_wcnt[lane] : 0u;
+            uint32_t inc = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t v = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += v;
+            }
+            if (lane < kPPT * 4) s_woff[lane] = inc - c;
+            const uint32_t acc = __shfl(inc, 63, 64);
             const uint32_t excl = tile_prefix(st, t, first, epoch, acc);
             if (lane == 0) {
                 if (t == last) d.evc[(int64_t)ghost * B + b] = (int64_t)(excl + acc);
@@ -220,16 +227,18 @@ __global__ __launch_bounds__(kThreads) void k_stream(Dev d, int ghost)
         __syncthreads();
     }
 
-    if (last_block_done(&ctl->done[pass])) {
-        block_plan(d.tileB + (int64_t)ghost * (B + 1), d.evc + (int64_t)ghost * B, B, kTileB);
-        for (int b = tid; b < B; b += kThreads) {
-            d.chc[(int64_t)ghost * B + b] = 0;
-            if (!ghost) d.tally[(int64_t)b * kTalCount + kTalPSteps] += Ncur[b];
-        }
-        if (tid == 0) {
-            ctl->ticket[pass] = 0u;
-            ctl->done[pass] = 0u;
-        }
+}
+
+// After k_stream (one block): the family-tile plan from the event counts,
+// cleared record counts, and the particle-step tally.
+__global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
+{
+    const int B = d.B;
+    const int64_t *Ncur = ghost ? d.NG : d.N;
+    block_plan(d.tileB + (int64_t)ghost * (B + 1), d.evc + (int64_t)ghost * B, B, kTileB);
+    for (int b = threadIdx.x; b < B; b += kThreads) {
+        d.chc[(int64_t)ghost * B + b] = 0;
+        if (!ghost) d.tally[(int64_t)b * kTalCount + kTalPSteps] += Ncur[b];
     }
 }
 
@@ -491,7 +500,7 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
 }
 
 template <int DIM, bool SP2, bool TAN>
-__global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advance)
+__global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost)
 {
     __shared__ int64_t s_t;
     __shared__ uint32_t s_wsum[4];
@@ -517,7 +526,7 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advan
     uint32_t err = 0;
 
     for (;;) {
-        if (tid == 0) s_t = (int64_t)atomicAdd(&ctl->ticket[pass], 1u);
+        if (tid == 0) s_t = next_tile(&ctl->ticket[pass], ntiles);
         if (tid < 5) s_tal[tid] = 0;
         __syncthreads();
         const int64_t t = s_t;
@@ -626,29 +635,35 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost, int advan
     }
     if (err) atomicOr(&ctl->err, err);
 
-    if (last_block_done(&ctl->done[pass])) {
-        int64_t *chc = d.chc + (int64_t)ghost * B;
-        int64_t *evc = d.evc + (int64_t)ghost * B;
-        for (int b = tid; b < B; b += kThreads) {
-            const InstParam &P = d.ip[b];
-            const int64_t cap = ghost ? P.gcap : P.cap;
-            int64_t n = Ncur[b] + chc[b];
-            if (n > cap) {
-                atomicOr(&ctl->err, kErrCapacity);
-                n = cap;
-            }
-            Ncur[b] = n;
-            chc[b] = 0;
-            evc[b] = 0;
+}
+
+// After k_family (one block): the new particle counts with the capacity
+// clamp, cleared event and record counts, the streaming-tile plan of the
+// next step, and the step counter.
+__global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int advance)
+{
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const uint32_t step = ctl->step;
+    int64_t *Ncur = ghost ? d.NG : d.N;
+    const int tid = threadIdx.x;
+    int64_t *chc = d.chc + (int64_t)ghost * B;
+    int64_t *evc = d.evc + (int64_t)ghost * B;
+    for (int b = tid; b < B; b += kThreads) {
+        const InstParam &P = d.ip[b];
+        const int64_t cap = ghost ? P.gcap : P.cap;
+        int64_t n = Ncur[b] + chc[b];
+        if (n > cap) {
+            atomicOr(&ctl->err, kErrCapacity);
+            n = cap;
         }
-        __syncthreads();
-        block_plan(d.tileA + (int64_t)ghost * (B + 1), Ncur, B, kTileA);
-        if (tid == 0) {
-            ctl->ticket[pass] = 0u;
-            ctl->done[pass] = 0u;
-            if (advance) ctl->step = step + 1u;
-        }
+        Ncur[b] = n;
+        chc[b] = 0;
+        evc[b] = 0;
     }
+    __syncthreads();
+    block_plan(d.tileA + (int64_t)ghost * (B + 1), Ncur, B, kTileA);
+    if (tid == 0 && advance) ctl->step = step + 1u;
 }
 
 }  // namespace wbrw
