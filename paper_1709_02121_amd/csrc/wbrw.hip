@@ -32,7 +32,7 @@ struct Layout {
     size_t ens[2][8] = {}, gens[2][8] = {};
     size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
     size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, chc = 0, tileA = 0, tileB = 0, tileR = 0,
-           tileG = 0, tally = 0, ev_idx = 0, ev_x0 = 0, ev_x1 = 0, gev_idx = 0, gev_x0 = 0,
+           tileG = 0, tally = 0, fpart = 0, ev_idx = 0, ev_x0 = 0, ev_x1 = 0, gev_idx = 0, gev_x0 = 0,
            gev_x1 = 0, stA = 0, stAg = 0, stB = 0, stBg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
            bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0, xitab = 0;
@@ -187,6 +187,7 @@ Layout make_layout(const wbrw_config *c)
     L.tileR = take(cur, (BB + 1) * 8);
     L.tileG = take(cur, (BB + 1) * 8);
     L.tally = take(cur, BB * kTalCount * 8);
+    L.fpart = take(cur, (size_t)kMaxGrid * 8 * 8);
     L.stA = take(cur, (size_t)L.tilesA * 8);
     L.stB = take(cur, (size_t)L.tilesB * 8);
     if (tan) {
@@ -257,7 +258,7 @@ int persistent_blocks(K kernel, int cus)
 {
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) != hipSuccess || per < 1) per = 1;
-    return per * cus;
+    return std::min(per * cus, kMaxGrid);
 }
 
 // Alg. 4 sampler: xi(r) = (1/2) int |V_W| dq for the Gaussian barrier on
@@ -383,13 +384,13 @@ void enqueue_step_dim(wbrw_t h)
     else
         hipLaunchKernelGGL((k_family<DIM, false, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
-    hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 0, tan ? 0 : 1);
+    hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 0, tan ? 0 : 1, h->grid[G_FAMILY]);
     if (tan) {
         stage_begin(h, WBRW_STAGE_GHOST);
         hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1);
-        hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 1, 1);
+        hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 1, 1, h->grid[G_FAMILY]);
         stage_end(h);
     }
 }
@@ -636,6 +637,7 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.tileR = at<int64_t>(w, L.tileR);
     d.tileG = at<int64_t>(w, L.tileG);
     d.tally = at<int64_t>(w, L.tally);
+    d.fpart = at<int64_t>(w, L.fpart);
     d.ev_idx = at<uint32_t>(w, L.ev_idx);
     d.ev_x0 = at<double>(w, L.ev_x0);
     d.ev_x1 = cfg->dim == 2 ? at<double>(w, L.ev_x1) : nullptr;

@@ -24,6 +24,7 @@ constexpr uint32_t kEventCap = 4096u;   // jumps per particle-step
 constexpr int kXiN = 4096;              // xi(r) grid intervals (Alg. 4 sampler)
 constexpr int kXiQ = 8192;              // quadrature nodes for xi(r)
 constexpr uint32_t kRejectMax = 256u;   // rejection proposals per kick
+constexpr int kMaxGrid = 8192;          // blocks of a persistent launch (per-block partials)
 
 enum : uint32_t { kErrCapacity = 1u, kErrDepth = 2u };
 
@@ -108,6 +109,7 @@ struct Dev {
     int64_t *tileR;             // [B+1] regeneration-tile plan
     int64_t *tileG;             // [B+1] ghost-regeneration plan
     int64_t *tally;             // [B][kTalCount]
+    int64_t *fpart;             // [kMaxGrid][8]: instance and tallies of each family block
     uint32_t *ev_idx;           // [cap_total] event-parent index within its instance
     double *ev_x0, *ev_x1;      // [cap_total] its position at the start of the step
     uint32_t *gev_idx;          // ghosts

@@ -245,6 +245,11 @@ __global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
 // ---------------------------------------------------------------------------
 // Pass 2: family trees of event parents
 // ---------------------------------------------------------------------------
+// Kick and weight of a created pair (see draw_pair).
+struct PairDraw {
+    double q, arg, sn, sigma, amp;
+};
+
 struct Node {
     double x[2], k[2];   // position at t0, wave vector
     double t0;           // start of this particle's walk within the step
@@ -261,14 +266,25 @@ struct Node {
     int32_t m, side, in_ev;
 };
 
+// True if the clock draw u certainly gives no jump before the end of the
+// step for a clock running from t, i.e. t - ln(1-u)/gamma0 > dt as the exact
+// test evaluates it.  -ln(1-u) >= u makes u > gamma0 (dt - t) sufficient in
+// exact arithmetic; the relative 2^-30 and absolute dt 2^-40 margins cover
+// the rounding of the exact test (the logarithm within a few ulp, the
+// division, the sum compared with dt).  Only draws below the bound (a few
+// percent) pay for the logarithm.
+__device__ __forceinline__ bool surely_no_jump(double u, double t, double dt, double g0)
+{
+    return u > g0 * ((dt - t) * (1.0 + 0x1p-30) + dt * 0x1p-40);
+}
+
 struct Tally {
     int64_t events, pairs, killed, cap;
     int32_t maxdepth;
 };
 
-// The first kStash records of each thread's family, kept in LDS by the
-// counting walk: a family with at most kStash records (most of them: one
-// pair) is copied out after the scan instead of being walked a second time.
+// The records of a family found by fast_family (at most kStash: nearly
+// always one pair), kept in LDS until the ordered scan has placed them.
 constexpr int kStash = 2;
 template <int DIM, bool SP2, bool TAN>
 struct Stash {
@@ -281,13 +297,240 @@ struct Stash {
     int8_t sg[kStash][kTileB];
 };
 
+// Records of the families that took the general walk, in order of creation
+// across the tile, each tagged with its family's slot and its rank within
+// the family.  A family whose records do not all fit is walked again when
+// the records are written.
+constexpr int kPool = 256;
+template <int DIM, bool SP2, bool TAN>
+struct Pool {
+    double x0[kPool], k0[kPool];
+    double x1[DIM == 2 ? kPool : 1], k1[DIM == 2 ? kPool : 1];
+    double w[SP2 ? kPool : 1];
+    double D[TAN ? 3 : 1][TAN ? kPool : 1];
+    uint64_t id[kPool];
+    uint16_t slot[kPool], rank[kPool];
+    int8_t sg[kPool];
+    uint32_t n;
+};
+
+// Pair decision and kick of component m at jump e of particle `id`
+// (Alg. 1 rules 3-5 with the majorant sampler of Remark 3, or Alg. 4):
+// returns false if no pair is created.
+
+template <bool SP2>
+__device__ __forceinline__ bool draw_pair(const Dev &d, const InstParam &P, uint64_t id, uint32_t step,
+                                          uint32_t e, int m, const double *xe, double te, double ua0,
+                                          double w, PairDraw &J)
+{
+    const uint32_t seed = d.seed, key = P.key;
+    double cm = P.c[m], sgv = P.sgnV[m];
+    bool alg4 = false;
+    if (d.sampler[m] == 1) {
+        // Alg. 1 sp1 box with Pr = xi(x)/gamma0, kick by Alg. 4
+        const double r = phase_offset(d, m, xe, P.center[m]);
+        double ua = ua0;
+        if (m > 0) {
+            const W4 ra = draw(id, step, kTagStep, e, (uint32_t)(8 + m), seed, key);
+            ua = unit53(ra.a, ra.b);
+        }
+        const double *tab = d.xi_tab + ((int64_t)(&P - d.ip) * d.M + m) * (kXiN + 1);
+        double qk = 0.0;
+        if (!(ua < xi_lerp(tab, P.xi_h[m], r) / P.gamma0) || !reject_kick(d, P, id, step, e, m, r, qk))
+            return false;
+        J.q = qk;
+        J.arg = (2.0 * qk) * r;
+        J.sn = 1.0;
+        sgv = 1.0;
+        alg4 = true;
+    } else {
+        const W4 rq = draw(id, step, kTagStep, e, (uint32_t)(1 + m), seed, key);
+        J.q = kick_sample(d, P, m, unit53(rq.a, rq.b), unit53(rq.c, rq.d));
+        J.arg = (2.0 * J.q) * phase_offset(d, m, xe, P.center[m]);
+        J.sn = sin_det(J.arg);
+    }
+    if (d.tdep && d.kind[m] == 0 && !alg4) {   // Remark 1: kernel at the absolute jump time
+        const double tabs = (double)step * d.dt + te;
+        const double f = P.ma[m] + P.mb[m] * cos_det(P.mw[m] * tabs + P.mp[m]);
+        const double He = P.H[m] * f;
+        cm = ((2.0 * fabs(He)) / d.hbar) / (2.0 * P.gamma0);
+        sgv = He >= 0.0 ? 1.0 : -1.0;
+    }
+    J.sigma = (J.sn > 0.0) ? sgv : -sgv;
+    J.amp = 0.0;
+    if (!SP2 && !alg4) {
+        double ua = ua0;
+        if (m > 0) {
+            const W4 ra = draw(id, step, kTagStep, e, (uint32_t)(8 + m), seed, key);
+            ua = unit53(ra.a, ra.b);
+        }
+        if (!(ua < cm * fabs(J.sn))) return false;   // no pair: only the survivor continues
+    } else if (SP2) {
+        J.amp = w * (cm * fabs(J.sn));
+    }
+    return true;
+}
+
+// Offspring `side` (0: "+", 1: "-") of the pair J of component m at jump e;
+// rc is the child-id draw of (parent, e, m).  Sets k, sign, weight, id and
+// tangent of ch.
+template <bool SP2, bool TAN>
+__device__ __forceinline__ void make_child(const Dev &d, const InstParam &P, const Node &par, int m, int side,
+                                           const PairDraw &J, const W4 &rc, Node &ch)
+{
+    const uint64_t cls = ((par.id >> 62) & 1ull) ? 3ull : 2ull;   // ghost lineages keep bit 62
+    ch.id = side == 0 ? ((cls << 62) | ((uint64_t)(rc.b & 0x3FFFFFFFu) << 32) | (uint64_t)rc.a)
+                      : ((cls << 62) | ((uint64_t)(rc.d & 0x3FFFFFFFu) << 32) | (uint64_t)rc.c);
+    const double kick = J.sigma * J.q;
+    ch.k[0] = par.k[0];
+    ch.k[1] = par.k[1];
+    const int ax = d.axis[m];
+    if (ax == 0) {
+        ch.k[0] = side == 0 ? par.k[0] + kick : par.k[0] - kick;
+    } else if (ax == 1) {
+        ch.k[1] = side == 0 ? par.k[1] + kick : par.k[1] - kick;
+    } else {
+        ch.k[0] = side == 0 ? par.k[0] + kick : par.k[0] - kick;
+        ch.k[1] = side == 0 ? par.k[1] - kick : par.k[1] + kick;
+    }
+    ch.sg = side == 0 ? par.sg : -par.sg;
+    ch.w = side == 0 ? J.amp : -J.amp;
+    if (TAN) {
+        const double wd = P.width[m];
+        const double s0 = 1.0 / P.H[m];
+        const double s1 = 1.0 / wd - ((4.0 * wd) * J.q) * J.q;
+        const double s2 = -(2.0 * J.q) * (cos_det(J.arg) / J.sn);
+        const double sdir = side == 0 ? 1.0 : -1.0;
+        const double sgd = (double)ch.sg;
+        ch.D[0] = sdir * par.D[0] + sgd * s0;
+        ch.D[1] = sdir * par.D[1] + sgd * s1;
+        ch.D[2] = sdir * par.D[2] + sgd * s2;
+    } else {
+        ch.D[0] = ch.D[1] = ch.D[2] = 0.0;
+    }
+}
+
+// k-truncation tally of a child that left the k-box (Sec. 2)
+template <bool SP2>
+__device__ __forceinline__ int64_t killed_amount(const Node &ch)
+{
+    if (SP2) {
+        const int64_t q32 = (int64_t)floor(fabs(ch.w) * 4294967296.0);
+        return ch.w < 0.0 ? -q32 : q32;
+    }
+    return ch.sg;
+}
+
+// End-of-step record of a child created at time te at position xe, kept in
+// stash row r of `slot`.
+template <int DIM, bool SP2, bool TAN>
+__device__ __forceinline__ void stash_record(const Dev &d, Stash<DIM, SP2, TAN> *sh, int r, int slot,
+                                             const double *xe, double te, const Node &ch)
+{
+    sh->x0[r][slot] = xe[0] + (d.vfac * ch.k[0]) * (d.dt - te);
+    sh->k0[r][slot] = ch.k[0];
+    if (DIM == 2) {
+        sh->x1[r][slot] = xe[1] + (d.vfac * ch.k[1]) * (d.dt - te);
+        sh->k1[r][slot] = ch.k[1];
+    }
+    if (SP2) sh->w[r][slot] = ch.w; else sh->sg[r][slot] = (int8_t)ch.sg;
+    sh->id[r][slot] = ch.id;
+    if (TAN) {
+        sh->D[3 * r][slot] = ch.D[0];
+        sh->D[3 * r + 1][slot] = ch.D[1];
+        sh->D[3 * r + 2][slot] = ch.D[2];
+    }
+}
+
+template <int DIM, bool SP2, bool TAN>
+__device__ __forceinline__ bool pool_record(const Dev &d, Pool<DIM, SP2, TAN> *pl, int rank, int slot,
+                                            const double *xe, double te, const Node &ch)
+{
+    const uint32_t r = atomicAdd(&pl->n, 1u);
+    if (r >= (uint32_t)kPool) return false;
+    pl->x0[r] = xe[0] + (d.vfac * ch.k[0]) * (d.dt - te);
+    pl->k0[r] = ch.k[0];
+    if (DIM == 2) {
+        pl->x1[r] = xe[1] + (d.vfac * ch.k[1]) * (d.dt - te);
+        pl->k1[r] = ch.k[1];
+    }
+    if (SP2) pl->w[r] = ch.w; else pl->sg[r] = (int8_t)ch.sg;
+    pl->id[r] = ch.id;
+    if (TAN) {
+        pl->D[0][r] = ch.D[0];
+        pl->D[1][r] = ch.D[1];
+        pl->D[2][r] = ch.D[2];
+    }
+    pl->slot[r] = (uint16_t)slot;
+    pl->rank[r] = (uint16_t)rank;
+    return true;
+}
+
+// The common family in lockstep: the parent jumps once in the step, and
+// every kept child is a leaf (its first clock draw falls past the end of
+// the step).  Produces the same records, in the same order, and the same
+// tallies as walk_family would, with no per-lane state machine.  Returns
+// false if the family is not of this kind (a second jump of the parent, a
+// child that jumps again, or more than kStash records); cnt and tl are then
+// to be discarded.
+template <int DIM, bool SP2, bool TAN>
+__device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, uint32_t step,
+                                            const Node &root, Stash<DIM, SP2, TAN> *sh, int slot,
+                                            uint32_t &cnt, Tally &tl)
+{
+    const uint32_t seed = d.seed, key = P.key;
+    cnt = 0;
+    const W4 r = draw(root.id, step, kTagStep, 0u, 0u, seed, key);
+    const double te = root.t0 + (-ln_series(1.0 - unit53(r.a, r.b)) / P.gamma0);
+    if (!(te <= d.dt)) return true;
+    tl.events++;
+    const double ua0 = unit53(r.c, r.d);
+    double xe[2];
+    xe[0] = root.x[0] + (d.vfac * root.k[0]) * (te - root.t0);
+    xe[1] = DIM == 2 ? root.x[1] + (d.vfac * root.k[1]) * (te - root.t0) : 0.0;
+    bool fast = true;
+    for (int m = 0; m < d.M; ++m) {
+        PairDraw J;
+        if (!draw_pair<SP2>(d, P, root.id, step, 0u, m, xe, te, ua0, root.w, J)) continue;
+        tl.pairs++;
+        const W4 rc = draw(root.id, step, kTagChild, 0u, (uint32_t)m, seed, key);
+        for (int side = 0; side < 2; ++side) {
+            Node ch;
+            make_child<SP2, TAN>(d, P, root, m, side, J, rc, ch);
+            if (!in_kbox<DIM>(d, ch.k)) {
+                tl.killed += killed_amount<SP2>(ch);
+                continue;
+            }
+            if (cnt < (uint32_t)kStash) stash_record<DIM, SP2, TAN>(d, sh, (int)cnt, slot, xe, te, ch);
+            else fast = false;
+            cnt++;
+            if (tl.maxdepth < 1) tl.maxdepth = 1;
+            const W4 r0 = draw(ch.id, step, kTagStep, 0u, 0u, seed, key);
+            const double u0 = unit53(r0.a, r0.b);
+            if (!surely_no_jump(u0, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u0) / P.gamma0) <= d.dt)
+                fast = false;
+        }
+    }
+    const W4 r1 = draw(root.id, step, kTagStep, 1u, 0u, seed, key);
+    const double u1 = unit53(r1.a, r1.b);
+    if (!surely_no_jump(u1, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u1) / P.gamma0) <= d.dt)
+        fast = false;
+    return fast;
+}
+
+// General depth-first walk of one family (any number of jumps and levels).
+// Counting mode (EMIT false) tallies and puts the records into the tile's
+// pool (clearing `pooled` if one did not fit); emitting mode writes every
+// record from first_rec on.
 template <int DIM, bool SP2, bool TAN, bool EMIT>
 __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step, Node cur,
                                 const Ens &out, int64_t base, int64_t first_rec, int64_t cap,
                                 int64_t dstride, Tally &tl, uint32_t &err,
-                                Stash<DIM, SP2, TAN> *sh)
+                                Pool<DIM, SP2, TAN> *pl, int slot, bool &pooled)
 {
     Node stack[kMaxDepth];
+    PairDraw stackJ[kMaxDepth];
+    W4 stackR[kMaxDepth];
     int sp = 0;
     uint32_t nrec = 0;
     const uint32_t seed = d.seed, key = P.key;
@@ -305,8 +548,8 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
             } else {
                 const W4 r = draw(cur.id, step, kTagStep, cur.e, 0u, seed, key);
                 const double u = unit53(r.a, r.b);
-                const double tau = -ln_series(1.0 - u) / P.gamma0;
-                const double te = cur.t + tau;
+                const double te = surely_no_jump(u, cur.t, d.dt, P.gamma0)
+                                      ? d.dt + 1.0 : cur.t + (-ln_series(1.0 - u) / P.gamma0);
                 if (!(te <= d.dt)) {
                     done = true;
                 } else {
@@ -334,155 +577,80 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
             continue;
         }
         const int m = cur.m;
-        double q, arg, sn, cm = P.c[m], sgv = P.sgnV[m];
-        bool alg4 = false;
-        if (d.sampler[m] == 1) {
-            // Alg. 1 sp1 box with Pr = xi(x)/gamma0, kick by Alg. 4
-            const double r = phase_offset(d, m, cur.xe, P.center[m]);
-            double ua = cur.ua0;
-            if (m > 0) {
-                const W4 ra = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(8 + m), seed, key);
-                ua = unit53(ra.a, ra.b);
-            }
-            const double *tab = d.xi_tab + ((int64_t)(&P - d.ip) * d.M + m) * (kXiN + 1);
-            double qk = 0.0;
-            if (!(ua < xi_lerp(tab, P.xi_h[m], r) / P.gamma0) || !reject_kick(d, P, cur.id, step, cur.e, m, r, qk)) {
+        PairDraw J;
+        W4 rc;
+        if (cur.side == 0) {
+            if (!draw_pair<SP2>(d, P, cur.id, step, cur.e, m, cur.xe, cur.te, cur.ua0, cur.w, J)) {
                 cur.m += 1;
-                cur.side = 0;
                 continue;
             }
-            q = qk;
-            arg = (2.0 * qk) * r;
-            sn = 1.0;
-            sgv = 1.0;
-            alg4 = true;
+            rc = draw(cur.id, step, kTagChild, cur.e, (uint32_t)m, seed, key);
+            if (!EMIT) tl.pairs++;
         } else {
-            const W4 rq = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(1 + m), seed, key);
-            q = kick_sample(d, P, m, unit53(rq.a, rq.b), unit53(rq.c, rq.d));
-            arg = (2.0 * q) * phase_offset(d, m, cur.xe, P.center[m]);
-            sn = sin_det(arg);
+            J = stackJ[sp];        // saved when this frame descended into its "+" offspring
+            rc = stackR[sp];
         }
-        if (d.tdep && d.kind[m] == 0 && !alg4) {   // Remark 1: kernel at the absolute jump time
-            const double tabs = (double)step * d.dt + cur.te;
-            const double f = P.ma[m] + P.mb[m] * cos_det(P.mw[m] * tabs + P.mp[m]);
-            const double He = P.H[m] * f;
-            cm = ((2.0 * fabs(He)) / d.hbar) / (2.0 * P.gamma0);
-            sgv = He >= 0.0 ? 1.0 : -1.0;
-        }
-        const double sigma = (sn > 0.0) ? sgv : -sgv;
-        double amp = 0.0;
-        if (!SP2 && !alg4) {
-            double ua = cur.ua0;
-            if (m > 0) {
-                const W4 ra = draw(cur.id, step, kTagStep, cur.e, (uint32_t)(8 + m), seed, key);
-                ua = unit53(ra.a, ra.b);
-            }
-            if (!(ua < cm * fabs(sn))) {       // no pair: only the survivor continues
-                cur.m += 1;
-                cur.side = 0;
-                continue;
-            }
-        } else if (SP2) {
-            amp = cur.w * (cm * fabs(sn));
-        }
-        const int side = cur.side;
-        if (!EMIT && side == 0) tl.pairs++;
-        if (side == 0) { cur.side = 1; } else { cur.side = 0; cur.m += 1; }
-
-        const W4 rc = draw(cur.id, step, kTagChild, cur.e, (uint32_t)m, seed, key);
-        const uint64_t cls = ((cur.id >> 62) & 1ull) ? 3ull : 2ull;
-        const uint64_t cid = side == 0
-            ? ((cls << 62) | ((uint64_t)(rc.b & 0x3FFFFFFFu) << 32) | (uint64_t)rc.a)
-            : ((cls << 62) | ((uint64_t)(rc.d & 0x3FFFFFFFu) << 32) | (uint64_t)rc.c);
-        const double kick = sigma * q;
+        bool descend = false;
         Node ch;
-        ch.k[0] = cur.k[0];
-        ch.k[1] = cur.k[1];
-        const int ax = d.axis[m];
-        if (ax == 0) {
-            ch.k[0] = side == 0 ? cur.k[0] + kick : cur.k[0] - kick;
-        } else if (ax == 1) {
-            ch.k[1] = side == 0 ? cur.k[1] + kick : cur.k[1] - kick;
-        } else {
-            ch.k[0] = side == 0 ? cur.k[0] + kick : cur.k[0] - kick;
-            ch.k[1] = side == 0 ? cur.k[1] - kick : cur.k[1] + kick;
-        }
-        ch.sg = side == 0 ? cur.sg : -cur.sg;
-        ch.w = side == 0 ? amp : -amp;
-        ch.id = cid;
-        if (TAN) {
-            const double wd = P.width[m];
-            const double s0 = 1.0 / P.H[m];
-            const double s1 = 1.0 / wd - ((4.0 * wd) * q) * q;
-            const double s2 = -(2.0 * q) * (cos_det(arg) / sn);
-            const double sdir = side == 0 ? 1.0 : -1.0;
-            const double sgd = (double)ch.sg;
-            ch.D[0] = sdir * cur.D[0] + sgd * s0;
-            ch.D[1] = sdir * cur.D[1] + sgd * s1;
-            ch.D[2] = sdir * cur.D[2] + sgd * s2;
-        } else {
-            ch.D[0] = ch.D[1] = ch.D[2] = 0.0;
-        }
-        if (!in_kbox<DIM>(d, ch.k)) {          // k-truncation (Sec. 2)
-            if (!EMIT) {
-                if (SP2) {
-                    const int64_t q32 = (int64_t)floor(fabs(ch.w) * 4294967296.0);
-                    tl.killed += ch.w < 0.0 ? -q32 : q32;
+        for (int side = cur.side; side < 2 && !descend; ++side) {
+            make_child<SP2, TAN>(d, P, cur, m, side, J, rc, ch);
+            if (!in_kbox<DIM>(d, ch.k)) {          // k-truncation (Sec. 2)
+                if (!EMIT) tl.killed += killed_amount<SP2>(ch);
+                continue;
+            }
+            if (EMIT) {
+                const int64_t li = first_rec + nrec;
+                if (li < cap) {
+                    const int64_t o = base + li;
+                    out.x0[o] = cur.xe[0] + (d.vfac * ch.k[0]) * (d.dt - cur.te);
+                    out.k0[o] = ch.k[0];
+                    if (DIM == 2) {
+                        out.x1[o] = cur.xe[1] + (d.vfac * ch.k[1]) * (d.dt - cur.te);
+                        out.k1[o] = ch.k[1];
+                    }
+                    if (SP2) out.w[o] = ch.w; else out.sg[o] = (int8_t)ch.sg;
+                    out.id[o] = ch.id;
+                    if (TAN) {
+                        out.D[o] = ch.D[0];
+                        out.D[dstride + o] = ch.D[1];
+                        out.D[2 * dstride + o] = ch.D[2];
+                    }
                 } else {
-                    tl.killed += ch.sg;
+                    err |= kErrCapacity;
                 }
+            } else if (pooled) {
+                pooled = pool_record<DIM, SP2, TAN>(d, pl, (int)nrec, slot, cur.xe, cur.te, ch);
             }
-            continue;
-        }
-        if (EMIT) {
-            const int64_t li = first_rec + nrec;
-            if (li < cap) {
-                const int64_t o = base + li;
-                out.x0[o] = cur.xe[0] + (d.vfac * ch.k[0]) * (d.dt - cur.te);
-                out.k0[o] = ch.k[0];
-                if (DIM == 2) {
-                    out.x1[o] = cur.xe[1] + (d.vfac * ch.k[1]) * (d.dt - cur.te);
-                    out.k1[o] = ch.k[1];
-                }
-                if (SP2) out.w[o] = ch.w; else out.sg[o] = (int8_t)ch.sg;
-                out.id[o] = ch.id;
-                if (TAN) {
-                    out.D[o] = ch.D[0];
-                    out.D[dstride + o] = ch.D[1];
-                    out.D[2 * dstride + o] = ch.D[2];
-                }
-            } else {
-                err |= kErrCapacity;
-            }
-        } else if (nrec < (uint32_t)kStash) {
-            const int r = (int)nrec, l = threadIdx.x;
-            sh->x0[r][l] = cur.xe[0] + (d.vfac * ch.k[0]) * (d.dt - cur.te);
-            sh->k0[r][l] = ch.k[0];
-            if (DIM == 2) {
-                sh->x1[r][l] = cur.xe[1] + (d.vfac * ch.k[1]) * (d.dt - cur.te);
-                sh->k1[r][l] = ch.k[1];
-            }
-            if (SP2) sh->w[r][l] = ch.w; else sh->sg[r][l] = (int8_t)ch.sg;
-            sh->id[r][l] = ch.id;
-            if (TAN) {
-                sh->D[3 * r][l] = ch.D[0];
-                sh->D[3 * r + 1][l] = ch.D[1];
-                sh->D[3 * r + 2][l] = ch.D[2];
-            }
-        }
-        nrec++;
-        ch.depth = cur.depth + 1;
-        if (!EMIT && ch.depth > tl.maxdepth) tl.maxdepth = ch.depth;
-        {
+            nrec++;
+            ch.depth = cur.depth + 1;
+            if (!EMIT && ch.depth > tl.maxdepth) tl.maxdepth = ch.depth;
             // The child's first clock draw, exactly as its own walk would take
             // it: most children do not jump before the end of the step, and
             // then there is nothing to walk and the parent stays off the stack.
             const W4 r0 = draw(ch.id, step, kTagStep, 0u, 0u, seed, key);
-            const double tau0 = -ln_series(1.0 - unit53(r0.a, r0.b)) / P.gamma0;
-            if (!(cur.te + tau0 <= d.dt)) continue;
+            const double u0 = unit53(r0.a, r0.b);
+            if (surely_no_jump(u0, cur.te, d.dt, P.gamma0) ||
+                !(cur.te + (-ln_series(1.0 - u0) / P.gamma0) <= d.dt))
+                continue;
+            if (sp >= kMaxDepth) {
+                err |= kErrDepth;
+                continue;
+            }
+            // descend into the child; the parent resumes with its "-"
+            // offspring (pair kept with the frame) or its next component
+            if (side == 0) {
+                stackJ[sp] = J;
+                stackR[sp] = rc;
+                cur.side = 1;
+            } else {
+                cur.side = 0;
+                cur.m += 1;
+            }
+            descend = true;
         }
-        if (sp >= kMaxDepth) {
-            err |= kErrDepth;
+        if (!descend) {
+            cur.side = 0;
+            cur.m += 1;
             continue;
         }
         ch.x[0] = cur.xe[0];
@@ -500,13 +668,19 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
 }
 
 template <int DIM, bool SP2, bool TAN>
-__global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost)
+__global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
 {
     __shared__ int64_t s_t;
     __shared__ uint32_t s_wsum[4];
     __shared__ uint32_t s_excl;
     __shared__ int64_t s_tal[5];
+    __shared__ uint32_t s_nslow;
+    __shared__ uint16_t s_slow[kTileB];      // slots whose family needs the general walk
+    __shared__ uint32_t s_cnt[kTileB];       // their record counts
+    __shared__ int64_t s_first[kTileB];      // output offset of every slot's first record
+    __shared__ uint8_t s_pooled[kTileB];     // all records of the slot's general walk are pooled
     __shared__ Stash<DIM, SP2, TAN> s_stash;
+    __shared__ Pool<DIM, SP2, TAN> s_pool;
 
     Ctl *ctl = d.ctl;
     const uint32_t step = ctl->step;
@@ -525,13 +699,54 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t err = 0;
 
+    // the event parent of tile position `slot`, at the start of the step
+    auto load_root = [&](int64_t base, int64_t j0, int slot) {
+        Node root;
+        const int64_t pos = base + j0 + slot;
+        const int64_t i = base + (int64_t)evi[pos];
+        root.x[0] = evx0[pos];
+        root.x[1] = DIM == 2 ? evx1[pos] : 0.0;
+        root.k[0] = E.k0[i];
+        root.k[1] = DIM == 2 ? E.k1[i] : 0.0;
+        root.t0 = 0.0;
+        root.id = E.id[i];
+        root.w = SP2 ? E.w[i] : 0.0;
+        root.sg = SP2 ? 0 : (int32_t)E.sg[i];
+        if (TAN) {
+            root.D[0] = E.D[i];
+            root.D[1] = E.D[dstride + i];
+            root.D[2] = E.D[2 * dstride + i];
+        } else {
+            root.D[0] = root.D[1] = root.D[2] = 0.0;
+        }
+        return root;
+    };
+
+    // Tallies stay in LDS while the block works on one instance; they go to
+    // the instance's counters when the block moves on to another one, and the
+    // last instance's share is left in the block's slot of fpart for the
+    // closing launch.  Per-tile atomics on one cache line would serialise
+    // the whole grid.
+    int cb = -1;
+    if (tid < 5) s_tal[tid] = 0;
     for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[pass], ntiles);
-        if (tid < 5) s_tal[tid] = 0;
+        if (tid == 0) { s_t = next_tile(&ctl->ticket[pass], ntiles); s_nslow = 0; s_pool.n = 0; }
         __syncthreads();
         const int64_t t = s_t;
         if (t >= ntiles) break;
         const int b = segment_of(plan, B, t);
+        if (b != cb) {
+            if (tid == 0 && cb >= 0) {
+                int64_t *T = d.tally + (int64_t)cb * kTalCount;
+                if (s_tal[0]) atomicAdd((unsigned long long *)&T[kTalEvents], (unsigned long long)s_tal[0]);
+                if (s_tal[1]) atomicAdd((unsigned long long *)&T[kTalPairs], (unsigned long long)s_tal[1]);
+                if (s_tal[2]) atomicAdd((unsigned long long *)&T[kTalKilled], (unsigned long long)s_tal[2]);
+                if (s_tal[3]) atomicAdd((unsigned long long *)&T[kTalEventCap], (unsigned long long)s_tal[3]);
+                if (s_tal[4]) atomicMax((unsigned long long *)&T[kTalMaxDepth], (unsigned long long)s_tal[4]);
+                for (int q = 0; q < 5; ++q) s_tal[q] = 0;
+            }
+            cb = b;
+        }
         const int64_t first = plan[b];
         const int64_t tl_i = t - first;
         const int64_t last = plan[b + 1] - 1;
@@ -540,36 +755,36 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost)
         const int64_t cap = ghost ? P.gcap : P.cap;
         const int64_t nev = d.evc[(int64_t)ghost * B + b];
         const int64_t n_before = Ncur[b];
-        const int64_t j = tl_i * kTileB + tid;
-        const bool ok = j < nev;
+        const int64_t j0 = tl_i * kTileB;
+        const bool ok = j0 + tid < nev;
 
-        Node root;
-        root.x[0] = root.x[1] = root.k[0] = root.k[1] = 0.0;
-        root.t0 = 0.0;
-        root.w = 0.0;
-        root.D[0] = root.D[1] = root.D[2] = 0.0;
-        root.id = 0;
-        root.sg = 0;
-        if (ok) {
-            const int64_t pos = base + j;
-            const int64_t i = base + (int64_t)evi[pos];
-            root.x[0] = evx0[pos];
-            root.k[0] = E.k0[i];
-            if (DIM == 2) { root.x[1] = evx1[pos]; root.k[1] = E.k1[i]; }
-            root.id = E.id[i];
-            if (SP2) root.w = E.w[i]; else root.sg = (int32_t)E.sg[i];
-            if (TAN) {
-                root.D[0] = E.D[i];
-                root.D[1] = E.D[dstride + i];
-                root.D[2] = E.D[2 * dstride + i];
-            }
-        }
+        // 1. every family in lockstep on the common path
         Tally tal{0, 0, 0, 0, 0};
         uint32_t cnt = 0;
-        if (ok) cnt = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal, err,
-                                                        &s_stash);
+        bool slow = false;
+        if (ok) {
+            const Node root = load_root(base, j0, tid);
+            slow = !fast_family<DIM, SP2, TAN>(d, P, step, root, &s_stash, tid, cnt, tal);
+        }
+        if (slow) {
+            tal = Tally{0, 0, 0, 0, 0};
+            s_slow[atomicAdd(&s_nslow, 1u)] = (uint16_t)tid;
+        }
+        __syncthreads();
+        // 2. the rest walked in full, spread over the block's threads
+        const int nslow = (int)s_nslow;
+        for (int k = tid; k < nslow; k += kThreads) {
+            const int slot = s_slow[k];
+            const Node root = load_root(base, j0, slot);
+            bool pooled = true;
+            s_cnt[slot] = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal,
+                                                            err, &s_pool, slot, pooled);
+            s_pooled[slot] = pooled ? 1 : 0;
+        }
+        __syncthreads();
+        if (slow) cnt = s_cnt[tid];
 
-        // ordered exclusive scan of the record counts over the tile
+        // 3. ordered exclusive scan of the record counts over the tile
         uint32_t incl = cnt;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -592,10 +807,11 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost)
         }
         __syncthreads();
         const int64_t my_first = n_before + (int64_t)s_excl + (int64_t)(woff + incl - cnt);
-        if (ok && cnt > (uint32_t)kStash) {
-            walk_family<DIM, SP2, TAN, true>(d, P, step, root, E, base, my_first, cap, dstride, tal, err,
-                                             &s_stash);
-        } else if (ok) {
+        s_first[tid] = my_first;
+
+        // 4. records: from the stash and the pool, or by a second full walk
+        //    for a family whose records overflowed the pool
+        if (ok && !slow) {
             for (uint32_t r = 0; r < cnt; ++r) {
                 const int64_t li = my_first + r;
                 if (li >= cap) { err |= kErrCapacity; continue; }
@@ -615,6 +831,37 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost)
                 }
             }
         }
+        __syncthreads();
+        const int npool = (int)min(s_pool.n, (uint32_t)kPool);
+        for (int r = tid; r < npool; r += kThreads) {
+            const int slot = s_pool.slot[r];
+            if (!s_pooled[slot]) continue;
+            const int64_t li = s_first[slot] + s_pool.rank[r];
+            if (li >= cap) { err |= kErrCapacity; continue; }
+            const int64_t o = base + li;
+            E.x0[o] = s_pool.x0[r];
+            E.k0[o] = s_pool.k0[r];
+            if (DIM == 2) {
+                E.x1[o] = s_pool.x1[r];
+                E.k1[o] = s_pool.k1[r];
+            }
+            if (SP2) E.w[o] = s_pool.w[r]; else E.sg[o] = s_pool.sg[r];
+            E.id[o] = s_pool.id[r];
+            if (TAN) {
+                E.D[o] = s_pool.D[0][r];
+                E.D[dstride + o] = s_pool.D[1][r];
+                E.D[2 * dstride + o] = s_pool.D[2][r];
+            }
+        }
+        for (int k = tid; k < nslow; k += kThreads) {
+            const int slot = s_slow[k];
+            if (s_pooled[slot]) continue;
+            const Node root = load_root(base, j0, slot);
+            Tally none{0, 0, 0, 0, 0};
+            bool unused = false;
+            walk_family<DIM, SP2, TAN, true>(d, P, step, root, E, base, s_first[slot], cap, dstride, none, err,
+                                             &s_pool, slot, unused);
+        }
 
         // per-instance tallies
         if (tal.events) atomicAdd((unsigned long long *)&s_tal[0], (unsigned long long)tal.events);
@@ -623,30 +870,36 @@ __global__ __launch_bounds__(kThreads) void k_family(Dev d, int ghost)
         if (tal.cap) atomicAdd((unsigned long long *)&s_tal[3], (unsigned long long)tal.cap);
         if (tal.maxdepth) atomicMax((unsigned long long *)&s_tal[4], (unsigned long long)tal.maxdepth);
         __syncthreads();
-        if (tid == 0) {
-            int64_t *T = d.tally + (int64_t)b * kTalCount;
-            if (s_tal[0]) atomicAdd((unsigned long long *)&T[kTalEvents], (unsigned long long)s_tal[0]);
-            if (s_tal[1]) atomicAdd((unsigned long long *)&T[kTalPairs], (unsigned long long)s_tal[1]);
-            if (s_tal[2]) atomicAdd((unsigned long long *)&T[kTalKilled], (unsigned long long)s_tal[2]);
-            if (s_tal[3]) atomicAdd((unsigned long long *)&T[kTalEventCap], (unsigned long long)s_tal[3]);
-            if (s_tal[4]) atomicMax((unsigned long long *)&T[kTalMaxDepth], (unsigned long long)s_tal[4]);
-        }
-        __syncthreads();
+    }
+    if (tid == 0) {
+        int64_t *F = d.fpart + (int64_t)blockIdx.x * 8;
+        F[0] = cb;
+        for (int q = 0; q < 5; ++q) F[1 + q] = s_tal[q];
     }
     if (err) atomicOr(&ctl->err, err);
-
 }
 
-// After k_family (one block): the new particle counts with the capacity
-// clamp, cleared event and record counts, the streaming-tile plan of the
-// next step, and the step counter.
-__global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int advance)
+// After k_family (one block): the family blocks' tallies, the new particle
+// counts with the capacity clamp, cleared event and record counts, the
+// streaming-tile plan of the next step, and the step counter.
+__global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int advance, int fgrid)
 {
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const uint32_t step = ctl->step;
     int64_t *Ncur = ghost ? d.NG : d.N;
     const int tid = threadIdx.x;
+    // the family blocks' last tallies
+    for (int g = tid; g < fgrid; g += kThreads) {
+        const int64_t *F = d.fpart + (int64_t)g * 8;
+        if (F[0] < 0) continue;
+        int64_t *T = d.tally + F[0] * kTalCount;
+        if (F[1]) atomicAdd((unsigned long long *)&T[kTalEvents], (unsigned long long)F[1]);
+        if (F[2]) atomicAdd((unsigned long long *)&T[kTalPairs], (unsigned long long)F[2]);
+        if (F[3]) atomicAdd((unsigned long long *)&T[kTalKilled], (unsigned long long)F[3]);
+        if (F[4]) atomicAdd((unsigned long long *)&T[kTalEventCap], (unsigned long long)F[4]);
+        if (F[5]) atomicMax((unsigned long long *)&T[kTalMaxDepth], (unsigned long long)F[5]);
+    }
     int64_t *chc = d.chc + (int64_t)ghost * B;
     int64_t *evc = d.evc + (int64_t)ghost * B;
     for (int b = tid; b < B; b += kThreads) {
