@@ -32,8 +32,8 @@ struct Layout {
     size_t ens[2][8] = {}, gens[2][8] = {};
     size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
     size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, chc = 0, tileA = 0, tileB = 0, tileR = 0,
-           tileG = 0, tally = 0, fpart = 0, ev_idx = 0, ev_x0 = 0, ev_x1 = 0, gev_idx = 0, gev_x0 = 0,
-           gev_x1 = 0, stA = 0, stAg = 0, stB = 0, stBg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
+           tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
+           tcA = 0, tcAg = 0, emA = 0, emAg = 0, stB = 0, stBg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
            bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0, xitab = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
@@ -122,6 +122,7 @@ Layout make_layout(const wbrw_config *c)
         L.tilesA += ceil_div(c->capacity[b], kTileA) + 1;
         L.tilesB += ceil_div(c->capacity[b], kTileB) + 1;
         L.tilesP += ceil_div(c->capacity[b], kTileS) + 1;
+        L.rtiles += ceil_div(c->capacity[b], kTileR) + 1;
         if (tan) {
             L.gcap_total += c->ghost_capacity;
             L.tilesAg += ceil_div(c->ghost_capacity, kTileA) + 1;
@@ -151,12 +152,7 @@ Layout make_layout(const wbrw_config *c)
         }
     }
     L.ev_idx = take(cur, C * 4);
-    L.ev_x0 = take(cur, C * 8);
-    L.ev_x1 = c->dim == 2 ? take(cur, C * 8) : 0;
-    if (tan) {
-        L.gev_idx = take(cur, G * 4);
-        L.gev_x0 = take(cur, G * 8);
-    }
+    if (tan) L.gev_idx = take(cur, G * 4);
     L.ip = take(cur, BB * sizeof(InstParam));
     for (int m = 0; m < c->n_components; ++m)
         if (c->comp[m].kind == WBRW_KERNEL_TABLE) L.tab[m] = take(cur, ((size_t)c->comp[m].table_n + 1) * 8);
@@ -188,10 +184,13 @@ Layout make_layout(const wbrw_config *c)
     L.tileG = take(cur, (BB + 1) * 8);
     L.tally = take(cur, BB * kTalCount * 8);
     L.fpart = take(cur, (size_t)kMaxGrid * 8 * 8);
-    L.stA = take(cur, (size_t)L.tilesA * 8);
+    L.rstart = take(cur, (size_t)L.rtiles * 8);
+    L.tcA = take(cur, (size_t)L.tilesA * 8);
+    L.emA = take(cur, (size_t)L.tilesA * kPPT * 4 * 8);
     L.stB = take(cur, (size_t)L.tilesB * 8);
     if (tan) {
-        L.stAg = take(cur, (size_t)L.tilesAg * 8);
+        L.tcAg = take(cur, (size_t)L.tilesAg * 8);
+        L.emAg = take(cur, (size_t)L.tilesAg * kPPT * 4 * 8);
         L.stBg = take(cur, (size_t)L.tilesBg * 8);
         L.stG = take(cur, (size_t)L.tilesS * 8);
     }
@@ -251,7 +250,7 @@ namespace {
 template <typename T>
 T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off); }
 
-enum { G_STREAM = 0, G_FAMILY, G_BIN, G_SCAN, G_REGEN, G_DENS, G_SP2, G_GHOST };
+enum { G_STREAM = 0, G_FAMILY, G_BIN, G_SCAN, G_REGEN, G_DENS, G_SP2, G_GHOST, G_EVENTS, G_COUNT };
 
 template <typename K>
 int persistent_blocks(K kernel, int cus)
@@ -376,6 +375,7 @@ void enqueue_step_dim(wbrw_t h)
     hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
     hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 0);
+    hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
     stage_begin(h, WBRW_STAGE_FAMILY);
     if (h->strategy == WBRW_SP2)
         hipLaunchKernelGGL((k_family<DIM, true, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
@@ -389,6 +389,7 @@ void enqueue_step_dim(wbrw_t h)
         stage_begin(h, WBRW_STAGE_GHOST);
         hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 1, 1, h->grid[G_FAMILY]);
         stage_end(h);
@@ -477,6 +478,7 @@ void set_grids_dim(wbrw_t h)
     h->grid[G_DENS] = persistent_blocks(k_density_bin<DIM, false, false>, cus);
     h->grid[G_SP2] = persistent_blocks(k_sp2_classify<DIM>, cus);
     h->grid[G_GHOST] = persistent_blocks(k_ghosts, cus);
+    h->grid[G_EVENTS] = persistent_blocks(k_events, cus);
 }
 
 }  // namespace
@@ -582,12 +584,15 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         d.tab[m].dq = dq;
     }
     h->ip.resize(h->B);
-    int64_t base = 0, gbase = 0;
+    int64_t base = 0, gbase = 0, rbase = 0;
     for (int b = 0; b < h->B; ++b) {
         derive(cfg, b, xi_tab, h->ip[b]);
         h->ip[b].base = base;
         h->ip[b].cap = cfg->capacity[b];
         base += cfg->capacity[b];
+        h->ip[b].rbase = rbase;
+        h->ip[b].rtiles = ceil_div(cfg->capacity[b], kTileR) + 1;
+        rbase += h->ip[b].rtiles;
         if (h->tangent) {
             h->ip[b].gbase = gbase;
             h->ip[b].gcap = cfg->ghost_capacity;
@@ -638,15 +643,14 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.tileG = at<int64_t>(w, L.tileG);
     d.tally = at<int64_t>(w, L.tally);
     d.fpart = at<int64_t>(w, L.fpart);
+    d.rstart = at<int64_t>(w, L.rstart);
     d.ev_idx = at<uint32_t>(w, L.ev_idx);
-    d.ev_x0 = at<double>(w, L.ev_x0);
-    d.ev_x1 = cfg->dim == 2 ? at<double>(w, L.ev_x1) : nullptr;
     d.gev_idx = h->tangent ? at<uint32_t>(w, L.gev_idx) : nullptr;
-    d.gev_x0 = h->tangent ? at<double>(w, L.gev_x0) : nullptr;
-    d.gev_x1 = nullptr;
-    d.stA = at<uint64_t>(w, L.stA);
+    d.tcA = at<uint64_t>(w, L.tcA);
+    d.emA = at<uint64_t>(w, L.emA);
     d.stB = at<uint64_t>(w, L.stB);
-    d.stAg = h->tangent ? at<uint64_t>(w, L.stAg) : nullptr;
+    d.tcAg = h->tangent ? at<uint64_t>(w, L.tcAg) : nullptr;
+    d.emAg = h->tangent ? at<uint64_t>(w, L.emAg) : nullptr;
     d.stBg = h->tangent ? at<uint64_t>(w, L.stBg) : nullptr;
     d.stG = h->tangent ? at<uint64_t>(w, L.stG) : nullptr;
     d.stS = at<uint64_t>(w, L.stS);

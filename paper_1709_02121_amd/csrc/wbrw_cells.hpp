@@ -173,7 +173,6 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     // equal cells are close in the array but not adjacent; the table finds
     // them anyway.  A particle whose probes all fail adds directly.
     constexpr int kSlots = 4096;
-    __shared__ int64_t s_t;
     __shared__ int64_t s_esc;
     __shared__ int32_t s_key[TAN ? 1 : kSlots];
     __shared__ int32_t s_val[TAN ? 1 : kSlots];
@@ -186,11 +185,9 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     const int tid = threadIdx.x;
     if (!TAN)
         for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
-    for (;;) {
-        if (tid == 0) { s_t = next_tile(&ctl->ticket[kPassTiles], ntiles); s_esc = 0; }
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        if (tid == 0) s_esc = 0;
         __syncthreads();
-        const int64_t t = s_t;
-        if (t >= ntiles) break;
         const int b = segment_of(plan, B, t);
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
@@ -328,12 +325,19 @@ __global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
         }
         __syncthreads();
         int64_t run = (int64_t)s_excl + (int64_t)(woff + incl - sum);
+        const InstParam &P = d.ip[b];
+        int64_t *rst = d.rstart + P.rbase;
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const int64_t c = c0 + j;
             if (c < d.Nh) {
+                const int64_t a = v[j] < 0 ? -v[j] : v[j];
                 d.off[cbase + c] = run | (v[j] < 0 ? kOffNeg : 0);
-                run += (v[j] < 0 ? -v[j] : v[j]);
+                // this cell holds the first output of every regeneration tile
+                // that starts inside [run, run + a)
+                for (int64_t q = (run + kTileR - 1) / kTileR; q * kTileR < run + a && q < P.rtiles; ++q)
+                    rst[q] = c;
+                run += a;
                 if (zero_counts && v[j] != 0) d.cnt[cbase + c] = 0;
             }
         }
@@ -356,10 +360,9 @@ __global__ __launch_bounds__(kThreads) void k_close_scan(Dev d)
     block_plan(d.tileR, d.Nnew, B, kTileR);
 }
 
-// largest cell nu with (off[nu] & mask) <= o
-__device__ __forceinline__ int64_t cell_of_output(const int64_t *off, int64_t Nh, int64_t o)
+// largest cell nu in [lo, hi] with (off[nu] & mask) <= o
+__device__ __forceinline__ int64_t cell_of_output(const int64_t *off, int64_t lo, int64_t hi, int64_t o)
 {
-    int64_t lo = 0, hi = Nh - 1;
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
         if ((off[mid] & kOffMask) <= o) lo = mid; else hi = mid - 1;
@@ -373,28 +376,29 @@ __device__ __forceinline__ int64_t cell_of_output(const int64_t *off, int64_t Nh
 template <int DIM, bool SP2, bool TAN>
 __global__ __launch_bounds__(kThreads) void k_regen(Dev d)
 {
-    __shared__ int64_t s_t;
     Ctl *ctl = d.ctl;
     const uint32_t step = ctl->step;
     const int B = d.B;
     const int64_t ntiles = d.tileR[B];
     const Ens O = pick_set(d, 0, ctl->cur ^ 1u);
     const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassRegen], ntiles);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         __syncthreads();
-        const int64_t t = s_t;
-        __syncthreads();
-        if (t >= ntiles) break;
         const int b = segment_of(d.tileR, B, t);
         const InstParam &P = d.ip[b];
         const int64_t nout = d.Nnew[b];
         const int64_t cbase = (int64_t)b * d.Nh;
         const int64_t *off = d.off + cbase;
+        // the tile's outputs lie in cells [first cell of this tile, first
+        // cell of the next one] (the scan recorded both), so each search
+        // covers a few cells where the ensemble is dense
+        const int64_t q = t - d.tileR[b];
+        const int64_t nu_lo = d.rstart[P.rbase + q];
+        const int64_t nu_hi = (q + 1) * kTileR < nout ? d.rstart[P.rbase + q + 1] : d.Nh - 1;
         for (int j = 0; j < kTileR / kThreads; ++j) {
-            const int64_t o = (t - d.tileR[b]) * kTileR + (int64_t)j * kThreads + tid;
+            const int64_t o = q * kTileR + (int64_t)j * kThreads + tid;
             if (o >= nout) break;
-            const int64_t nu = cell_of_output(off, d.Nh, o);
+            const int64_t nu = cell_of_output(off, nu_lo, nu_hi, o);
             const int64_t onu = off[nu];
             const int64_t jj = o - (onu & kOffMask);
             const uint64_t id = ((uint64_t)nu << 32) | (uint64_t)jj;
@@ -447,7 +451,6 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
     // Integer weights (signs, 32.32 fixed-point weights) sum exactly in any
     // order.  Histograms wider than the LDS array go straight to HBM.
     constexpr int kLds = 4096;
-    __shared__ int64_t s_t;
     __shared__ uint64_t s_raw[kLds];
     double *s_d = reinterpret_cast<double *>(s_raw);
     Ctl *ctl = d.ctl;
@@ -480,12 +483,8 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
         }
         __syncthreads();
     };
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         __syncthreads();
-        const int64_t t = s_t;
-        __syncthreads();
-        if (t >= ntiles) break;
         const int b = segment_of(plan, B, t);
         if (priv && b != cb) {
             if (cb >= 0) flush(cb);
@@ -577,7 +576,6 @@ __global__ __launch_bounds__(kThreads) void k_density_out(Dev d, int nbins, doub
 __global__ __launch_bounds__(kThreads) void k_vjp(Dev d, int ghost, int nbins, double lo, double dxb,
                                                   const double *g, double *acc)
 {
-    __shared__ int64_t s_t;
     __shared__ double s_sum[3][kThreads / 64];
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -587,11 +585,8 @@ __global__ __launch_bounds__(kThreads) void k_vjp(Dev d, int ghost, int nbins, d
     const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
     const int64_t ds = ghost ? d.gcap_total : d.cap_total;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         __syncthreads();
-        const int64_t t = s_t;
-        if (t >= ntiles) break;
         const int b = segment_of(plan, B, t);
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;

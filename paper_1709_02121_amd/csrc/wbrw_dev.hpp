@@ -54,6 +54,7 @@ struct InstParam {
     int64_t base, cap;              // particle segment
     int64_t gbase, gcap;            // ghost segment
     int64_t N0;                     // sample size N_alpha
+    int64_t rbase, rtiles;          // this instance's slots in Dev::rstart
     uint32_t key;                   // Philox key word 1
     uint32_t pad;
 };
@@ -110,11 +111,12 @@ struct Dev {
     int64_t *tileG;             // [B+1] ghost-regeneration plan
     int64_t *tally;             // [B][kTalCount]
     int64_t *fpart;             // [kMaxGrid][8]: instance and tallies of each family block
+    int64_t *rstart;            // first cell of every regeneration tile (written by k_scan)
     uint32_t *ev_idx;           // [cap_total] event-parent index within its instance
-    double *ev_x0, *ev_x1;      // [cap_total] its position at the start of the step
     uint32_t *gev_idx;          // ghosts
-    double *gev_x0, *gev_x1;
-    uint64_t *stA, *stAg, *stB, *stBg, *stS, *stG;   // look-back status words
+    uint64_t *stB, *stBg, *stS, *stG;   // look-back status words
+    uint64_t *tcA, *tcAg;               // per streaming tile: event count, then its prefix
+    uint64_t *emA, *emAg;               // per streaming tile: kPPT x 4 wavefront event ballots
     int32_t *cnt;               // [B][Nh] signed counts (sp1) / rounded counts (sp2)
     int64_t *off;               // [B][Nh] exclusive prefix of |n_nu|, bit 62 = negative cell
     int32_t *occ;               // [B][Nh] occupancy (tangents)

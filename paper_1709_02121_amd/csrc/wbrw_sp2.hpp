@@ -51,7 +51,6 @@ __device__ __forceinline__ u128 ld128(const uint64_t *p)
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
 {
-    __shared__ int64_t s_t;
     __shared__ unsigned long long s_acc[5];   // N0, N1, S0, S1, escaped
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -59,12 +58,9 @@ __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
     const int64_t ntiles = plan[B];
     const Ens E = pick_set(d, 0, ctl->cur);
     const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         if (tid < 5) s_acc[tid] = 0ull;
         __syncthreads();
-        const int64_t t = s_t;
-        if (t >= ntiles) break;
         const int b = segment_of(plan, B, t);
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
@@ -110,7 +106,6 @@ __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
 // ---- stage 2: kept copies k_i, residuals r_i, per-tile residual sums --------
 __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
 {
-    __shared__ int64_t s_t;
     __shared__ unsigned long long s_acc[6];    // sumk0, sumk1, tile sums (lo,hi) x 2
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -118,12 +113,9 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
     const int64_t ntiles = plan[B];
     const int tid = threadIdx.x;
     const int64_t C = d.cap_total;
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         if (tid < 6) s_acc[tid] = 0ull;
         __syncthreads();
-        const int64_t t = s_t;
-        if (t >= ntiles) break;
         const int b = segment_of(plan, B, t);
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
@@ -236,7 +228,6 @@ __global__ __launch_bounds__(kThreads) void k_close_sp2_tilescan(Dev d)
 // ---- stage 4: per-particle exclusive prefixes P_0, P_1 (128-bit) -----------
 __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
 {
-    __shared__ int64_t s_t;
     __shared__ uint64_t s_lo[2][kThreads], s_hi[2][kThreads];
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -244,11 +235,8 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
     const int64_t ntiles = plan[B];
     const int64_t C = d.cap_total;
     const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         __syncthreads();
-        const int64_t t = s_t;
-        if (t >= ntiles) break;
         const int b = segment_of(plan, B, t);
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
@@ -302,19 +290,14 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
 // ---- stage 5: the N_r i.i.d. draws of each class (Alg. 2 step 2) ------------
 __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
 {
-    __shared__ int64_t s_t;
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const uint32_t step = ctl->step;
     const int64_t n0 = d.tileD[B], ntiles = n0 + d.tileD[2 * B + 1];
     const int64_t C = d.cap_total;
     const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         __syncthreads();
-        const int64_t t = s_t;
-        __syncthreads();
-        if (t >= ntiles) break;
         const int c = t < n0 ? 0 : 1;
         const int64_t *plan = d.tileD + (int64_t)c * (B + 1);
         const int64_t tc = t - (c ? n0 : 0);
@@ -344,19 +327,14 @@ __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
 // ---- stage 6: filtered counts per cell and class ---------------------------
 __global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
 {
-    __shared__ int64_t s_t;
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t *plan = d.tileA;
     const int64_t ntiles = plan[B];
     const int tid = threadIdx.x;
     const int64_t plane = (int64_t)B * d.Nh;
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassTiles], ntiles);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         __syncthreads();
-        const int64_t t = s_t;
-        __syncthreads();
-        if (t >= ntiles) break;
         const int b = segment_of(plan, B, t);
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];

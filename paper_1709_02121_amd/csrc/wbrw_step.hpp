@@ -5,8 +5,8 @@
 // (exact for a constant gamma0, Sec. 3.2.1), moves freely to the end of the
 // step (a particle keeps its k after a jump: offspring 2M+1 of Alg. 1, so its
 // end position does not depend on its jumps) and, if its first jump falls
-// inside the step, is appended to an ordered per-instance event list together
-// with its start position.  Ordering uses a wavefront ballot, an LDS scan over
+// inside the step, is appended to an ordered per-instance event list (and
+// keeps its start position until its family has been walked).  Ordering uses a wavefront ballot, an LDS scan over
 // the block and a decoupled look-back across tiles.  Only the first of the
 // two uniforms decides, and only a 1e-9-wide band around the threshold
 // evaluates the logarithm.
@@ -96,40 +96,30 @@ __device__ __forceinline__ bool in_kbox(const Dev &d, const double *k)
 }
 
 // ---------------------------------------------------------------------------
-// Pass 1: streaming clock test + free flight + ordered event compaction
+// Pass 1: streaming clock test + free flight; the event flags of every tile
+// are kept as wavefront ballots, and the tile's event count is stored.
+// No tile waits for another: tiles are assigned statically and the ordered
+// event list is built by k_close_stream (scan of the tile counts) and
+// k_events (expansion of the ballots).
 // ---------------------------------------------------------------------------
 template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_stream(Dev d, int ghost)
+__global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
 {
-    __shared__ int64_t s_t;
-    __shared__ uint32_t s_wcnt[kPPT * 4];
-    __shared__ uint32_t s_woff[kPPT * 4];
-    __shared__ uint32_t s_excl;
-
-    Ctl *ctl = d.ctl;
+    __shared__ uint32_t s_wcnt[4];
+    const Ctl *ctl = d.ctl;
     const uint32_t step = ctl->step;
-    const uint32_t epoch = 2u * step + (uint32_t)ghost + 1u;
     const int B = d.B;
     const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
     const int64_t ntiles = plan[B];
     const int64_t *Ncur = ghost ? d.NG : d.N;
     const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
-    uint64_t *st = ghost ? d.stAg : d.stA;
-    uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
-    double *evx0 = ghost ? d.gev_x0 : d.ev_x0;
-    double *evx1 = ghost ? d.gev_x1 : d.ev_x1;
-    const int pass = ghost ? kPassStreamG : kPassStream;
+    uint64_t *tcnt = ghost ? d.tcAg : d.tcA;
+    uint64_t *emask = ghost ? d.emAg : d.emA;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[pass], ntiles);
-        __syncthreads();
-        const int64_t t = s_t;
-        if (t >= ntiles) break;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int b = segment_of(plan, B, t);
-        const int64_t first = plan[b];
-        const int64_t tl = t - first;
-        const int64_t last = plan[b + 1] - 1;
+        const int64_t tl = t - plan[b];
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t n = Ncur[b];
@@ -163,8 +153,8 @@ __global__ __launch_bounds__(kThreads) void k_stream(Dev d, int ghost)
                 if (DIM == 2) { xs1[j] = E.x1[i]; kv1[j] = E.k1[i]; }
             }
         }
-        uint32_t rank[kPPT];
-        uint32_t evbits = 0;
+        uint32_t evbits = 0, nev = 0;
+        uint64_t *em = emask + t * (kPPT * 4);
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const bool valid = full || (li0 + (int64_t)j * kThreads < n);
@@ -180,65 +170,120 @@ __global__ __launch_bounds__(kThreads) void k_stream(Dev d, int ghost)
             }
             ev = ev && valid;
             const uint64_t m = __ballot(ev);
-            rank[j] = lane_rank(m);
-            if (lane == 0) s_wcnt[j * 4 + wv] = (uint32_t)__popcll(m);
+            if (lane == 0) em[j * 4 + wv] = m;
+            nev += (uint32_t)__popcll(m);
             evbits |= (ev ? 1u : 0u) << j;
         }
-        // free flight to the end of the step
+        // free flight to the end of the step; an event parent keeps its
+        // start position, which its family walk needs, and k_family moves it
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const int64_t li = li0 + (int64_t)j * kThreads;
-            if (full || li < n) {
+            if ((full || li < n) && !((evbits >> j) & 1u)) {
                 const int64_t i = base + li;
                 E.x0[i] = xs0[j] + (d.vfac * kv0[j]) * d.dt;
                 if (DIM == 2) E.x1[i] = xs1[j] + (d.vfac * kv1[j]) * d.dt;
             }
         }
+        if (lane == 0) s_wcnt[wv] = nev;
         __syncthreads();
-        if (wv == 0) {
-            // exclusive scan of the kPPT x 4 wave counts, in (j, wave) order
-            static_assert(kPPT * 4 <= 64, "one lane per (particle slot, wave)");
-            const uint32_t c = lane < kPPT * 4 ? s_wcnt[lane] : 0u;
-            uint32_t inc = c;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t v = __shfl_up(inc, o, 64);
-                if (lane >= o) inc += v;
-            }
-            if (lane < kPPT * 4) s_woff[lane] = inc - c;
-            const uint32_t acc = __shfl(inc, 63, 64);
-            const uint32_t excl = tile_prefix(st, t, first, epoch, acc);
-            if (lane == 0) {
-                if (t == last) d.evc[(int64_t)ghost * B + b] = (int64_t)(excl + acc);
-                s_excl = excl;
-            }
-        }
-        __syncthreads();
-        const uint32_t ex = s_excl;
-#pragma unroll
-        for (int j = 0; j < kPPT; ++j) {
-            if ((evbits >> j) & 1u) {
-                const int64_t pos = base + ex + s_woff[j * 4 + wv] + rank[j];
-                evi[pos] = (uint32_t)(tl * kTileA + (int64_t)j * kThreads + tid);
-                evx0[pos] = xs0[j];
-                if (DIM == 2) evx1[pos] = xs1[j];
-            }
-        }
+        if (tid == 0) tcnt[t] = (uint64_t)(s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3]);
         __syncthreads();
     }
-
 }
 
-// After k_stream (one block): the family-tile plan from the event counts,
-// cleared record counts, and the particle-step tally.
+// After k_stream (one block): exclusive scan of the tile event counts over
+// all tiles (in place), the event count of every instance, the family-tile
+// plan, cleared record counts, and the particle-step tally.
 __global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
 {
+    __shared__ uint64_t s_sum[kThreads];
     const int B = d.B;
+    const int tid = threadIdx.x;
+    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
     const int64_t *Ncur = ghost ? d.NG : d.N;
-    block_plan(d.tileB + (int64_t)ghost * (B + 1), d.evc + (int64_t)ghost * B, B, kTileB);
-    for (int b = threadIdx.x; b < B; b += kThreads) {
+    uint64_t *tc = ghost ? d.tcAg : d.tcA;
+    int64_t *evc = d.evc + (int64_t)ghost * B;
+    const int64_t T = plan[B];
+    // thread tid scans the contiguous chunk [c0, c1) of tiles; its loads are
+    // independent of each other, so they are issued together
+    const int64_t per = (T + kThreads - 1) / kThreads;
+    const int64_t c0 = min((int64_t)tid * per, T), c1 = min(c0 + per, T);
+    uint64_t acc = 0;
+#pragma unroll 16
+    for (int64_t q = c0; q < c1; ++q) acc += tc[q];
+    s_sum[tid] = acc;
+    __syncthreads();
+    for (int o = 1; o < kThreads; o <<= 1) {
+        const uint64_t v = tid >= o ? s_sum[tid - o] : 0ull;
+        __syncthreads();
+        s_sum[tid] += v;
+        __syncthreads();
+    }
+    uint64_t run = s_sum[tid] - acc;
+#pragma unroll 16
+    for (int64_t q = c0; q < c1; ++q) {
+        const uint64_t c = tc[q];
+        tc[q] = run;
+        run += c;
+    }
+    __syncthreads();
+    const uint64_t total = s_sum[kThreads - 1];
+    for (int b = tid; b < B; b += kThreads) {
+        const uint64_t lo = plan[b] < T ? tc[plan[b]] : total;
+        const uint64_t hi = plan[b + 1] < T ? tc[plan[b + 1]] : total;
+        evc[b] = (int64_t)(hi - lo);
+    }
+    __syncthreads();
+    block_plan(d.tileB + (int64_t)ghost * (B + 1), evc, B, kTileB);
+    for (int b = tid; b < B; b += kThreads) {
         d.chc[(int64_t)ghost * B + b] = 0;
         if (!ghost) d.tally[(int64_t)b * kTalCount + kTalPSteps] += Ncur[b];
+    }
+}
+
+// After k_close_stream: the ordered event list.  Every streaming tile turns
+// its ballots into the within-instance indices of its event parents, at the
+// tile's offset in its instance's list (order: particle slot, wavefront,
+// lane, as in the particle array).
+__global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost)
+{
+    const int B = d.B;
+    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
+    const int64_t ntiles = plan[B];
+    const uint64_t *tc = ghost ? d.tcAg : d.tcA;
+    const uint64_t *emask = ghost ? d.emAg : d.emA;
+    uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    static_assert(kPPT * 4 <= 64, "one lane per (particle slot, wavefront) ballot");
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int b = segment_of(plan, B, t);
+        const int64_t tl = t - plan[b];
+        const InstParam &P = d.ip[b];
+        const int64_t base = ghost ? P.gbase : P.base;
+        const uint64_t rel = tc[t] - tc[plan[b]];
+        // exclusive scan of the ballot popcounts in (slot, wave) order, by
+        // each wave for itself
+        const uint64_t *em = emask + t * (kPPT * 4);
+        const uint64_t mine = lane < kPPT * 4 ? em[lane] : 0ull;
+        const uint32_t c = (uint32_t)__popcll(mine);
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        const uint32_t exc = inc - c;
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {
+            const int q = j * 4 + wv;
+            const uint64_t m = __shfl(mine, q, 64);
+            const uint32_t off = __shfl(exc, q, 64);
+            if ((m >> lane) & 1ull) {
+                const int64_t pos = base + (int64_t)rel + off + lane_rank(m);
+                evi[pos] = (uint32_t)(tl * kTileA + (int64_t)j * kThreads + tid);
+            }
+        }
     }
 }
 
@@ -692,8 +737,6 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
     uint64_t *st = ghost ? d.stBg : d.stB;
     const uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
-    const double *evx0 = ghost ? d.gev_x0 : d.ev_x0;
-    const double *evx1 = ghost ? d.gev_x1 : d.ev_x1;
     const int pass = ghost ? kPassFamilyG : kPassFamily;
     const int64_t dstride = ghost ? d.gcap_total : d.cap_total;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -704,8 +747,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
         Node root;
         const int64_t pos = base + j0 + slot;
         const int64_t i = base + (int64_t)evi[pos];
-        root.x[0] = evx0[pos];
-        root.x[1] = DIM == 2 ? evx1[pos] : 0.0;
+        root.x[0] = E.x0[i];
+        root.x[1] = DIM == 2 ? E.x1[i] : 0.0;
         root.k[0] = E.k0[i];
         root.k[1] = DIM == 2 ? E.k1[i] : 0.0;
         root.t0 = 0.0;
@@ -870,6 +913,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
         if (tal.cap) atomicAdd((unsigned long long *)&s_tal[3], (unsigned long long)tal.cap);
         if (tal.maxdepth) atomicMax((unsigned long long *)&s_tal[4], (unsigned long long)tal.maxdepth);
         __syncthreads();
+        // every walk of this tile is done: the parents move to the end of the
+        // step (k_stream left them at their start positions)
+        if (ok) {
+            const int64_t i = base + (int64_t)evi[base + j0 + tid];
+            E.x0[i] = E.x0[i] + (d.vfac * E.k0[i]) * d.dt;
+            if (DIM == 2) E.x1[i] = E.x1[i] + (d.vfac * E.k1[i]) * d.dt;
+        }
     }
     if (tid == 0) {
         int64_t *F = d.fpart + (int64_t)blockIdx.x * 8;
@@ -889,17 +939,42 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
     const uint32_t step = ctl->step;
     int64_t *Ncur = ghost ? d.NG : d.N;
     const int tid = threadIdx.x;
-    // the family blocks' last tallies
+    // the family blocks' last tallies, summed per instance in LDS when the
+    // instances fit (global atomics from one block on one line serialise)
+    constexpr int kLdsB = 512;
+    __shared__ int64_t s_acc[5][kLdsB];
+    const bool lds = B <= kLdsB;
+    if (lds)
+        for (int b = tid; b < B; b += kThreads)
+            for (int q = 0; q < 5; ++q) s_acc[q][b] = 0;
+    __syncthreads();
     for (int g = tid; g < fgrid; g += kThreads) {
         const int64_t *F = d.fpart + (int64_t)g * 8;
         if (F[0] < 0) continue;
-        int64_t *T = d.tally + F[0] * kTalCount;
-        if (F[1]) atomicAdd((unsigned long long *)&T[kTalEvents], (unsigned long long)F[1]);
-        if (F[2]) atomicAdd((unsigned long long *)&T[kTalPairs], (unsigned long long)F[2]);
-        if (F[3]) atomicAdd((unsigned long long *)&T[kTalKilled], (unsigned long long)F[3]);
-        if (F[4]) atomicAdd((unsigned long long *)&T[kTalEventCap], (unsigned long long)F[4]);
-        if (F[5]) atomicMax((unsigned long long *)&T[kTalMaxDepth], (unsigned long long)F[5]);
+        if (lds) {
+            const int b = (int)F[0];
+            for (int q = 0; q < 4; ++q)
+                if (F[1 + q]) atomicAdd((unsigned long long *)&s_acc[q][b], (unsigned long long)F[1 + q]);
+            if (F[5]) atomicMax((unsigned long long *)&s_acc[4][b], (unsigned long long)F[5]);
+        } else {
+            int64_t *T = d.tally + F[0] * kTalCount;
+            if (F[1]) atomicAdd((unsigned long long *)&T[kTalEvents], (unsigned long long)F[1]);
+            if (F[2]) atomicAdd((unsigned long long *)&T[kTalPairs], (unsigned long long)F[2]);
+            if (F[3]) atomicAdd((unsigned long long *)&T[kTalKilled], (unsigned long long)F[3]);
+            if (F[4]) atomicAdd((unsigned long long *)&T[kTalEventCap], (unsigned long long)F[4]);
+            if (F[5]) atomicMax((unsigned long long *)&T[kTalMaxDepth], (unsigned long long)F[5]);
+        }
     }
+    __syncthreads();
+    if (lds)
+        for (int b = tid; b < B; b += kThreads) {
+            int64_t *T = d.tally + (int64_t)b * kTalCount;
+            T[kTalEvents] += s_acc[0][b];
+            T[kTalPairs] += s_acc[1][b];
+            T[kTalKilled] += s_acc[2][b];
+            T[kTalEventCap] += s_acc[3][b];
+            if (s_acc[4][b] > T[kTalMaxDepth]) T[kTalMaxDepth] = s_acc[4][b];
+        }
     int64_t *chc = d.chc + (int64_t)ghost * B;
     int64_t *evc = d.evc + (int64_t)ghost * B;
     for (int b = tid; b < B; b += kThreads) {
