@@ -166,14 +166,17 @@ __global__ __launch_bounds__(kThreads) void k_hist_round(Dev d, const double *hi
 template <int DIM, bool TAN>
 __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
 {
-    // Without tangents the signs of a tile are first summed per cell in an
-    // LDS hash table (open addressing on the cell index, 8 probes), and each
-    // distinct cell of the tile costs one global atomic.  A cell-ordered
-    // ensemble straddles cell boundaries after a few steps of drift, so
-    // equal cells are close in the array but not adjacent; the table finds
-    // them anyway.  A particle whose probes all fail adds directly.
+    // Each block takes a contiguous run of tiles.  Without tangents the
+    // signs are summed per cell in an LDS hash table (open addressing on the
+    // cell index, 8 probes) that lives across the block's tiles and is added
+    // to the count grid when the block moves to another instance, when it is
+    // half full, and at the end: a cell-ordered ensemble straddles cell
+    // boundaries after a few steps of drift, so equal cells are close in the
+    // array but rarely in adjacent lanes, and neighbouring tiles share most
+    // of their cells.  A particle whose probes all fail adds directly.
     constexpr int kSlots = 4096;
     __shared__ int64_t s_esc;
+    __shared__ uint32_t s_nkeys;
     __shared__ int32_t s_key[TAN ? 1 : kSlots];
     __shared__ int32_t s_val[TAN ? 1 : kSlots];
     Ctl *ctl = d.ctl;
@@ -185,10 +188,36 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     const int tid = threadIdx.x;
     if (!TAN)
         for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        if (tid == 0) s_esc = 0;
+    if (tid == 0) { s_esc = 0; s_nkeys = 0; }
+    auto flush = [&](int fb) {
+        if (!TAN) {
+            const int64_t fbase = (int64_t)fb * d.Nh;
+            for (int j = tid; j < kSlots; j += kThreads) {
+                const int k = s_key[j];
+                if (k < 0) continue;
+                const int v = s_val[j];
+                if (v != 0) atomicAdd(&d.cnt[fbase + k], v);
+                s_key[j] = -1;
+                s_val[j] = 0;
+            }
+        }
+        if (tid == 0) {
+            if (s_esc)
+                atomicAdd((unsigned long long *)&d.tally[(int64_t)fb * kTalCount + kTalEscaped],
+                          (unsigned long long)s_esc);
+            s_esc = 0;
+            s_nkeys = 0;
+        }
+        __syncthreads();
+    };
+    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = min((int64_t)blockIdx.x * per, ntiles), t1 = min(t0 + per, ntiles);
+    int cb = -1;
+    for (int64_t t = t0; t < t1; ++t) {
         __syncthreads();
         const int b = segment_of(plan, B, t);
+        if (cb >= 0 && (b != cb || s_nkeys > (uint32_t)(kSlots / 2))) flush(cb);
+        cb = b;
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t n = Ncur[b];
@@ -223,7 +252,10 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 for (int pr = 0; pr < 8 && !done; ++pr) {
                     const int slot = (int)((h + (uint32_t)pr) & (uint32_t)(kSlots - 1));
                     int k = __hip_atomic_load(&s_key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (k == -1) k = atomicCAS(&s_key[slot], -1, key);
+                    if (k == -1) {
+                        k = atomicCAS(&s_key[slot], -1, key);
+                        if (k == -1) atomicAdd(&s_nkeys, 1u);
+                    }
                     if (k == -1 || k == key) {
                         atomicAdd(&s_val[slot], s);
                         done = true;
@@ -254,22 +286,9 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
             }
         }
         if (esc) atomicAdd((unsigned long long *)&s_esc, (unsigned long long)esc);
-        __syncthreads();
-        if (!TAN) {
-            for (int j = tid; j < kSlots; j += kThreads) {
-                const int k = s_key[j];
-                if (k < 0) continue;
-                const int v = s_val[j];
-                if (v != 0) atomicAdd(&d.cnt[cbase + k], v);
-                s_key[j] = -1;
-                s_val[j] = 0;
-            }
-        }
-        if (tid == 0 && s_esc)
-            atomicAdd((unsigned long long *)&d.tally[(int64_t)b * kTalCount + kTalEscaped],
-                      (unsigned long long)s_esc);
-        __syncthreads();
     }
+    __syncthreads();
+    if (cb >= 0) flush(cb);
 }
 
 // ---------------------------------------------------------------------------

@@ -14,7 +14,7 @@ namespace wbrw {
 
 constexpr int kMaxM = 4;
 constexpr int kThreads = 256;           // threads per block in every kernel
-constexpr int kPPT = 16;                // particles (or cells) per thread in streaming passes
+constexpr int kPPT = 8;                 // particles (or cells) per thread in streaming passes
 constexpr int kTileA = kThreads * kPPT; // particles per streaming tile
 constexpr int kTileB = kThreads;        // event-parents per family tile
 constexpr int kTileS = kThreads * kPPT; // cells per scan tile
