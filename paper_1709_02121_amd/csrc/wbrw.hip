@@ -33,7 +33,7 @@ struct Layout {
     size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
     size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, chc = 0, tileA = 0, tileB = 0, tileR = 0,
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
-           tcA = 0, tcAg = 0, emA = 0, emAg = 0, stB = 0, stBg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
+           tcA = 0, tcAg = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, toB = 0, toBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
            bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0, xitab = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
@@ -187,11 +187,16 @@ Layout make_layout(const wbrw_config *c)
     L.rstart = take(cur, (size_t)L.rtiles * 8);
     L.tcA = take(cur, (size_t)L.tilesA * 8);
     L.emA = take(cur, (size_t)L.tilesA * kPPT * 4 * 8);
-    L.stB = take(cur, (size_t)L.tilesB * 8);
+    L.tcB = take(cur, (size_t)L.tilesB * 8);
+    L.toB = take(cur, (size_t)L.tilesB * 8);
+    L.tsB = take(cur, (size_t)L.tilesB * 8);
+    L.stg = take(cur, 2 * BB * 8);
     if (tan) {
         L.tcAg = take(cur, (size_t)L.tilesAg * 8);
         L.emAg = take(cur, (size_t)L.tilesAg * kPPT * 4 * 8);
-        L.stBg = take(cur, (size_t)L.tilesBg * 8);
+        L.tcBg = take(cur, (size_t)L.tilesBg * 8);
+        L.toBg = take(cur, (size_t)L.tilesBg * 8);
+        L.tsBg = take(cur, (size_t)L.tilesBg * 8);
         L.stG = take(cur, (size_t)L.tilesS * 8);
     }
     L.stS = take(cur, (size_t)L.tilesS * 8);
@@ -384,6 +389,13 @@ void enqueue_step_dim(wbrw_t h)
     else
         hipLaunchKernelGGL((k_family<DIM, false, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
+    hipLaunchKernelGGL(k_close_records, dim3(1), dim3(kThreads), 0, s, d, 0);
+    if (h->strategy == WBRW_SP2)
+        hipLaunchKernelGGL((k_place_records<DIM, true, false>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
+    else if (tan)
+        hipLaunchKernelGGL((k_place_records<DIM, false, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
+    else
+        hipLaunchKernelGGL((k_place_records<DIM, false, false>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
     hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 0, tan ? 0 : 1, h->grid[G_FAMILY]);
     if (tan) {
         stage_begin(h, WBRW_STAGE_GHOST);
@@ -391,6 +403,8 @@ void enqueue_step_dim(wbrw_t h)
         hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL(k_close_records, dim3(1), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL((k_place_records<DIM, false, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 1, 1, h->grid[G_FAMILY]);
         stage_end(h);
     }
@@ -648,10 +662,15 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.gev_idx = h->tangent ? at<uint32_t>(w, L.gev_idx) : nullptr;
     d.tcA = at<uint64_t>(w, L.tcA);
     d.emA = at<uint64_t>(w, L.emA);
-    d.stB = at<uint64_t>(w, L.stB);
+    d.tcB = at<uint64_t>(w, L.tcB);
+    d.toB = at<uint64_t>(w, L.toB);
+    d.tsB = at<int64_t>(w, L.tsB);
+    d.stg = at<int64_t>(w, L.stg);
     d.tcAg = h->tangent ? at<uint64_t>(w, L.tcAg) : nullptr;
     d.emAg = h->tangent ? at<uint64_t>(w, L.emAg) : nullptr;
-    d.stBg = h->tangent ? at<uint64_t>(w, L.stBg) : nullptr;
+    d.tcBg = h->tangent ? at<uint64_t>(w, L.tcBg) : nullptr;
+    d.toBg = h->tangent ? at<uint64_t>(w, L.toBg) : nullptr;
+    d.tsBg = h->tangent ? at<int64_t>(w, L.tsBg) : nullptr;
     d.stG = h->tangent ? at<uint64_t>(w, L.stG) : nullptr;
     d.stS = at<uint64_t>(w, L.stS);
     d.cnt = at<int32_t>(w, L.cnt);

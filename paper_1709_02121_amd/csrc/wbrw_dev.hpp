@@ -114,7 +114,11 @@ struct Dev {
     int64_t *rstart;            // first cell of every regeneration tile (written by k_scan)
     uint32_t *ev_idx;           // [cap_total] event-parent index within its instance
     uint32_t *gev_idx;          // ghosts
-    uint64_t *stB, *stBg, *stS, *stG;   // look-back status words
+    uint64_t *stS, *stG;                // look-back status words
+    uint64_t *tcB, *tcBg;               // per family tile: record count
+    uint64_t *toB, *toBg;               // per family tile: exclusive prefix of the counts
+    int64_t *tsB, *tsBg;                // per family tile: where its records were staged
+    int64_t *stg;                       // [2][B] staging fill of the inactive buffer sets
     uint64_t *tcA, *tcAg;               // per streaming tile: event count, then its prefix
     uint64_t *emA, *emAg;               // per streaming tile: kPPT x 4 wavefront event ballots
     int32_t *cnt;               // [B][Nh] signed counts (sp1) / rounded counts (sp2)

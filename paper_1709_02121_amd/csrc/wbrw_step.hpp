@@ -192,26 +192,18 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
     }
 }
 
-// After k_stream (one block): exclusive scan of the tile event counts over
-// all tiles (in place), the event count of every instance, the family-tile
-// plan, cleared record counts, and the particle-step tally.
-__global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
+// Exclusive scan of the per-tile counts cnt[0..T) into pre[0..T) by one
+// block (pre may be cnt); returns the total.  Each thread scans a
+// contiguous chunk whose loads are independent of each other.
+__device__ uint64_t scan_tile_counts(const uint64_t *cnt, uint64_t *pre, int64_t T)
 {
     __shared__ uint64_t s_sum[kThreads];
-    const int B = d.B;
     const int tid = threadIdx.x;
-    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
-    const int64_t *Ncur = ghost ? d.NG : d.N;
-    uint64_t *tc = ghost ? d.tcAg : d.tcA;
-    int64_t *evc = d.evc + (int64_t)ghost * B;
-    const int64_t T = plan[B];
-    // thread tid scans the contiguous chunk [c0, c1) of tiles; its loads are
-    // independent of each other, so they are issued together
     const int64_t per = (T + kThreads - 1) / kThreads;
     const int64_t c0 = min((int64_t)tid * per, T), c1 = min(c0 + per, T);
     uint64_t acc = 0;
 #pragma unroll 16
-    for (int64_t q = c0; q < c1; ++q) acc += tc[q];
+    for (int64_t q = c0; q < c1; ++q) acc += cnt[q];
     s_sum[tid] = acc;
     __syncthreads();
     for (int o = 1; o < kThreads; o <<= 1) {
@@ -223,12 +215,28 @@ __global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
     uint64_t run = s_sum[tid] - acc;
 #pragma unroll 16
     for (int64_t q = c0; q < c1; ++q) {
-        const uint64_t c = tc[q];
-        tc[q] = run;
+        const uint64_t c = cnt[q];
+        pre[q] = run;
         run += c;
     }
-    __syncthreads();
     const uint64_t total = s_sum[kThreads - 1];
+    __syncthreads();
+    return total;
+}
+
+// After k_stream (one block): exclusive scan of the tile event counts over
+// all tiles (in place), the event count of every instance, the family-tile
+// plan, cleared record counts and staging, and the particle-step tally.
+__global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
+{
+    const int B = d.B;
+    const int tid = threadIdx.x;
+    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
+    const int64_t *Ncur = ghost ? d.NG : d.N;
+    uint64_t *tc = ghost ? d.tcAg : d.tcA;
+    int64_t *evc = d.evc + (int64_t)ghost * B;
+    const int64_t T = plan[B];
+    const uint64_t total = scan_tile_counts(tc, tc, T);
     for (int b = tid; b < B; b += kThreads) {
         const uint64_t lo = plan[b] < T ? tc[plan[b]] : total;
         const uint64_t hi = plan[b + 1] < T ? tc[plan[b + 1]] : total;
@@ -238,6 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
     block_plan(d.tileB + (int64_t)ghost * (B + 1), evc, B, kTileB);
     for (int b = tid; b < B; b += kThreads) {
         d.chc[(int64_t)ghost * B + b] = 0;
+        d.stg[(int64_t)ghost * B + b] = 0;
         if (!ghost) d.tally[(int64_t)b * kTalCount + kTalPSteps] += Ncur[b];
     }
 }
@@ -717,7 +726,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
 {
     __shared__ int64_t s_t;
     __shared__ uint32_t s_wsum[4];
-    __shared__ uint32_t s_excl;
+    __shared__ int64_t s_excl;
     __shared__ int64_t s_tal[5];
     __shared__ uint32_t s_nslow;
     __shared__ uint16_t s_slow[kTileB];      // slots whose family needs the general walk
@@ -729,13 +738,16 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
 
     Ctl *ctl = d.ctl;
     const uint32_t step = ctl->step;
-    const uint32_t epoch = 2u * step + (uint32_t)ghost + 1u;
     const int B = d.B;
     const int64_t *plan = d.tileB + (int64_t)ghost * (B + 1);
     const int64_t ntiles = plan[B];
-    int64_t *Ncur = ghost ? d.NG : d.N;
-    const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
-    uint64_t *st = ghost ? d.stBg : d.stB;
+    const uint32_t set = ghost ? ctl->gcur : ctl->cur;
+    const Ens E = pick_set(d, ghost, set);
+    // records are staged in the inactive buffer set, tile by tile, and
+    // placed after the ordered scan by k_place_records
+    const Ens S = pick_set(d, ghost, set ^ 1u);
+    uint64_t *tcnt = ghost ? d.tcBg : d.tcB;
+    int64_t *tstg = ghost ? d.tsBg : d.tsB;
     const uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
     const int pass = ghost ? kPassFamilyG : kPassFamily;
     const int64_t dstride = ghost ? d.gcap_total : d.cap_total;
@@ -790,14 +802,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             }
             cb = b;
         }
-        const int64_t first = plan[b];
-        const int64_t tl_i = t - first;
-        const int64_t last = plan[b + 1] - 1;
+        const int64_t tl_i = t - plan[b];
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t cap = ghost ? P.gcap : P.cap;
         const int64_t nev = d.evc[(int64_t)ghost * B + b];
-        const int64_t n_before = Ncur[b];
         const int64_t j0 = tl_i * kTileB;
         const bool ok = j0 + tid < nev;
 
@@ -841,36 +850,38 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             if (q < wv) woff += s_wsum[q];
             agg += s_wsum[q];
         }
-        if (wv == 0) {
-            const uint32_t excl = tile_prefix(st, t, first, epoch, agg);
-            if (lane == 0) {
-                if (t == last) d.chc[(int64_t)ghost * B + b] = (int64_t)(excl + agg);
-                s_excl = excl;
-            }
+        if (tid == 0) {
+            // the tile's records take a contiguous stretch of the staging
+            // area; no tile waits for another
+            const int64_t sb = (int64_t)atomicAdd((unsigned long long *)&d.stg[(int64_t)ghost * B + b],
+                                                  (unsigned long long)agg);
+            s_excl = sb;
+            tcnt[t] = agg;
+            tstg[t] = sb;
         }
         __syncthreads();
-        const int64_t my_first = n_before + (int64_t)s_excl + (int64_t)(woff + incl - cnt);
+        const int64_t my_first = s_excl + (int64_t)(woff + incl - cnt);
         s_first[tid] = my_first;
 
-        // 4. records: from the stash and the pool, or by a second full walk
-        //    for a family whose records overflowed the pool
+        // 4. records into the staging area: from the stash and the pool, or
+        //    by a second full walk for a family that overflowed the pool
         if (ok && !slow) {
             for (uint32_t r = 0; r < cnt; ++r) {
                 const int64_t li = my_first + r;
                 if (li >= cap) { err |= kErrCapacity; continue; }
                 const int64_t o = base + li;
-                E.x0[o] = s_stash.x0[r][tid];
-                E.k0[o] = s_stash.k0[r][tid];
+                S.x0[o] = s_stash.x0[r][tid];
+                S.k0[o] = s_stash.k0[r][tid];
                 if (DIM == 2) {
-                    E.x1[o] = s_stash.x1[r][tid];
-                    E.k1[o] = s_stash.k1[r][tid];
+                    S.x1[o] = s_stash.x1[r][tid];
+                    S.k1[o] = s_stash.k1[r][tid];
                 }
-                if (SP2) E.w[o] = s_stash.w[r][tid]; else E.sg[o] = s_stash.sg[r][tid];
-                E.id[o] = s_stash.id[r][tid];
+                if (SP2) S.w[o] = s_stash.w[r][tid]; else S.sg[o] = s_stash.sg[r][tid];
+                S.id[o] = s_stash.id[r][tid];
                 if (TAN) {
-                    E.D[o] = s_stash.D[3 * r][tid];
-                    E.D[dstride + o] = s_stash.D[3 * r + 1][tid];
-                    E.D[2 * dstride + o] = s_stash.D[3 * r + 2][tid];
+                    S.D[o] = s_stash.D[3 * r][tid];
+                    S.D[dstride + o] = s_stash.D[3 * r + 1][tid];
+                    S.D[2 * dstride + o] = s_stash.D[3 * r + 2][tid];
                 }
             }
         }
@@ -882,18 +893,18 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             const int64_t li = s_first[slot] + s_pool.rank[r];
             if (li >= cap) { err |= kErrCapacity; continue; }
             const int64_t o = base + li;
-            E.x0[o] = s_pool.x0[r];
-            E.k0[o] = s_pool.k0[r];
+            S.x0[o] = s_pool.x0[r];
+            S.k0[o] = s_pool.k0[r];
             if (DIM == 2) {
-                E.x1[o] = s_pool.x1[r];
-                E.k1[o] = s_pool.k1[r];
+                S.x1[o] = s_pool.x1[r];
+                S.k1[o] = s_pool.k1[r];
             }
-            if (SP2) E.w[o] = s_pool.w[r]; else E.sg[o] = s_pool.sg[r];
-            E.id[o] = s_pool.id[r];
+            if (SP2) S.w[o] = s_pool.w[r]; else S.sg[o] = s_pool.sg[r];
+            S.id[o] = s_pool.id[r];
             if (TAN) {
-                E.D[o] = s_pool.D[0][r];
-                E.D[dstride + o] = s_pool.D[1][r];
-                E.D[2 * dstride + o] = s_pool.D[2][r];
+                S.D[o] = s_pool.D[0][r];
+                S.D[dstride + o] = s_pool.D[1][r];
+                S.D[2 * dstride + o] = s_pool.D[2][r];
             }
         }
         for (int k = tid; k < nslow; k += kThreads) {
@@ -902,7 +913,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             const Node root = load_root(base, j0, slot);
             Tally none{0, 0, 0, 0, 0};
             bool unused = false;
-            walk_family<DIM, SP2, TAN, true>(d, P, step, root, E, base, s_first[slot], cap, dstride, none, err,
+            walk_family<DIM, SP2, TAN, true>(d, P, step, root, S, base, s_first[slot], cap, dstride, none, err,
                                              &s_pool, slot, unused);
         }
 
@@ -925,6 +936,71 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
         int64_t *F = d.fpart + (int64_t)blockIdx.x * 8;
         F[0] = cb;
         for (int q = 0; q < 5; ++q) F[1 + q] = s_tal[q];
+    }
+    if (err) atomicOr(&ctl->err, err);
+}
+
+// After k_family (one block): exclusive scan of the family tiles' record
+// counts and the record count of every instance.
+__global__ __launch_bounds__(kThreads) void k_close_records(Dev d, int ghost)
+{
+    const int B = d.B;
+    const int64_t *plan = d.tileB + (int64_t)ghost * (B + 1);
+    const uint64_t *tc = ghost ? d.tcBg : d.tcB;
+    uint64_t *to = ghost ? d.toBg : d.toB;
+    const int64_t T = plan[B];
+    const uint64_t total = scan_tile_counts(tc, to, T);
+    for (int b = threadIdx.x; b < B; b += kThreads) {
+        const uint64_t lo = plan[b] < T ? to[plan[b]] : total;
+        const uint64_t hi = plan[b + 1] < T ? to[plan[b + 1]] : total;
+        d.chc[(int64_t)ghost * B + b] = (int64_t)(hi - lo);
+    }
+}
+
+// Every family tile's staged records (contiguous in the inactive buffer set)
+// go to their place after the instance's particles: tile order, then the
+// order of the family walks within the tile.
+template <int DIM, bool SP2, bool TAN>
+__global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost)
+{
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int64_t *plan = d.tileB + (int64_t)ghost * (B + 1);
+    const int64_t ntiles = plan[B];
+    const int64_t *Ncur = ghost ? d.NG : d.N;
+    const uint32_t set = ghost ? ctl->gcur : ctl->cur;
+    const Ens E = pick_set(d, ghost, set);
+    const Ens S = pick_set(d, ghost, set ^ 1u);
+    const uint64_t *tc = ghost ? d.tcBg : d.tcB;
+    const uint64_t *to = ghost ? d.toBg : d.toB;
+    const int64_t *ts = ghost ? d.tsBg : d.tsB;
+    const int64_t dstride = ghost ? d.gcap_total : d.cap_total;
+    uint32_t err = 0;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int b = segment_of(plan, B, t);
+        const InstParam &P = d.ip[b];
+        const int64_t base = ghost ? P.gbase : P.base;
+        const int64_t cap = ghost ? P.gcap : P.cap;
+        const int64_t n = (int64_t)tc[t], src = ts[t];
+        const int64_t dst = Ncur[b] + (int64_t)(to[t] - to[plan[b]]);
+        for (int64_t r = threadIdx.x; r < n; r += kThreads) {
+            if (src + r >= cap) break;                 // never staged (flagged by k_family)
+            if (dst + r >= cap) { err |= kErrCapacity; break; }
+            const int64_t i = base + src + r, o = base + dst + r;
+            E.x0[o] = S.x0[i];
+            E.k0[o] = S.k0[i];
+            if (DIM == 2) {
+                E.x1[o] = S.x1[i];
+                E.k1[o] = S.k1[i];
+            }
+            if (SP2) E.w[o] = S.w[i]; else E.sg[o] = S.sg[i];
+            E.id[o] = S.id[i];
+            if (TAN) {
+                E.D[o] = S.D[i];
+                E.D[dstride + o] = S.D[dstride + i];
+                E.D[2 * dstride + o] = S.D[2 * dstride + i];
+            }
+        }
     }
     if (err) atomicOr(&ctl->err, err);
 }
