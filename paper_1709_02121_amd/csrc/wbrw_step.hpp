@@ -375,7 +375,7 @@ struct Pool {
 template <bool SP2>
 __device__ __forceinline__ bool draw_pair(const Dev &d, const InstParam &P, uint64_t id, uint32_t step,
                                           uint32_t e, int m, const double *xe, double te, double ua0,
-                                          double w, PairDraw &J)
+                                          double w, PairDraw &J, const W4 *kick_draw = nullptr)
 {
     const uint32_t seed = d.seed, key = P.key;
     double cm = P.c[m], sgv = P.sgnV[m];
@@ -398,7 +398,7 @@ __device__ __forceinline__ bool draw_pair(const Dev &d, const InstParam &P, uint
         sgv = 1.0;
         alg4 = true;
     } else {
-        const W4 rq = draw(id, step, kTagStep, e, (uint32_t)(1 + m), seed, key);
+        const W4 rq = kick_draw ? *kick_draw : draw(id, step, kTagStep, e, (uint32_t)(1 + m), seed, key);
         J.q = kick_sample(d, P, m, unit53(rq.a, rq.b), unit53(rq.c, rq.d));
         J.arg = (2.0 * J.q) * phase_offset(d, m, xe, P.center[m]);
         J.sn = sin_det(J.arg);
@@ -534,7 +534,13 @@ __device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, ui
 {
     const uint32_t seed = d.seed, key = P.key;
     cnt = 0;
+    // The draws that do not depend on each other are taken together, so
+    // their Philox chains interleave: the first and second clock draws, and
+    // the kick and child-id draws of component 0.
     const W4 r = draw(root.id, step, kTagStep, 0u, 0u, seed, key);
+    const W4 r1 = draw(root.id, step, kTagStep, 1u, 0u, seed, key);
+    const W4 rq0 = draw(root.id, step, kTagStep, 0u, 1u, seed, key);
+    const W4 rc0 = draw(root.id, step, kTagChild, 0u, 0u, seed, key);
     const double te = root.t0 + (-ln_series(1.0 - unit53(r.a, r.b)) / P.gamma0);
     if (!(te <= d.dt)) return true;
     tl.events++;
@@ -545,27 +551,30 @@ __device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, ui
     bool fast = true;
     for (int m = 0; m < d.M; ++m) {
         PairDraw J;
-        if (!draw_pair<SP2>(d, P, root.id, step, 0u, m, xe, te, ua0, root.w, J)) continue;
+        if (!draw_pair<SP2>(d, P, root.id, step, 0u, m, xe, te, ua0, root.w, J, m == 0 ? &rq0 : nullptr))
+            continue;
         tl.pairs++;
-        const W4 rc = draw(root.id, step, kTagChild, 0u, (uint32_t)m, seed, key);
+        const W4 rc = m == 0 ? rc0 : draw(root.id, step, kTagChild, 0u, (uint32_t)m, seed, key);
+        Node ch[2];
+        make_child<SP2, TAN>(d, P, root, m, 0, J, rc, ch[0]);
+        make_child<SP2, TAN>(d, P, root, m, 1, J, rc, ch[1]);
+        // both offspring's first clock draws, together
+        const W4 l0 = draw(ch[0].id, step, kTagStep, 0u, 0u, seed, key);
+        const W4 l1 = draw(ch[1].id, step, kTagStep, 0u, 0u, seed, key);
         for (int side = 0; side < 2; ++side) {
-            Node ch;
-            make_child<SP2, TAN>(d, P, root, m, side, J, rc, ch);
-            if (!in_kbox<DIM>(d, ch.k)) {
-                tl.killed += killed_amount<SP2>(ch);
+            if (!in_kbox<DIM>(d, ch[side].k)) {
+                tl.killed += killed_amount<SP2>(ch[side]);
                 continue;
             }
-            if (cnt < (uint32_t)kStash) stash_record<DIM, SP2, TAN>(d, sh, (int)cnt, slot, xe, te, ch);
+            if (cnt < (uint32_t)kStash) stash_record<DIM, SP2, TAN>(d, sh, (int)cnt, slot, xe, te, ch[side]);
             else fast = false;
             cnt++;
             if (tl.maxdepth < 1) tl.maxdepth = 1;
-            const W4 r0 = draw(ch.id, step, kTagStep, 0u, 0u, seed, key);
-            const double u0 = unit53(r0.a, r0.b);
+            const double u0 = side == 0 ? unit53(l0.a, l0.b) : unit53(l1.a, l1.b);
             if (!surely_no_jump(u0, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u0) / P.gamma0) <= d.dt)
                 fast = false;
         }
     }
-    const W4 r1 = draw(root.id, step, kTagStep, 1u, 0u, seed, key);
     const double u1 = unit53(r1.a, r1.b);
     if (!surely_no_jump(u1, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u1) / P.gamma0) <= d.dt)
         fast = false;
@@ -814,8 +823,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
         Tally tal{0, 0, 0, 0, 0};
         uint32_t cnt = 0;
         bool slow = false;
+        int64_t pi = 0;                       // the parent and its end-of-step position
+        double xend0 = 0.0, xend1 = 0.0;
         if (ok) {
             const Node root = load_root(base, j0, tid);
+            pi = base + (int64_t)evi[base + j0 + tid];
+            xend0 = root.x[0] + (d.vfac * root.k[0]) * d.dt;
+            xend1 = root.x[1] + (d.vfac * root.k[1]) * d.dt;
             slow = !fast_family<DIM, SP2, TAN>(d, P, step, root, &s_stash, tid, cnt, tal);
         }
         if (slow) {
@@ -823,9 +837,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             s_slow[atomicAdd(&s_nslow, 1u)] = (uint16_t)tid;
         }
         __syncthreads();
-        // 2. the rest walked in full, spread over the block's threads
+        // 2. the rest walked in full, spread over the block's threads with
+        //    consecutive families in different wavefronts
         const int nslow = (int)s_nslow;
-        for (int k = tid; k < nslow; k += kThreads) {
+        const int kme = lane * 4 + wv;
+        for (int k = kme; k < nslow; k += kThreads) {
             const int slot = s_slow[k];
             const Node root = load_root(base, j0, slot);
             bool pooled = true;
@@ -907,7 +923,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
                 S.D[2 * dstride + o] = s_pool.D[2][r];
             }
         }
-        for (int k = tid; k < nslow; k += kThreads) {
+        for (int k = kme; k < nslow; k += kThreads) {
             const int slot = s_slow[k];
             if (s_pooled[slot]) continue;
             const Node root = load_root(base, j0, slot);
@@ -917,19 +933,26 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
                                              &s_pool, slot, unused);
         }
 
-        // per-instance tallies
-        if (tal.events) atomicAdd((unsigned long long *)&s_tal[0], (unsigned long long)tal.events);
-        if (tal.pairs) atomicAdd((unsigned long long *)&s_tal[1], (unsigned long long)tal.pairs);
-        if (tal.killed) atomicAdd((unsigned long long *)&s_tal[2], (unsigned long long)tal.killed);
-        if (tal.cap) atomicAdd((unsigned long long *)&s_tal[3], (unsigned long long)tal.cap);
-        if (tal.maxdepth) atomicMax((unsigned long long *)&s_tal[4], (unsigned long long)tal.maxdepth);
+        // per-instance tallies, summed over the wavefront first
+        int64_t tv[4] = {tal.events, tal.pairs, tal.killed, tal.cap};
+        int64_t tm = tal.maxdepth;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tv[q] += __shfl_xor(tv[q], o, 64);
+            tm = max(tm, __shfl_xor(tm, o, 64));
+        }
+        if (lane == 0) {
+            for (int q = 0; q < 4; ++q)
+                if (tv[q]) atomicAdd((unsigned long long *)&s_tal[q], (unsigned long long)tv[q]);
+            if (tm) atomicMax((unsigned long long *)&s_tal[4], (unsigned long long)tm);
+        }
         __syncthreads();
         // every walk of this tile is done: the parents move to the end of the
         // step (k_stream left them at their start positions)
         if (ok) {
-            const int64_t i = base + (int64_t)evi[base + j0 + tid];
-            E.x0[i] = E.x0[i] + (d.vfac * E.k0[i]) * d.dt;
-            if (DIM == 2) E.x1[i] = E.x1[i] + (d.vfac * E.k1[i]) * d.dt;
+            E.x0[pi] = xend0;
+            if (DIM == 2) E.x1[pi] = xend1;
         }
     }
     if (tid == 0) {
