@@ -120,7 +120,7 @@ def measured_traffic(dim, bytes_per_launch):
         return None
     info = json.load(open(path))
     h = hashlib.sha256()
-    for f in ("wbrw_step.hpp", "wbrw_math.hpp", "wbrw_dev.hpp"):
+    for f in ("wbrw_stream.hpp", "wbrw_math.hpp", "wbrw_dev.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1709_02121_amd", "csrc", f), "rb").read())
     if info.get("source_sha256") != h.hexdigest():
         return None

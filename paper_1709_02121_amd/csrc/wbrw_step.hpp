@@ -1,30 +1,26 @@
-// One time step of the Wigner branching random walk (Alg. 1, Sec. 2) as two
-// persistent kernels.
+// One time step of the Wigner branching random walk (Alg. 1, Sec. 2), after
+// the streaming pass (wbrw_stream.hpp):
 //
-// Pass 1, k_stream (HBM-bound): every particle draws its first life-length
-// (exact for a constant gamma0, Sec. 3.2.1), moves freely to the end of the
-// step (a particle keeps its k after a jump: offspring 2M+1 of Alg. 1, so its
-// end position does not depend on its jumps) and, if its first jump falls
-// inside the step, is appended to an ordered per-instance event list (and
-// keeps its start position until its family has been walked).  Ordering uses a wavefront ballot, an LDS scan over
-// the block and a decoupled look-back across tiles.  Only the first of the
-// two uniforms decides, and only a 1e-9-wide band around the threshold
-// evaluates the logarithm.
+// k_close_stream, k_events: the tiles' event counts are scanned by one block,
+// and every tile turns its wavefront ballots into the ordered list of event
+// parents (instance by instance, in particle order).
 //
-// Pass 2, k_family (latency-bound, ~3% of particles): one thread per event
-// parent walks the parent's whole family within the step, depth first: for
-// each jump in time order, each component in order, the "+" offspring, its own
+// k_family (latency-bound, ~3% of particles): one thread per event parent
+// walks the parent's whole family within the step, depth first: for each
+// jump in time order, each component in order, the "+" offspring, its own
 // family, then the "-" offspring and its family.  Offspring are new particles
 // of the system with their own lineage ids and exponential clocks (Alg. 1
-// rule 3).  A first walk counts the records and keeps the first two in LDS;
-// after an ordered scan with look-back fixes the output offset, families of
-// at most two records (nearly all) are copied out and only larger ones are
-// walked again to write them.  A child whose first clock draw falls past the
-// end of the step is a leaf and never enters the walk's stack.  Records hold
-// the end-of-step state, so no generation is revisited in a later launch.
+// rule 3).  The common family (one jump, offspring that do not jump again
+// before the end of the step) is evaluated for all parents in lockstep; the
+// others take the general walk, spread over the block.  Records hold the
+// end-of-step state, so no generation is revisited in a later launch.  Each
+// tile stages its records contiguously in the inactive buffer set;
+// k_close_records scans the tiles' record counts and k_place_records copies
+// the records to their ordered place after the instance's particles.
 #pragma once
 #include "wbrw_dev.hpp"
 #include "wbrw_math.hpp"
+#include "wbrw_stream.hpp"
 
 namespace wbrw {
 
@@ -93,103 +89,6 @@ __device__ __forceinline__ bool in_kbox(const Dev &d, const double *k)
     if (!(k[0] >= d.k_lo && k[0] < d.k_hi)) return false;
     if (DIM == 2 && !(k[1] >= d.k_lo && k[1] < d.k_hi)) return false;
     return true;
-}
-
-// ---------------------------------------------------------------------------
-// Pass 1: streaming clock test + free flight; the event flags of every tile
-// are kept as wavefront ballots, and the tile's event count is stored.
-// No tile waits for another: tiles are assigned statically and the ordered
-// event list is built by k_close_stream (scan of the tile counts) and
-// k_events (expansion of the ballots).
-// ---------------------------------------------------------------------------
-template <int DIM>
-__global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
-{
-    __shared__ uint32_t s_wcnt[4];
-    const Ctl *ctl = d.ctl;
-    const uint32_t step = ctl->step;
-    const int B = d.B;
-    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
-    const int64_t ntiles = plan[B];
-    const int64_t *Ncur = ghost ? d.NG : d.N;
-    const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
-    uint64_t *tcnt = ghost ? d.tcAg : d.tcA;
-    uint64_t *emask = ghost ? d.emAg : d.emA;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int b = segment_of(plan, B, t);
-        const int64_t tl = t - plan[b];
-        const InstParam &P = d.ip[b];
-        const int64_t base = ghost ? P.gbase : P.base;
-        const int64_t n = Ncur[b];
-        const double thr_lo = P.thr_lo, thr_hi = P.thr_hi, g0 = P.gamma0;
-        const uint32_t key = P.key;
-
-        // All loads of the thread's kPPT particles are issued before any
-        // compute or store, so every wave keeps 3*kPPT (4D: 5*kPPT) loads in
-        // flight; full tiles need no bounds checks.
-        const int64_t li0 = tl * kTileA + tid;
-        const bool full = (tl + 1) * kTileA <= n;
-        double xs0[kPPT], xs1[kPPT], kv0[kPPT], kv1[kPPT];
-        uint64_t idv[kPPT];
-        if (full) {
-#pragma unroll
-            for (int j = 0; j < kPPT; ++j) {
-                const int64_t i = base + li0 + (int64_t)j * kThreads;
-                xs0[j] = E.x0[i];
-                kv0[j] = E.k0[i];
-                idv[j] = E.id[i];
-                if (DIM == 2) { xs1[j] = E.x1[i]; kv1[j] = E.k1[i]; }
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < kPPT; ++j) {
-                const int64_t li = li0 + (int64_t)j * kThreads;
-                const int64_t i = base + (li < n ? li : 0);
-                xs0[j] = E.x0[i];
-                kv0[j] = E.k0[i];
-                idv[j] = E.id[i];
-                if (DIM == 2) { xs1[j] = E.x1[i]; kv1[j] = E.k1[i]; }
-            }
-        }
-        uint32_t evbits = 0, nev = 0;
-        uint64_t *em = emask + t * (kPPT * 4);
-#pragma unroll
-        for (int j = 0; j < kPPT; ++j) {
-            const bool valid = full || (li0 + (int64_t)j * kThreads < n);
-            bool ev = false;
-            const W4 r = draw(idv[j], step, kTagStep, 0u, 0u, d.seed, key);
-            const double u = unit53(r.a, r.b);
-            if (u < thr_lo) {
-                ev = true;
-            } else if (u <= thr_hi) {
-                const double tau = -ln_series(1.0 - u) / g0;
-                const double te = 0.0 + tau;
-                ev = (te <= d.dt);
-            }
-            ev = ev && valid;
-            const uint64_t m = __ballot(ev);
-            if (lane == 0) em[j * 4 + wv] = m;
-            nev += (uint32_t)__popcll(m);
-            evbits |= (ev ? 1u : 0u) << j;
-        }
-        // free flight to the end of the step; an event parent keeps its
-        // start position, which its family walk needs, and k_family moves it
-#pragma unroll
-        for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = li0 + (int64_t)j * kThreads;
-            if ((full || li < n) && !((evbits >> j) & 1u)) {
-                const int64_t i = base + li;
-                E.x0[i] = xs0[j] + (d.vfac * kv0[j]) * d.dt;
-                if (DIM == 2) E.x1[i] = xs1[j] + (d.vfac * kv1[j]) * d.dt;
-            }
-        }
-        if (lane == 0) s_wcnt[wv] = nev;
-        __syncthreads();
-        if (tid == 0) tcnt[t] = (uint64_t)(s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3]);
-        __syncthreads();
-    }
 }
 
 // Exclusive scan of the per-tile counts cnt[0..T) into pre[0..T) by one

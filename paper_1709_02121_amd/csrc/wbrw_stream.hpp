@@ -1,0 +1,113 @@
+// One time step of the Wigner branching random walk (Alg. 1, Sec. 2),
+// pass 1: k_stream (HBM-bound).  Every particle draws its first
+// life-length (exact for a constant gamma0, Sec. 3.2.1) and, unless that jump
+// falls inside the step, moves freely to the end of the step (a particle
+// keeps its k after a jump: offspring 2M+1 of Alg. 1, so its end position
+// does not depend on its jumps).  Only the first of the two uniforms decides,
+// and only a 1e-9-wide band around the threshold evaluates the logarithm.
+// The event flags of each tile are kept as wavefront ballots; the ordered
+// event list is built from them by the passes in wbrw_step.hpp.
+#pragma once
+#include "wbrw_dev.hpp"
+#include "wbrw_math.hpp"
+
+namespace wbrw {
+
+// ---------------------------------------------------------------------------
+// Pass 1: streaming clock test + free flight; the event flags of every tile
+// are kept as wavefront ballots, and the tile's event count is stored.
+// No tile waits for another: tiles are assigned statically and the ordered
+// event list is built by k_close_stream (scan of the tile counts) and
+// k_events (expansion of the ballots).
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
+{
+    __shared__ uint32_t s_wcnt[4];
+    const Ctl *ctl = d.ctl;
+    const uint32_t step = ctl->step;
+    const int B = d.B;
+    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
+    const int64_t ntiles = plan[B];
+    const int64_t *Ncur = ghost ? d.NG : d.N;
+    const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
+    uint64_t *tcnt = ghost ? d.tcAg : d.tcA;
+    uint64_t *emask = ghost ? d.emAg : d.emA;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int b = segment_of(plan, B, t);
+        const int64_t tl = t - plan[b];
+        const InstParam &P = d.ip[b];
+        const int64_t base = ghost ? P.gbase : P.base;
+        const int64_t n = Ncur[b];
+        const double thr_lo = P.thr_lo, thr_hi = P.thr_hi, g0 = P.gamma0;
+        const uint32_t key = P.key;
+
+        // All loads of the thread's kPPT particles are issued before any
+        // compute or store, so every wave keeps 3*kPPT (4D: 5*kPPT) loads in
+        // flight; full tiles need no bounds checks.
+        const int64_t li0 = tl * kTileA + tid;
+        const bool full = (tl + 1) * kTileA <= n;
+        double xs0[kPPT], xs1[kPPT], kv0[kPPT], kv1[kPPT];
+        uint64_t idv[kPPT];
+        if (full) {
+#pragma unroll
+            for (int j = 0; j < kPPT; ++j) {
+                const int64_t i = base + li0 + (int64_t)j * kThreads;
+                xs0[j] = E.x0[i];
+                kv0[j] = E.k0[i];
+                idv[j] = E.id[i];
+                if (DIM == 2) { xs1[j] = E.x1[i]; kv1[j] = E.k1[i]; }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPPT; ++j) {
+                const int64_t li = li0 + (int64_t)j * kThreads;
+                const int64_t i = base + (li < n ? li : 0);
+                xs0[j] = E.x0[i];
+                kv0[j] = E.k0[i];
+                idv[j] = E.id[i];
+                if (DIM == 2) { xs1[j] = E.x1[i]; kv1[j] = E.k1[i]; }
+            }
+        }
+        uint32_t evbits = 0, nev = 0;
+        uint64_t *em = emask + t * (kPPT * 4);
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {
+            const bool valid = full || (li0 + (int64_t)j * kThreads < n);
+            bool ev = false;
+            const W4 r = draw(idv[j], step, kTagStep, 0u, 0u, d.seed, key);
+            const double u = unit53(r.a, r.b);
+            if (u < thr_lo) {
+                ev = true;
+            } else if (u <= thr_hi) {
+                const double tau = -ln_series(1.0 - u) / g0;
+                const double te = 0.0 + tau;
+                ev = (te <= d.dt);
+            }
+            ev = ev && valid;
+            const uint64_t m = __ballot(ev);
+            if (lane == 0) em[j * 4 + wv] = m;
+            nev += (uint32_t)__popcll(m);
+            evbits |= (ev ? 1u : 0u) << j;
+        }
+        // free flight to the end of the step; an event parent keeps its
+        // start position, which its family walk needs, and k_family moves it
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {
+            const int64_t li = li0 + (int64_t)j * kThreads;
+            if ((full || li < n) && !((evbits >> j) & 1u)) {
+                const int64_t i = base + li;
+                E.x0[i] = xs0[j] + (d.vfac * kv0[j]) * d.dt;
+                if (DIM == 2) E.x1[i] = xs1[j] + (d.vfac * kv1[j]) * d.dt;
+            }
+        }
+        if (lane == 0) s_wcnt[wv] = nev;
+        __syncthreads();
+        if (tid == 0) tcnt[t] = (uint64_t)(s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3]);
+        __syncthreads();
+    }
+}
+
+}  // namespace wbrw
