@@ -207,6 +207,7 @@ def main():
                 ("sp2", lambda: W.gaussian_barrier_large("sp2"), 50, 10),
                 ("batched_256", lambda: W.batched_barriers(), 100, 10),
                 ("fwd_adjoint", lambda: W.differentiation(), 50, 10),
+                ("fwd_adjoint_x0_deriv_pairs", lambda: W.differentiation(track_tangent=2), 50, 10),
                 ("helium_4d", lambda: W.helium_soft_coulomb(), 10, 0)):
             try:
                 torch.cuda.empty_cache()

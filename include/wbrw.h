@@ -100,7 +100,10 @@ typedef struct wbrw_config {
     int32_t n_components;     /* 1 .. WBRW_MAX_COMPONENTS */
     int32_t n_instances;      /* B, 1 .. 65536 independent ensembles */
     int32_t instance_offset;  /* instance b draws with key index instance_offset + b */
-    int32_t track_tangent;    /* 1: carry d/d(H, w, x0) tangents (sp1, dim 1, one Gaussian component) */
+    int32_t track_tangent;    /* 0: none; 1: carry d/d(H, w, x0) tangents by likelihood-ratio
+                                 scores (sp1, dim 1, one Gaussian component); 2: the same for
+                                 (H, w), and d/dx0 by derivative ghost pairs instead of the
+                                 x0 score (finite variance; see wbrw_density_tangent) */
     uint32_t seed;            /* Philox key word */
     int32_t max_density_bins; /* largest nbins a later wbrw_density() may ask for */
     double hbar, mass;        /* free flight x += (hbar/mass) k dt */
@@ -121,7 +124,9 @@ typedef struct wbrw_config {
 } wbrw_config;
 
 typedef struct wbrw_stats {
-    int64_t n;                /* particles held (sp1/sp2), excluding ghosts */
+    int64_t n;                /* particles held (sp1/sp2), excluding the ghost ensemble; with
+                                 track_tangent 2 this includes the sign-0 derivative ghosts
+                                 born since the last annihilation */
     int64_t n_ghost;          /* tangent ghosts held */
     int64_t events;           /* jumps so far */
     int64_t pairs;            /* offspring pairs generated so far */
@@ -195,15 +200,17 @@ int wbrw_run(wbrw_t h, int32_t nsteps, int32_t annihilate_every, int32_t use_gra
 int wbrw_density(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, double *d_out);
 
 /* Tangent density (track_tangent only): d_out[(b*3 + c) * nbins + j] =
- * sum over real particles and ghosts in bin j of D_c / (N0_b dx), the
- * likelihood-ratio derivative of the density with respect to
- * theta = (H, w, x0).  d_out: device, caller-owned.  No synchronisation. */
+ * sum over real particles and ghosts in bin j of D_c / (N0_b dx), an unbiased
+ * estimate of the derivative of the density with respect to
+ * theta = (H, w, x0) (likelihood-ratio scores; with track_tangent 2 the x0
+ * part comes from derivative ghost pairs).  d_out: device, caller-owned.
+ * No synchronisation. */
 int wbrw_density_tangent(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi,
                          double *d_out);
 
 /* Backward pass of the density (track_tangent only): grad_out[b*3 + c] =
  * sum_j g[b*nbins + j] d rho_bj / d theta_c, accumulated directly from the
- * per-particle likelihood-ratio tangents of real particles and ghosts in bin
+ * per-particle tangents of real particles and ghosts in bin
  * j, theta = (H, w, x0).  g, grad_out: device, caller-owned.  Same binning as
  * wbrw_density.  No synchronisation. */
 int wbrw_density_vjp(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi,

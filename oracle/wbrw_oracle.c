@@ -46,7 +46,7 @@ typedef __int128 i128;
 #define ORC_EMAX 4096u /* event cap per particle-step (never reached at the configs) */
 
 enum { TAG_STEP = 0, TAG_REGEN = 1, TAG_INIT = 2, TAG_BOOT = 3, TAG_ROUND = 4,
-       TAG_CHILD = 5, TAG_GHOST = 6, TAG_HIST = 7, TAG_REJECT = 8 };
+       TAG_CHILD = 5, TAG_GHOST = 6, TAG_HIST = 7, TAG_REJECT = 8, TAG_DERIV = 9 };
 #define ORC_XI_N 4096      /* xi(r) grid intervals over r in [0, 8w] (Alg. 4 sampler) */
 #define ORC_XI_Q 8192      /* midpoint quadrature nodes over q in [-8/w, 8/w) */
 #define ORC_REJECT_MAX 256 /* proposals per kick before the pair is dropped */
@@ -62,7 +62,9 @@ typedef struct {
     int32_t M;              /* kernel components */
     int32_t B;              /* instances */
     int32_t instance_offset;/* key index of instance 0 (lets one instance replay instance b) */
-    int32_t track_tangent;  /* 1: carry LR tangents (sp1, single Gaussian component) */
+    int32_t track_tangent;  /* 1: carry LR tangents (sp1, single Gaussian component);
+                             * 2: the same for (H, w), and the x0 tangent by
+                             * derivative ghost pairs (see deriv_pairs) */
     uint32_t seed;
     int32_t pad0;
     double hbar, mass, dt, gamma0, gamma_scale;
@@ -591,6 +593,75 @@ static int reject_kick(const orc_sim *S, const inst_t *I, uint64_t id, uint32_t 
 /* (offspring 2M+1), so its end-of-step position does not depend on jumps.    */
 /* Pinned by tests/test_oracle_physics.py and tests/test_oracle_invariants.py */
 /* ------------------------------------------------------------------------ */
+static void walk(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth);
+
+/* ------------------------------------------------------------------------ */
+/* Derivative ghost pairs: the x0 tangent without the likelihood-ratio score. */
+/* The pair intensity of component m at a jump is c sin(2 q (x - x0)) per     */
+/* unit of the kick density (Alg. 1, pair box, with the majorant of Remark 3) */
+/* and depends on x0 only through the sine; its x0-derivative is              */
+/* -2 q c cos(2 q (x - x0)).  With probability c |cos| (an independent        */
+/* uniform) and the same kick q, a pair of ghosts (sign 0) is placed at       */
+/* k +/- sigma' q, sigma' = sgn(F[V]) sgn(cos), carrying x0-tangents          */
+/* -/+ 2 q s (s the parent's sign) and zero (H, w) tangents.  Its expectation */
+/* is the x0-derivative of the signed pair measure, and the tangent is        */
+/* bounded by 2|q|, so it has finite variance where the score -2q cot does    */
+/* not.  Only signed particles spawn them; the ghosts then walk like any      */
+/* particle and join the real ensemble until the next annihilation folds      */
+/* their tangents into the cell sums.  Order: after the jump's real pairs, per */
+/* component, "+" ghost and its family, then "-" ghost and its family.        */
+/* Pinned by tests/test_oracle_gradient.py (finite differences under common  */
+/* random numbers; variance below the score's).                               */
+/* ------------------------------------------------------------------------ */
+static void deriv_pairs(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth,
+                        uint32_t e, const double *xe, double te)
+{
+    const orc_config *C = &S->cfg;
+    const double dt = C->dt;
+    for (int m = 0; m < C->M; m++) {
+        jump_t J;
+        double sgnV;
+        draw_jump(S, I, P->id, e, m, xe, 0.0, (double)S->step * dt + te, &J);
+        kernel_at(S, I, m, (double)S->step * dt + te, &J.c, &sgnV);
+        double cs = orc_dcos(J.arg);
+        uint32_t ru[4], rc[4];
+        rng4(C->seed, I->key_inst, P->id, S->step, TAG_DERIV, e, (uint32_t)m, ru);
+        if (!(orc_u01(ru[0], ru[1]) < J.c * fabs(cs))) continue;
+        rng4(C->seed, I->key_inst, P->id, S->step, TAG_DERIV, e, (uint32_t)(8 + m), rc);
+        uint64_t cid[2] = {
+            (3ull << 62) | ((uint64_t)(rc[1] & 0x3FFFFFFFu) << 32) | rc[0],
+            (3ull << 62) | ((uint64_t)(rc[3] & 0x3FFFFFFFu) << 32) | rc[2] };
+        double kick = (cs > 0.0 ? sgnV : -sgnV) * J.q;
+        double dx0 = (2.0 * J.q) * (double)P->sgn;
+        for (int side = 0; side < 2; side++) {
+            part_t ch;
+            memset(&ch, 0, sizeof(ch));
+            ch.k[0] = P->k[0]; ch.k[1] = P->k[1];
+            switch (C->comp_axis[m]) {
+            case 0: ch.k[0] = side == 0 ? P->k[0] + kick : P->k[0] - kick; break;
+            case 1: ch.k[1] = side == 0 ? P->k[1] + kick : P->k[1] - kick; break;
+            default:
+                ch.k[0] = side == 0 ? P->k[0] + kick : P->k[0] - kick;
+                ch.k[1] = side == 0 ? P->k[1] - kick : P->k[1] + kick;
+                break;
+            }
+            ch.sgn = 0;
+            ch.w = 0.0;
+            ch.id = cid[side];
+            ch.D[2] = side == 0 ? -dx0 : dx0;
+            if (!in_kbox(S, ch.k)) continue;   /* nullified outside K, like any offspring */
+            ch.t0 = te;
+            part_t rec = ch;
+            for (int d = 0; d < C->dim; d++) {
+                ch.x[d] = xe[d];
+                rec.x[d] = xe[d] + (S->vfac * ch.k[d]) * (dt - te);
+            }
+            ens_push(out, &rec);
+            walk(S, I, out, &ch, depth + 1);
+        }
+    }
+}
+
 static void walk(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth)
 {
     const orc_config *C = &S->cfg;
@@ -656,7 +727,7 @@ static void walk(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth)
                 double wdt = I->width[m];
                 score[0] = 1.0 / I->H[m];
                 score[1] = 1.0 / wdt - ((4.0 * wdt) * q) * q;
-                score[2] = -(2.0 * q) * (orc_dcos(arg) / sn);
+                score[2] = C->track_tangent == 2 ? 0.0 : -(2.0 * q) * (orc_dcos(arg) / sn);
             }
             for (int side = 0; side < 2; side++) {
                 double sdir = side == 0 ? 1.0 : -1.0;
@@ -698,6 +769,7 @@ static void walk(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth)
                 walk(S, I, out, &ch, depth + 1);
             }
         }
+        if (C->track_tangent == 2 && P->sgn != 0) deriv_pairs(S, I, out, P, depth, e, xe, te);
         t = te;
     }
 }

@@ -61,6 +61,7 @@ int validate(const wbrw_config *c)
     if (!(c->hbar > 0) || !(c->mass > 0) || !(c->dt > 0)) return WBRW_EINVAL;
     if (!(c->x_hi > c->x_lo) || !(c->k_hi > c->k_lo) || c->nx < 1 || c->nk < 1) return WBRW_EINVAL;
     if (c->max_density_bins < 1) return WBRW_EINVAL;
+    if (c->track_tangent < 0 || c->track_tangent > 2) return WBRW_EINVAL;
     if (c->track_tangent) {
         if (c->strategy != WBRW_SP1 || c->dim != 1 || c->n_components != 1 ||
             c->comp[0].kind != WBRW_KERNEL_GAUSSIAN || c->ghost_capacity < 1 || c->comp[0].modulated)

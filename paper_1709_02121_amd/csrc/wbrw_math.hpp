@@ -22,7 +22,7 @@ namespace wbrw {
 
 enum : uint32_t {
     kTagStep = 0u, kTagRegen = 1u, kTagInit = 2u, kTagBoot = 3u,
-    kTagRound = 4u, kTagChild = 5u, kTagGhost = 6u, kTagHist = 7u, kTagReject = 8u
+    kTagRound = 4u, kTagChild = 5u, kTagGhost = 6u, kTagHist = 7u, kTagReject = 8u, kTagDeriv = 9u
 };
 
 struct W4 { uint32_t a, b, c, d; };

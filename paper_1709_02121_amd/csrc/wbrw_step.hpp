@@ -236,18 +236,19 @@ struct Tally {
     int32_t maxdepth;
 };
 
-// The records of a family found by fast_family (at most kStash: nearly
-// always one pair), kept in LDS until the ordered scan has placed them.
-constexpr int kStash = 2;
+// The records of a family found by fast_family (at most R: nearly always
+// one pair, and with derivative pairs at most one of each), kept in LDS
+// until the ordered scan has placed them.
 template <int DIM, bool SP2, bool TAN>
 struct Stash {
-    double x0[kStash][kTileB], k0[kStash][kTileB];
-    double x1[DIM == 2 ? kStash : 1][DIM == 2 ? kTileB : 1];
-    double k1[DIM == 2 ? kStash : 1][DIM == 2 ? kTileB : 1];
-    double w[SP2 ? kStash : 1][SP2 ? kTileB : 1];
-    double D[TAN ? 3 * kStash : 1][TAN ? kTileB : 1];
-    uint64_t id[kStash][kTileB];
-    int8_t sg[kStash][kTileB];
+    static constexpr int R = TAN ? 4 : 2;
+    double x0[R][kTileB], k0[R][kTileB];
+    double x1[DIM == 2 ? R : 1][DIM == 2 ? kTileB : 1];
+    double k1[DIM == 2 ? R : 1][DIM == 2 ? kTileB : 1];
+    double w[SP2 ? R : 1][SP2 ? kTileB : 1];
+    double D[TAN ? 3 * R : 1][TAN ? kTileB : 1];
+    uint64_t id[R][kTileB];
+    int8_t sg[R][kTileB];
 };
 
 // Records of the families that took the general walk, in order of creation
@@ -327,11 +328,9 @@ __device__ __forceinline__ bool draw_pair(const Dev &d, const InstParam &P, uint
 // Offspring `side` (0: "+", 1: "-") of the pair J of component m at jump e;
 // rc is the child-id draw of (parent, e, m).  Sets k, sign, weight, id and
 // tangent of ch.
-template <bool SP2, bool TAN>
-__device__ __forceinline__ void make_child(const Dev &d, const InstParam &P, const Node &par, int m, int side,
+__device__ __forceinline__ void child_id_k(const Dev &d, const Node &par, uint64_t cls, int m, int side,
                                            const PairDraw &J, const W4 &rc, Node &ch)
 {
-    const uint64_t cls = ((par.id >> 62) & 1ull) ? 3ull : 2ull;   // ghost lineages keep bit 62
     ch.id = side == 0 ? ((cls << 62) | ((uint64_t)(rc.b & 0x3FFFFFFFu) << 32) | (uint64_t)rc.a)
                       : ((cls << 62) | ((uint64_t)(rc.d & 0x3FFFFFFFu) << 32) | (uint64_t)rc.c);
     const double kick = J.sigma * J.q;
@@ -346,13 +345,22 @@ __device__ __forceinline__ void make_child(const Dev &d, const InstParam &P, con
         ch.k[0] = side == 0 ? par.k[0] + kick : par.k[0] - kick;
         ch.k[1] = side == 0 ? par.k[1] - kick : par.k[1] + kick;
     }
+}
+
+template <bool SP2, bool TAN>
+__device__ __forceinline__ void make_child(const Dev &d, const InstParam &P, const Node &par, int m, int side,
+                                           const PairDraw &J, const W4 &rc, Node &ch)
+{
+    const uint64_t cls = ((par.id >> 62) & 1ull) ? 3ull : 2ull;   // ghost lineages keep bit 62
+    child_id_k(d, par, cls, m, side, J, rc, ch);
     ch.sg = side == 0 ? par.sg : -par.sg;
     ch.w = side == 0 ? J.amp : -J.amp;
     if (TAN) {
         const double wd = P.width[m];
         const double s0 = 1.0 / P.H[m];
         const double s1 = 1.0 / wd - ((4.0 * wd) * J.q) * J.q;
-        const double s2 = -(2.0 * J.q) * (cos_det(J.arg) / J.sn);
+        // tangent mode 2 carries the x0 derivative by derivative pairs instead
+        const double s2 = d.tangent == 2 ? 0.0 : -(2.0 * J.q) * (cos_det(J.arg) / J.sn);
         const double sdir = side == 0 ? 1.0 : -1.0;
         const double sgd = (double)ch.sg;
         ch.D[0] = sdir * par.D[0] + sgd * s0;
@@ -361,6 +369,44 @@ __device__ __forceinline__ void make_child(const Dev &d, const InstParam &P, con
     } else {
         ch.D[0] = ch.D[1] = ch.D[2] = 0.0;
     }
+}
+
+// Derivative pair of component m at jump e (tangent mode 2).  The pair
+// intensity per unit kick density, c sin(2 q (x - x0)), depends on x0 only
+// through the sine, whose x0-derivative gives -2 q c cos(2 q (x - x0)).
+// With the jump's own kick q and an independent uniform, a pair of ghosts
+// is created with probability c |cos|, directed by sgn(F[V]) sgn(cos); the
+// "+" ghost carries the x0-tangent -2 q s and the "-" ghost +2 q s (s the
+// parent's sign).  Its expectation is the x0-derivative of the signed pair
+// measure with a tangent bounded by 2|q|, where the score -2q cot(2 q r) has
+// infinite variance.  Returns false if no pair is created.
+__device__ __forceinline__ bool draw_deriv(const Dev &d, const InstParam &P, uint64_t id, uint32_t step,
+                                           uint32_t e, int m, const double *xe, PairDraw &J,
+                                           const W4 *kick_draw = nullptr)
+{
+    const W4 rq = kick_draw ? *kick_draw : draw(id, step, kTagStep, e, (uint32_t)(1 + m), d.seed, P.key);
+    const W4 ru = draw(id, step, kTagDeriv, e, (uint32_t)m, d.seed, P.key);
+    J.q = kick_sample(d, P, m, unit53(rq.a, rq.b), unit53(rq.c, rq.d));
+    J.arg = (2.0 * J.q) * phase_offset(d, m, xe, P.center[m]);
+    const double cs = cos_det(J.arg);
+    if (!(unit53(ru.a, ru.b) < P.c[m] * fabs(cs))) return false;
+    J.sn = cs;
+    J.sigma = (cs > 0.0) ? P.sgnV[m] : -P.sgnV[m];
+    J.amp = 0.0;
+    return true;
+}
+
+// Ghost `side` of the derivative pair J (rc: its id draw); ghost lineage ids.
+__device__ __forceinline__ void make_deriv_child(const Dev &d, const Node &par, int m, int side,
+                                                 const PairDraw &J, const W4 &rc, Node &ch)
+{
+    child_id_k(d, par, 3ull, m, side, J, rc, ch);
+    ch.sg = 0;
+    ch.w = 0.0;
+    const double dx0 = (2.0 * J.q) * (double)par.sg;
+    ch.D[0] = 0.0;
+    ch.D[1] = 0.0;
+    ch.D[2] = side == 0 ? -dx0 : dx0;
 }
 
 // k-truncation tally of a child that left the k-box (Sec. 2)
@@ -448,6 +494,25 @@ __device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, ui
     xe[0] = root.x[0] + (d.vfac * root.k[0]) * (te - root.t0);
     xe[1] = DIM == 2 ? root.x[1] + (d.vfac * root.k[1]) * (te - root.t0) : 0.0;
     bool fast = true;
+    auto put_pair = [&](Node (&ch)[2]) {
+        // both offspring's first clock draws, together
+        const W4 l0 = draw(ch[0].id, step, kTagStep, 0u, 0u, seed, key);
+        const W4 l1 = draw(ch[1].id, step, kTagStep, 0u, 0u, seed, key);
+        for (int side = 0; side < 2; ++side) {
+            if (!in_kbox<DIM>(d, ch[side].k)) {
+                tl.killed += killed_amount<SP2>(ch[side]);
+                continue;
+            }
+            if (cnt < (uint32_t)Stash<DIM, SP2, TAN>::R)
+                stash_record<DIM, SP2, TAN>(d, sh, (int)cnt, slot, xe, te, ch[side]);
+            else fast = false;
+            cnt++;
+            if (tl.maxdepth < 1) tl.maxdepth = 1;
+            const double u0 = side == 0 ? unit53(l0.a, l0.b) : unit53(l1.a, l1.b);
+            if (!surely_no_jump(u0, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u0) / P.gamma0) <= d.dt)
+                fast = false;
+        }
+    };
     for (int m = 0; m < d.M; ++m) {
         PairDraw J;
         if (!draw_pair<SP2>(d, P, root.id, step, 0u, m, xe, te, ua0, root.w, J, m == 0 ? &rq0 : nullptr))
@@ -457,21 +522,17 @@ __device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, ui
         Node ch[2];
         make_child<SP2, TAN>(d, P, root, m, 0, J, rc, ch[0]);
         make_child<SP2, TAN>(d, P, root, m, 1, J, rc, ch[1]);
-        // both offspring's first clock draws, together
-        const W4 l0 = draw(ch[0].id, step, kTagStep, 0u, 0u, seed, key);
-        const W4 l1 = draw(ch[1].id, step, kTagStep, 0u, 0u, seed, key);
-        for (int side = 0; side < 2; ++side) {
-            if (!in_kbox<DIM>(d, ch[side].k)) {
-                tl.killed += killed_amount<SP2>(ch[side]);
-                continue;
-            }
-            if (cnt < (uint32_t)kStash) stash_record<DIM, SP2, TAN>(d, sh, (int)cnt, slot, xe, te, ch[side]);
-            else fast = false;
-            cnt++;
-            if (tl.maxdepth < 1) tl.maxdepth = 1;
-            const double u0 = side == 0 ? unit53(l0.a, l0.b) : unit53(l1.a, l1.b);
-            if (!surely_no_jump(u0, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u0) / P.gamma0) <= d.dt)
-                fast = false;
+        put_pair(ch);
+    }
+    if (TAN && d.tangent == 2 && root.sg != 0) {
+        for (int m = 0; m < d.M; ++m) {    // derivative pairs, after the jump's real pairs
+            PairDraw J;
+            if (!draw_deriv(d, P, root.id, step, 0u, m, xe, J, m == 0 ? &rq0 : nullptr)) continue;
+            const W4 rc = draw(root.id, step, kTagDeriv, 0u, (uint32_t)(8 + m), seed, key);
+            Node ch[2];
+            make_deriv_child(d, root, m, 0, J, rc, ch[0]);
+            make_deriv_child(d, root, m, 1, J, rc, ch[1]);
+            put_pair(ch);
         }
     }
     const double u1 = unit53(r1.a, r1.b);
@@ -532,22 +593,27 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
                 continue;
             }
         }
-        if (cur.m >= M) {
+        // pair slots of a jump: components 0..M-1, then (tangent mode 2,
+        // signed particles) their derivative pairs as slots M..2M-1
+        const int mend = (TAN && d.tangent == 2 && cur.sg != 0) ? 2 * M : M;
+        if (cur.m >= mend) {
             cur.t = cur.te;
             cur.e += 1u;
             cur.in_ev = 0;
             continue;
         }
-        const int m = cur.m;
+        const bool dv = TAN && cur.m >= M;
+        const int m = dv ? cur.m - M : cur.m;
         PairDraw J;
         W4 rc;
         if (cur.side == 0) {
-            if (!draw_pair<SP2>(d, P, cur.id, step, cur.e, m, cur.xe, cur.te, cur.ua0, cur.w, J)) {
+            if (dv ? !draw_deriv(d, P, cur.id, step, cur.e, m, cur.xe, J)
+                   : !draw_pair<SP2>(d, P, cur.id, step, cur.e, m, cur.xe, cur.te, cur.ua0, cur.w, J)) {
                 cur.m += 1;
                 continue;
             }
-            rc = draw(cur.id, step, kTagChild, cur.e, (uint32_t)m, seed, key);
-            if (!EMIT) tl.pairs++;
+            rc = draw(cur.id, step, dv ? kTagDeriv : kTagChild, cur.e, (uint32_t)(dv ? 8 + m : m), seed, key);
+            if (!EMIT && !dv) tl.pairs++;
         } else {
             J = stackJ[sp];        // saved when this frame descended into its "+" offspring
             rc = stackR[sp];
@@ -555,7 +621,8 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
         bool descend = false;
         Node ch;
         for (int side = cur.side; side < 2 && !descend; ++side) {
-            make_child<SP2, TAN>(d, P, cur, m, side, J, rc, ch);
+            if (dv) make_deriv_child(d, cur, m, side, J, rc, ch);
+            else make_child<SP2, TAN>(d, P, cur, m, side, J, rc, ch);
             if (!in_kbox<DIM>(d, ch.k)) {          // k-truncation (Sec. 2)
                 if (!EMIT) tl.killed += killed_amount<SP2>(ch);
                 continue;

@@ -203,18 +203,29 @@ def _close(a, b, what, rtol=1e-9):
     assert err <= rtol * scale, f"{what}: max abs err {err:.3e} vs scale {scale:.3e}"
 
 
-def test_tangent_parity(P, O):
-    """Likelihood-ratio tangents: the real ensemble stays bit-exact, ghosts
-    (integer creation rule) match exactly in count, position and id, and the
-    tangents (order-dependent floating sums per cell) agree to 1e-9 relative."""
-    cfg = W.gaussian_barrier_small(N0=np.array([5000]), gamma0=0.45, track_tangent=1)
+@pytest.mark.parametrize("mode", [1, 2])
+def test_tangent_parity(P, O, mode):
+    """Tangents (mode 1: likelihood-ratio scores; mode 2: x0 by derivative
+    ghost pairs, which ride in the real ensemble with sign 0 until the next
+    annihilation): the real ensemble stays bit-exact, ghosts (integer creation
+    rule) match exactly in count, position and id, and the tangents
+    (order-dependent floating sums per cell) agree to 1e-9 relative."""
+    cfg = W.gaussian_barrier_small(N0=np.array([5000]), gamma0=0.45, track_tangent=mode)
     g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.step(3)
+    r.step(3)
+    say(f"tangent mode {mode}: 3 steps n={r.count()}")
+    compare(g, r, f"tangent mode {mode} before annihilation")
+    _close(g.particles()["D"], r.particles()["D"], "real tangents before annihilation")
+    g.step(7)
+    r.step(7)
     for ep in range(3):
-        g.step(10)
-        r.step(10)
+        if ep:
+            g.step(10)
+            r.step(10)
         g.annihilate()
         r.annihilate()
-        say(f"tangent: epoch {ep} n={r.count()} ghosts={r.count(ghost=True)}")
+        say(f"tangent mode {mode}: epoch {ep} n={r.count()} ghosts={r.count(ghost=True)}")
         compare(g, r, f"tangent real {ep}")
         pg, pr = g.particles(), r.particles()
         _close(pg["D"], pr["D"], f"real tangents {ep}")
