@@ -62,9 +62,10 @@ typedef struct {
     int32_t M;              /* kernel components */
     int32_t B;              /* instances */
     int32_t instance_offset;/* key index of instance 0 (lets one instance replay instance b) */
-    int32_t track_tangent;  /* 1: carry LR tangents (sp1, single Gaussian component);
-                             * 2: the same for (H, w), and the x0 tangent by
-                             * derivative ghost pairs (see deriv_pairs) */
+    int32_t track_tangent;  /* single Gaussian component.  sp1: 1 = LR tangents;
+                             * 2 = the same for (H, w), and the x0 tangent by
+                             * derivative ghost pairs (see deriv_pairs).
+                             * sp2: 1 = pathwise weight tangents (see walk) */
     uint32_t seed;
     int32_t pad0;
     double hbar, mass, dt, gamma0, gamma_scale;
@@ -341,6 +342,7 @@ typedef struct {
     inst_t *I;
     uint32_t step;          /* number of completed steps */
     double vfac;            /* hbar / mass */
+    int ghost_pass;         /* stepping the ghost ensemble (sp1 branching rule) */
 } orc_sim;
 
 /* ------------------------------------------------------------------------ */
@@ -666,7 +668,10 @@ static void walk(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth)
 {
     const orc_config *C = &S->cfg;
     const double dt = C->dt;
-    const int sp2 = (C->strategy == STRAT_SP2);
+    /* ghosts (weight 0) branch by the sp1 rule in either strategy: a pair
+     * with probability c|sin| carries the parent's tangent, which has the
+     * expectation of wp's always-emitted pair with tangent factor c|sin| */
+    const int sp2 = (C->strategy == STRAT_SP2) && !S->ghost_pass;
     if (depth > I->st.max_depth) I->st.max_depth = depth;
     double t = P->t0;
     for (uint32_t e = 0;; e++) {
@@ -723,11 +728,28 @@ static void walk(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth)
             double kick = sigma * q;
             /* LR score of (kick density, acceptance) w.r.t. (H, w, x0) */
             double score[3] = { 0.0, 0.0, 0.0 };
+            /* sp2: the "+" child's tangent X, the "-" child's -X (see below) */
+            double X[3] = { 0.0, 0.0, 0.0 };
             if (C->track_tangent) {
                 double wdt = I->width[m];
                 score[0] = 1.0 / I->H[m];
                 score[1] = 1.0 / wdt - ((4.0 * wdt) * q) * q;
-                score[2] = C->track_tangent == 2 ? 0.0 : -(2.0 * q) * (orc_dcos(arg) / sn);
+                if (sp2) {
+                    /* The pair adds w c sgn(V) sin(2qr) [f(k+q) - f(k-q)] with q from
+                     * G/xi_hat (wp box of Alg. 1, Remark 3).  Differentiating its
+                     * expectation: the kick density times c is G/(2 gamma0), whose
+                     * log-derivative is score[0..1] (zero for x0), the parent's weight
+                     * carries D, and sin(2q(x - x0)) has x0-derivative -2q cos.  In
+                     * the children's frame (k +/- sigma q, weights +/- w c|sin|):
+                     * X = c|sin| (D + w score) + w c sgn(sin) d(sin)/d(theta). */
+                    double a = J.c * fabs(sn);
+                    double g = P->w * (J.c * (sn > 0.0 ? 1.0 : -1.0));
+                    X[0] = a * (P->D[0] + P->w * score[0]);
+                    X[1] = a * (P->D[1] + P->w * score[1]);
+                    X[2] = a * P->D[2] + g * (-(2.0 * q) * orc_dcos(arg));
+                } else {
+                    score[2] = C->track_tangent == 2 ? 0.0 : -(2.0 * q) * (orc_dcos(arg) / sn);
+                }
             }
             for (int side = 0; side < 2; side++) {
                 double sdir = side == 0 ? 1.0 : -1.0;
@@ -747,7 +769,7 @@ static void walk(orc_sim *S, inst_t *I, ens_t *out, const part_t *P, int depth)
                 ch.id = cid[side];
                 if (C->track_tangent) {
                     for (int c = 0; c < 3; c++)
-                        ch.D[c] = sdir * P->D[c] + (double)ch.sgn * score[c];
+                        ch.D[c] = sp2 ? sdir * X[c] : sdir * P->D[c] + (double)ch.sgn * score[c];
                 }
                 if (!in_kbox(S, ch.k)) {   /* k-truncation: nullified outside K */
                     if (sp2) {
@@ -802,7 +824,11 @@ void orc_step(orc_sim *S, int nsteps)
         for (int b = 0; b < S->cfg.B; b++) {
             inst_t *I = &S->I[b];
             step_ensemble(S, I, &I->real);
-            if (S->cfg.track_tangent) step_ensemble(S, I, &I->ghost);
+            if (S->cfg.track_tangent) {
+                S->ghost_pass = 1;
+                step_ensemble(S, I, &I->ghost);
+                S->ghost_pass = 0;
+            }
         }
         S->step++;
     }
@@ -1116,10 +1142,34 @@ static void annihilate_sp2(orc_sim *S, inst_t *I)
         int64_t m = orc_round_cell(an, den, S->cfg.seed, I->key_inst, S->step, (uint64_t)nu);
         cnt[nu] = num < 0 ? -m : m;
     }
-    regenerate(S, I, cnt, NULL, NULL);
+    /* tangents: the cell sums of Eq. boostrap_histogram's expectation,
+     * sum of w_i, are differentiated directly: T_nu = sum of D_i over the
+     * particles and ghosts in the cell, as in sp1 */
+    int64_t *occ = NULL;
+    double *T = NULL;
+    if (S->cfg.track_tangent) {
+        occ = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+        T = (double *)calloc((size_t)nc * 3, sizeof(double));
+        for (int64_t i = 0; i < n; i++) {
+            if (cell[i] < 0) continue;
+            occ[cell[i]] += 1;
+            for (int c = 0; c < 3; c++) T[3 * cell[i] + c] += I->real.D[3 * i + c];
+        }
+        for (int64_t i = 0; i < I->ghost.n; i++) {
+            double x[2] = { I->ghost.x[0][i], I->ghost.x[1][i] };
+            double k[2] = { I->ghost.k[0][i], I->ghost.k[1][i] };
+            int64_t nu = cell_of(S, x, k);
+            if (nu < 0) continue;
+            occ[nu] += 1;
+            for (int c = 0; c < 3; c++) T[3 * nu + c] += I->ghost.D[3 * i + c];
+        }
+    }
+    regenerate(S, I, cnt, occ, T);
     for (int c = 0; c < 2; c++) { free(A[c]); free(idx[c]); free(ntil[c]); }
     free(cell);
     free(cnt);
+    free(occ);
+    free(T);
 }
 
 void orc_annihilate(orc_sim *S)
