@@ -208,6 +208,7 @@ def main():
                 ("batched_256", lambda: W.batched_barriers(), 100, 10),
                 ("fwd_adjoint", lambda: W.differentiation(), 50, 10),
                 ("fwd_adjoint_x0_deriv_pairs", lambda: W.differentiation(track_tangent=2), 50, 10),
+                ("fwd_adjoint_sp2", lambda: W.differentiation(strategy="sp2"), 50, 10),
                 ("helium_4d", lambda: W.helium_soft_coulomb(), 10, 0)):
             try:
                 torch.cuda.empty_cache()

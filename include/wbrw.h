@@ -100,10 +100,13 @@ typedef struct wbrw_config {
     int32_t n_components;     /* 1 .. WBRW_MAX_COMPONENTS */
     int32_t n_instances;      /* B, 1 .. 65536 independent ensembles */
     int32_t instance_offset;  /* instance b draws with key index instance_offset + b */
-    int32_t track_tangent;    /* 0: none; 1: carry d/d(H, w, x0) tangents by likelihood-ratio
-                                 scores (sp1, dim 1, one Gaussian component); 2: the same for
-                                 (H, w), and d/dx0 by derivative ghost pairs instead of the
-                                 x0 score (finite variance; see wbrw_density_tangent) */
+    int32_t track_tangent;    /* tangents d/d(H, w, x0) (dim 1, one static Gaussian component,
+                                 majorant sampler).  0: none.  sp1: 1 = likelihood-ratio
+                                 scores of the kick density and pair acceptance; 2 = the same
+                                 for (H, w), and d/dx0 by derivative ghost pairs instead of
+                                 the x0 score (finite variance).  sp2: 1 = pathwise weight
+                                 derivatives with the kick-density score (finite variance);
+                                 2 is rejected.  Ghosts branch by the sp1 rule. */
     uint32_t seed;            /* Philox key word */
     int32_t max_density_bins; /* largest nbins a later wbrw_density() may ask for */
     double hbar, mass;        /* free flight x += (hbar/mass) k dt */
@@ -232,10 +235,13 @@ int wbrw_stats(wbrw_t h, int32_t b, wbrw_stats_t *out);
 /* Synchronises and writes the particle count of instance b (ghost != 0: ghosts). */
 int wbrw_count(wbrw_t h, int32_t b, int32_t ghost, int64_t *n);
 
-/* Copies instance b's ensemble into caller device buffers (any may be NULL):
- * x, k: [dim][n] doubles; sign: [n] int8 (sp1); w: [n] doubles (sp2 weights,
- * sp1 signs as +-1.0); id: [n] uint64 lineage ids; D: [n][3] tangents.
- * n must equal the current count (wbrw_count).  Enqueued copies, no sync. */
+/* Copies instance b's ensemble (ghost != 0: its tangent ghosts) into caller
+ * device buffers, any of which may be NULL: x, k: [dim][n] doubles; sign: [n]
+ * int8 (sp1 particles; ghosts in either strategy, where it is 0); w: [n]
+ * doubles (sp2 particles only); id: [n] uint64 lineage ids; D: [n][3]
+ * tangents (track_tangent only).  n must equal the current count
+ * (wbrw_count).  WBRW_EINVAL if n differs or a requested field does not exist
+ * for this ensemble.  Synchronises the handle's stream before and after. */
 int wbrw_export(wbrw_t h, int32_t b, int32_t ghost, int64_t n, double *x, double *k,
                 int8_t *sign, double *w, uint64_t *id, double *D);
 

@@ -342,7 +342,8 @@ class Simulation:
         x = t.empty((self.dim, n), dtype=t.float64, device=dev)
         k = t.empty((self.dim, n), dtype=t.float64, device=dev)
         ids = t.empty(n, dtype=t.int64, device=dev)
-        sp2 = self.cfg["strategy"] == "sp2"
+        # ghosts hold a sign (always 0) in either strategy
+        sp2 = self.cfg["strategy"] == "sp2" and not ghost
         s = t.empty(n, dtype=t.int8, device=dev) if not sp2 else None
         w = t.empty(n, dtype=t.float64, device=dev) if sp2 else None
         tan = bool(self.cfg.get("track_tangent", 0))

@@ -63,7 +63,8 @@ int validate(const wbrw_config *c)
     if (c->max_density_bins < 1) return WBRW_EINVAL;
     if (c->track_tangent < 0 || c->track_tangent > 2) return WBRW_EINVAL;
     if (c->track_tangent) {
-        if (c->strategy != WBRW_SP1 || c->dim != 1 || c->n_components != 1 ||
+        // sp2's x0 tangent is pathwise and bounded: derivative pairs are sp1's
+        if ((c->strategy == WBRW_SP2 && c->track_tangent != 1) || c->dim != 1 || c->n_components != 1 ||
             c->comp[0].kind != WBRW_KERNEL_GAUSSIAN || c->ghost_capacity < 1 || c->comp[0].modulated)
             return WBRW_EINVAL;
     }
@@ -383,7 +384,9 @@ void enqueue_step_dim(wbrw_t h)
     hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 0);
     hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
     stage_begin(h, WBRW_STAGE_FAMILY);
-    if (h->strategy == WBRW_SP2)
+    if (h->strategy == WBRW_SP2 && tan)
+        hipLaunchKernelGGL((k_family<DIM, true, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
+    else if (h->strategy == WBRW_SP2)
         hipLaunchKernelGGL((k_family<DIM, true, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     else if (tan)
         hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
@@ -391,7 +394,9 @@ void enqueue_step_dim(wbrw_t h)
         hipLaunchKernelGGL((k_family<DIM, false, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
     hipLaunchKernelGGL(k_close_records, dim3(1), dim3(kThreads), 0, s, d, 0);
-    if (h->strategy == WBRW_SP2)
+    if (h->strategy == WBRW_SP2 && tan)
+        hipLaunchKernelGGL((k_place_records<DIM, true, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
+    else if (h->strategy == WBRW_SP2)
         hipLaunchKernelGGL((k_place_records<DIM, true, false>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
     else if (tan)
         hipLaunchKernelGGL((k_place_records<DIM, false, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
@@ -399,6 +404,7 @@ void enqueue_step_dim(wbrw_t h)
         hipLaunchKernelGGL((k_place_records<DIM, false, false>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
     hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 0, tan ? 0 : 1, h->grid[G_FAMILY]);
     if (tan) {
+        // ghosts (weight 0) branch by the sp1 rule in either strategy
         stage_begin(h, WBRW_STAGE_GHOST);
         hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 1);
@@ -424,24 +430,40 @@ int enqueue_annihilate_dim(wbrw_t h)
     const Dev &d = h->d;
     hipStream_t s = h->stream;
     if (h->strategy == WBRW_SP2) {
+        const bool tan = h->tangent != 0;
+        if (tan) {
+            // occupancy and tangent sums per cell, particles and ghosts
+            stage_begin(h, WBRW_STAGE_BIN);
+            hipLaunchKernelGGL((k_bin<DIM, true, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
+            hipLaunchKernelGGL((k_bin<DIM, true, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 1);
+            stage_end(h);
+        }
         stage_begin(h, WBRW_STAGE_BOOTSTRAP);
         int rc = enqueue_sp2_bootstrap<DIM>(d, s, h->grid[G_SP2], h->grid[G_SCAN]);
         stage_end(h);
         if (rc) return rc;
         stage_begin(h, WBRW_STAGE_SCAN);
-        hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
+        // with tangents the counts stay for the ghost pass, which clears them
+        hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, tan ? 0 : 1);
         hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
         stage_end(h);
         stage_begin(h, WBRW_STAGE_REGEN);
-        hipLaunchKernelGGL((k_regen<DIM, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+        if (tan) hipLaunchKernelGGL((k_regen<DIM, true, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+        else hipLaunchKernelGGL((k_regen<DIM, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
         hipLaunchKernelGGL(k_close_regen, dim3(1), dim3(kThreads), 0, s, d);
         stage_end(h);
+        if (tan) {
+            stage_begin(h, WBRW_STAGE_GHOST);
+            hipLaunchKernelGGL(k_ghosts, dim3(h->grid[G_GHOST]), dim3(kThreads), 0, s, d);
+            hipLaunchKernelGGL(k_close_ghosts, dim3(1), dim3(kThreads), 0, s, d);
+            stage_end(h);
+        }
         return launch_check();
     }
     if (h->tangent) {
         stage_begin(h, WBRW_STAGE_BIN);
-        hipLaunchKernelGGL((k_bin<DIM, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
-        hipLaunchKernelGGL((k_bin<DIM, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL((k_bin<DIM, false, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
+        hipLaunchKernelGGL((k_bin<DIM, false, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 1);
         stage_end(h);
         stage_begin(h, WBRW_STAGE_SCAN);
         hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 0);
@@ -458,7 +480,7 @@ int enqueue_annihilate_dim(wbrw_t h)
         return launch_check();
     }
     stage_begin(h, WBRW_STAGE_BIN);
-    hipLaunchKernelGGL((k_bin<DIM, false>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
+    hipLaunchKernelGGL((k_bin<DIM, false, false>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
     stage_begin(h, WBRW_STAGE_SCAN);
     hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
@@ -481,13 +503,15 @@ void set_grids_dim(wbrw_t h)
 {
     const int cus = h->cus;
     h->grid[G_STREAM] = persistent_blocks(k_stream<DIM>, cus);
-    if (h->strategy == WBRW_SP2)
+    if (h->strategy == WBRW_SP2 && h->tangent)
+        h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, true, true>, cus);
+    else if (h->strategy == WBRW_SP2)
         h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, true, false>, cus);
     else if (h->tangent)
         h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, false, true>, cus);
     else
         h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, false, false>, cus);
-    h->grid[G_BIN] = persistent_blocks(k_bin<DIM, false>, cus);
+    h->grid[G_BIN] = persistent_blocks(k_bin<DIM, false, false>, cus);
     h->grid[G_SCAN] = persistent_blocks(k_scan, cus);
     h->grid[G_REGEN] = persistent_blocks(k_regen<DIM, false, false>, cus);
     h->grid[G_DENS] = persistent_blocks(k_density_bin<DIM, false, false>, cus);
@@ -733,7 +757,8 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
         if (h->dim == 1) {
-            if (h->strategy == WBRW_SP2) hipLaunchKernelGGL((k_regen<1, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+            if (h->strategy == WBRW_SP2 && h->tangent) hipLaunchKernelGGL((k_regen<1, true, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
+            else if (h->strategy == WBRW_SP2) hipLaunchKernelGGL((k_regen<1, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
             else if (h->tangent) hipLaunchKernelGGL((k_regen<1, false, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
             else hipLaunchKernelGGL((k_regen<1, false, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
         } else {

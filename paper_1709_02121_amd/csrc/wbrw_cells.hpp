@@ -161,9 +161,11 @@ __global__ __launch_bounds__(kThreads) void k_hist_round(Dev d, const double *hi
 }
 
 // ---------------------------------------------------------------------------
-// sp1 annihilation, pass 1: binning with exact integer sums per cell.
+// sp1 annihilation, pass 1: binning with exact integer sums per cell.  With
+// tangents, also the occupancy and the tangent sums T_nu per cell (for sp2
+// only these: its counts come from the bootstrap).
 // ---------------------------------------------------------------------------
-template <int DIM, bool TAN>
+template <int DIM, bool SP2, bool TAN>
 __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
 {
     // Each block takes a contiguous run of tiles.  Without tangents the
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
             ka[j] = E.k0[i];
             xb[j] = DIM == 2 ? E.x1[i] : 0.0;
             kb[j] = DIM == 2 ? E.k1[i] : 0.0;
-            sv[j] = ghost ? 0 : (int)E.sg[i];
+            sv[j] = (ghost || SP2) ? 0 : (int)E.sg[i];
         }
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 // lanes hold consecutive particles: sum equal-cell runs in
                 // registers, then one atomic per run
                 bool commit;
-                if (!ghost) {
+                if (!ghost && !SP2) {   // sp2's cell counts come from the bootstrap
                     const int ns = run_sum<int>(nu, nu >= 0 ? s : 0, commit);
                     if (commit && ns != 0) atomicAdd(&d.cnt[cbase + nu], ns);
                 }

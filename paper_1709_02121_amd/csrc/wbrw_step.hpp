@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost)
 // ---------------------------------------------------------------------------
 // Kick and weight of a created pair (see draw_pair).
 struct PairDraw {
-    double q, arg, sn, sigma, amp;
+    double q, arg, sn, sigma, amp, c;
 };
 
 struct Node {
@@ -241,7 +241,7 @@ struct Tally {
 // until the ordered scan has placed them.
 template <int DIM, bool SP2, bool TAN>
 struct Stash {
-    static constexpr int R = TAN ? 4 : 2;
+    static constexpr int R = (TAN && !SP2) ? 4 : 2;
     double x0[R][kTileB], k0[R][kTileB];
     double x1[DIM == 2 ? R : 1][DIM == 2 ? kTileB : 1];
     double k1[DIM == 2 ? R : 1][DIM == 2 ? kTileB : 1];
@@ -312,6 +312,7 @@ __device__ __forceinline__ bool draw_pair(const Dev &d, const InstParam &P, uint
     }
     J.sigma = (J.sn > 0.0) ? sgv : -sgv;
     J.amp = 0.0;
+    J.c = cm;
     if (!SP2 && !alg4) {
         double ua = ua0;
         if (m > 0) {
@@ -355,7 +356,27 @@ __device__ __forceinline__ void make_child(const Dev &d, const InstParam &P, con
     child_id_k(d, par, cls, m, side, J, rc, ch);
     ch.sg = side == 0 ? par.sg : -par.sg;
     ch.w = side == 0 ? J.amp : -J.amp;
-    if (TAN) {
+    if (TAN && SP2) {
+        // The wp pair adds w c sgn(V) sin(2qr) [f(k+q) - f(k-q)] with q drawn
+        // from G/xi_hat.  Differentiating its expectation: c times the kick
+        // density is G/(2 gamma0), whose log-derivative is (1/H, 1/w - 4wq^2, 0);
+        // the parent's weight carries D; sin(2q(x - x0)) has x0-derivative
+        // -2q cos.  In the children's frame (k +/- sigma q, weights
+        // +/- w c|sin|) the "+" child carries
+        // X = c|sin| (D + w dlogG) + w c sgn(sin) dsin, the "-" child -X.
+        const double wd = P.width[m];
+        const double s0 = 1.0 / P.H[m];
+        const double s1 = 1.0 / wd - ((4.0 * wd) * J.q) * J.q;
+        const double a = J.c * fabs(J.sn);
+        const double g = par.w * (J.c * (J.sn > 0.0 ? 1.0 : -1.0));
+        const double x0 = a * (par.D[0] + par.w * s0);
+        const double x1 = a * (par.D[1] + par.w * s1);
+        const double x2 = a * par.D[2] + g * (-(2.0 * J.q) * cos_det(J.arg));
+        const double sdir = side == 0 ? 1.0 : -1.0;
+        ch.D[0] = sdir * x0;
+        ch.D[1] = sdir * x1;
+        ch.D[2] = sdir * x2;
+    } else if (TAN) {
         const double wd = P.width[m];
         const double s0 = 1.0 / P.H[m];
         const double s1 = 1.0 / wd - ((4.0 * wd) * J.q) * J.q;

@@ -88,7 +88,9 @@ def test_invalid_configs_rejected(lib):
     c = W.gaussian_barrier_small(); c["components"][0]["width"] = np.array([0.0]); bad.append(c)
     c = W.gaussian_barrier_small(); c["capacity"] = 10; bad.append(c)           # below N0
     c = W.gaussian_barrier_small(); c["capacity"] = 1 << 31; bad.append(c)      # too large
-    c = W.gaussian_barrier_small(strategy="sp2", track_tangent=1); bad.append(c)
+    c = W.gaussian_barrier_small(strategy="sp2", track_tangent=2); bad.append(c)  # pairs are sp1's
+    c = W.gaussian_barrier_small(track_tangent=3); bad.append(c)
+    c = W.helium_soft_coulomb(track_tangent=1); bad.append(c)                   # tangents: 1D only
     c = W.helium_soft_coulomb(); c["components"][2]["sgn"] = 0.5; bad.append(c)
     for cfg in bad:
         with pytest.raises(P.WBRWError) as e:

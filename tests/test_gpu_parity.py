@@ -203,14 +203,16 @@ def _close(a, b, what, rtol=1e-9):
     assert err <= rtol * scale, f"{what}: max abs err {err:.3e} vs scale {scale:.3e}"
 
 
-@pytest.mark.parametrize("mode", [1, 2])
-def test_tangent_parity(P, O, mode):
-    """Tangents (mode 1: likelihood-ratio scores; mode 2: x0 by derivative
-    ghost pairs, which ride in the real ensemble with sign 0 until the next
-    annihilation): the real ensemble stays bit-exact, ghosts (integer creation
-    rule) match exactly in count, position and id, and the tangents
-    (order-dependent floating sums per cell) agree to 1e-9 relative."""
-    cfg = W.gaussian_barrier_small(N0=np.array([5000]), gamma0=0.45, track_tangent=mode)
+@pytest.mark.parametrize("strategy,mode", [("sp1", 1), ("sp1", 2), ("sp2", 1)])
+def test_tangent_parity(P, O, strategy, mode):
+    """Tangents (sp1 mode 1: likelihood-ratio scores; sp1 mode 2: x0 by
+    derivative ghost pairs, which ride in the real ensemble with sign 0 until
+    the next annihilation; sp2: pathwise weight tangents): the real ensemble
+    stays bit-exact, ghosts (integer creation rule) match exactly in count,
+    position and id, and the tangents (order-dependent floating sums per cell)
+    agree to 1e-9 relative."""
+    cfg = W.gaussian_barrier_small(N0=np.array([5000]), gamma0=0.45, track_tangent=mode,
+                                   strategy=strategy)
     g, r = P.Simulation(cfg), O.OracleSim(cfg)
     g.step(3)
     r.step(3)

@@ -3,7 +3,8 @@ times (default persistent grids and plain launches; the batched form with the
 autotuner and graph replay).  The oracle computes every particle of these
 ensembles in tens of seconds, so the comparison is over the whole ensemble,
 bit for bit, not over a sample: the 1e7-particle Gaussian barrier in sp1 and
-sp2, the differentiation form in both tangent modes, and the 1e7-particle 4D
+sp2, the differentiation form in every tangent mode (sp1 scores, sp1
+derivative pairs, sp2 pathwise), and the 1e7-particle 4D
 helium model.  The batched form (256 instances, 5.5e7 particles) is compared
 on sampled instances, each replayed by the oracle on its own through the
 instance key offset."""
@@ -106,10 +107,10 @@ def test_sp2_1e7(P, O):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("mode", [1, 2])
-def test_differentiation_1e7(P, O, mode):
-    epoch_parity(P, O, W.differentiation(track_tangent=mode), 10, f"differentiation mode {mode}",
-                 tangents=True)
+@pytest.mark.parametrize("strategy,mode", [("sp1", 1), ("sp1", 2), ("sp2", 1)])
+def test_differentiation_1e7(P, O, strategy, mode):
+    epoch_parity(P, O, W.differentiation(track_tangent=mode, strategy=strategy), 10,
+                 f"differentiation {strategy} mode {mode}", tangents=True)
 
 
 @pytest.mark.timeout(600)
