@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost)
 // ---------------------------------------------------------------------------
 // Kick and weight of a created pair (see draw_pair).
 struct PairDraw {
-    double q, arg, sn, sigma, amp, c;
+    double q, arg, sn, sigma, amp;
 };
 
 struct Node {
@@ -312,7 +312,6 @@ __device__ __forceinline__ bool draw_pair(const Dev &d, const InstParam &P, uint
     }
     J.sigma = (J.sn > 0.0) ? sgv : -sgv;
     J.amp = 0.0;
-    J.c = cm;
     if (!SP2 && !alg4) {
         double ua = ua0;
         if (m > 0) {
@@ -356,7 +355,7 @@ __device__ __forceinline__ void make_child(const Dev &d, const InstParam &P, con
     child_id_k(d, par, cls, m, side, J, rc, ch);
     ch.sg = side == 0 ? par.sg : -par.sg;
     ch.w = side == 0 ? J.amp : -J.amp;
-    if (TAN && SP2) {
+    if constexpr (TAN && SP2) {
         // The wp pair adds w c sgn(V) sin(2qr) [f(k+q) - f(k-q)] with q drawn
         // from G/xi_hat.  Differentiating its expectation: c times the kick
         // density is G/(2 gamma0), whose log-derivative is (1/H, 1/w - 4wq^2, 0);
@@ -367,8 +366,10 @@ __device__ __forceinline__ void make_child(const Dev &d, const InstParam &P, con
         const double wd = P.width[m];
         const double s0 = 1.0 / P.H[m];
         const double s1 = 1.0 / wd - ((4.0 * wd) * J.q) * J.q;
-        const double a = J.c * fabs(J.sn);
-        const double g = par.w * (J.c * (J.sn > 0.0 ? 1.0 : -1.0));
+        // tangents require a static kernel, so c is the instance's constant
+        const double cm = P.c[m];
+        const double a = cm * fabs(J.sn);
+        const double g = par.w * (cm * (J.sn > 0.0 ? 1.0 : -1.0));
         const double x0 = a * (par.D[0] + par.w * s0);
         const double x1 = a * (par.D[1] + par.w * s1);
         const double x2 = a * par.D[2] + g * (-(2.0 * J.q) * cos_det(J.arg));
@@ -376,7 +377,7 @@ __device__ __forceinline__ void make_child(const Dev &d, const InstParam &P, con
         ch.D[0] = sdir * x0;
         ch.D[1] = sdir * x1;
         ch.D[2] = sdir * x2;
-    } else if (TAN) {
+    } else if constexpr (TAN) {
         const double wd = P.width[m];
         const double s0 = 1.0 / P.H[m];
         const double s1 = 1.0 / wd - ((4.0 * wd) * J.q) * J.q;
@@ -486,6 +487,34 @@ __device__ __forceinline__ bool pool_record(const Dev &d, Pool<DIM, SP2, TAN> *p
     return true;
 }
 
+// A pair created at time te at xe, as fast_family keeps it: both children
+// into the stash (clearing `fast` if it is full) unless the k-box removes
+// them, and `fast` cleared if either child jumps again within the step.
+template <int DIM, bool SP2, bool TAN>
+__device__ __forceinline__ void leaf_pair(const Dev &d, const InstParam &P, uint32_t step, const Node (&ch)[2],
+                                          const double *xe, double te, Stash<DIM, SP2, TAN> *sh, int slot,
+                                          uint32_t &cnt, Tally &tl, bool &fast)
+{
+    // both offspring's first clock draws, together
+    const W4 l0 = draw(ch[0].id, step, kTagStep, 0u, 0u, d.seed, P.key);
+    const W4 l1 = draw(ch[1].id, step, kTagStep, 0u, 0u, d.seed, P.key);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        if (!in_kbox<DIM>(d, ch[side].k)) {
+            tl.killed += killed_amount<SP2>(ch[side]);
+            continue;
+        }
+        if (cnt < (uint32_t)Stash<DIM, SP2, TAN>::R)
+            stash_record<DIM, SP2, TAN>(d, sh, (int)cnt, slot, xe, te, ch[side]);
+        else fast = false;
+        cnt++;
+        if (tl.maxdepth < 1) tl.maxdepth = 1;
+        const double u0 = side == 0 ? unit53(l0.a, l0.b) : unit53(l1.a, l1.b);
+        if (!surely_no_jump(u0, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u0) / P.gamma0) <= d.dt)
+            fast = false;
+    }
+}
+
 // The common family in lockstep: the parent jumps once in the step, and
 // every kept child is a leaf (its first clock draw falls past the end of
 // the step).  Produces the same records, in the same order, and the same
@@ -515,25 +544,6 @@ __device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, ui
     xe[0] = root.x[0] + (d.vfac * root.k[0]) * (te - root.t0);
     xe[1] = DIM == 2 ? root.x[1] + (d.vfac * root.k[1]) * (te - root.t0) : 0.0;
     bool fast = true;
-    auto put_pair = [&](Node (&ch)[2]) {
-        // both offspring's first clock draws, together
-        const W4 l0 = draw(ch[0].id, step, kTagStep, 0u, 0u, seed, key);
-        const W4 l1 = draw(ch[1].id, step, kTagStep, 0u, 0u, seed, key);
-        for (int side = 0; side < 2; ++side) {
-            if (!in_kbox<DIM>(d, ch[side].k)) {
-                tl.killed += killed_amount<SP2>(ch[side]);
-                continue;
-            }
-            if (cnt < (uint32_t)Stash<DIM, SP2, TAN>::R)
-                stash_record<DIM, SP2, TAN>(d, sh, (int)cnt, slot, xe, te, ch[side]);
-            else fast = false;
-            cnt++;
-            if (tl.maxdepth < 1) tl.maxdepth = 1;
-            const double u0 = side == 0 ? unit53(l0.a, l0.b) : unit53(l1.a, l1.b);
-            if (!surely_no_jump(u0, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u0) / P.gamma0) <= d.dt)
-                fast = false;
-        }
-    };
     for (int m = 0; m < d.M; ++m) {
         PairDraw J;
         if (!draw_pair<SP2>(d, P, root.id, step, 0u, m, xe, te, ua0, root.w, J, m == 0 ? &rq0 : nullptr))
@@ -543,23 +553,64 @@ __device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, ui
         Node ch[2];
         make_child<SP2, TAN>(d, P, root, m, 0, J, rc, ch[0]);
         make_child<SP2, TAN>(d, P, root, m, 1, J, rc, ch[1]);
-        put_pair(ch);
+        leaf_pair<DIM, SP2, TAN>(d, P, step, ch, xe, te, sh, slot, cnt, tl, fast);
     }
-    if (TAN && d.tangent == 2 && root.sg != 0) {
-        for (int m = 0; m < d.M; ++m) {    // derivative pairs, after the jump's real pairs
-            PairDraw J;
-            if (!draw_deriv(d, P, root.id, step, 0u, m, xe, J, m == 0 ? &rq0 : nullptr)) continue;
-            const W4 rc = draw(root.id, step, kTagDeriv, 0u, (uint32_t)(8 + m), seed, key);
-            Node ch[2];
-            make_deriv_child(d, root, m, 0, J, rc, ch[0]);
-            make_deriv_child(d, root, m, 1, J, rc, ch[1]);
-            put_pair(ch);
+    if constexpr (TAN) {
+        if (d.tangent == 2 && root.sg != 0) {
+            for (int m = 0; m < d.M; ++m) {    // derivative pairs, after the jump's real pairs
+                PairDraw J;
+                if (!draw_deriv(d, P, root.id, step, 0u, m, xe, J, m == 0 ? &rq0 : nullptr)) continue;
+                const W4 rc = draw(root.id, step, kTagDeriv, 0u, (uint32_t)(8 + m), seed, key);
+                Node ch[2];
+                make_deriv_child(d, root, m, 0, J, rc, ch[0]);
+                make_deriv_child(d, root, m, 1, J, rc, ch[1]);
+                leaf_pair<DIM, SP2, TAN>(d, P, step, ch, xe, te, sh, slot, cnt, tl, fast);
+            }
         }
     }
     const double u1 = unit53(r1.a, r1.b);
     if (!surely_no_jump(u1, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u1) / P.gamma0) <= d.dt)
         fast = false;
     return fast;
+}
+
+// Pair slots of a jump in walk_family: components 0..M-1, then (tangent
+// mode 2, signed particles) their derivative pairs as slots M..2M-1.  Without
+// tangents these are exactly the pair draw and make_child.
+template <bool TAN>
+__device__ __forceinline__ int slot_end(const Dev &d, const Node &cur, int M)
+{
+    if constexpr (TAN) return (d.tangent == 2 && cur.sg != 0) ? 2 * M : M;
+    else return M;
+}
+
+template <bool SP2, bool TAN>
+__device__ __forceinline__ bool slot_draw(const Dev &d, const InstParam &P, const Node &cur, uint32_t step,
+                                          int slot, int M, PairDraw &J, W4 &rc)
+{
+    if constexpr (TAN) {
+        if (slot >= M) {
+            if (!draw_deriv(d, P, cur.id, step, cur.e, slot - M, cur.xe, J)) return false;
+            rc = draw(cur.id, step, kTagDeriv, cur.e, (uint32_t)(8 + slot - M), d.seed, P.key);
+            return true;
+        }
+    }
+    if (!draw_pair<SP2>(d, P, cur.id, step, cur.e, slot, cur.xe, cur.te, cur.ua0, cur.w, J)) return false;
+    rc = draw(cur.id, step, kTagChild, cur.e, (uint32_t)slot, d.seed, P.key);
+    return true;
+}
+
+template <bool SP2, bool TAN>
+__device__ __forceinline__ void slot_child(const Dev &d, const InstParam &P, const Node &cur, int slot, int M,
+                                           int side, const PairDraw &J, const W4 &rc, Node &ch)
+{
+    if constexpr (TAN) {
+        if (slot >= M) {
+            make_deriv_child(d, cur, slot - M, side, J, rc, ch);
+            return;
+        }
+    }
+    make_child<SP2, TAN>(d, P, cur, slot, side, J, rc, ch);
 }
 
 // General depth-first walk of one family (any number of jumps and levels).
@@ -614,27 +665,21 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
                 continue;
             }
         }
-        // pair slots of a jump: components 0..M-1, then (tangent mode 2,
-        // signed particles) their derivative pairs as slots M..2M-1
-        const int mend = (TAN && d.tangent == 2 && cur.sg != 0) ? 2 * M : M;
-        if (cur.m >= mend) {
+        if (cur.m >= slot_end<TAN>(d, cur, M)) {
             cur.t = cur.te;
             cur.e += 1u;
             cur.in_ev = 0;
             continue;
         }
-        const bool dv = TAN && cur.m >= M;
-        const int m = dv ? cur.m - M : cur.m;
+        const int m = cur.m;
         PairDraw J;
         W4 rc;
         if (cur.side == 0) {
-            if (dv ? !draw_deriv(d, P, cur.id, step, cur.e, m, cur.xe, J)
-                   : !draw_pair<SP2>(d, P, cur.id, step, cur.e, m, cur.xe, cur.te, cur.ua0, cur.w, J)) {
+            if (!slot_draw<SP2, TAN>(d, P, cur, step, m, M, J, rc)) {
                 cur.m += 1;
                 continue;
             }
-            rc = draw(cur.id, step, dv ? kTagDeriv : kTagChild, cur.e, (uint32_t)(dv ? 8 + m : m), seed, key);
-            if (!EMIT && !dv) tl.pairs++;
+            if (!EMIT && (!TAN || m < M)) tl.pairs++;
         } else {
             J = stackJ[sp];        // saved when this frame descended into its "+" offspring
             rc = stackR[sp];
@@ -642,8 +687,7 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
         bool descend = false;
         Node ch;
         for (int side = cur.side; side < 2 && !descend; ++side) {
-            if (dv) make_deriv_child(d, cur, m, side, J, rc, ch);
-            else make_child<SP2, TAN>(d, P, cur, m, side, J, rc, ch);
+            slot_child<SP2, TAN>(d, P, cur, m, M, side, J, rc, ch);
             if (!in_kbox<DIM>(d, ch.k)) {          // k-truncation (Sec. 2)
                 if (!EMIT) tl.killed += killed_amount<SP2>(ch);
                 continue;
