@@ -16,7 +16,7 @@ constexpr int kMaxM = 4;
 constexpr int kThreads = 256;           // threads per block in every kernel
 constexpr int kPPT = 8;                 // particles (or cells) per thread in streaming passes
 constexpr int kTileA = kThreads * kPPT; // particles per streaming tile
-constexpr int kTileB = kThreads;        // event-parents per family tile
+constexpr int kTileB = kThreads;        // event-parents per family tile (the smallest; see fam_tile)
 constexpr int kTileS = kThreads * kPPT; // cells per scan tile
 constexpr int kTileR = kThreads * 4;    // regenerated particles per tile
 constexpr int kMaxDepth = 16;           // deepest family tree walked within one step
@@ -25,6 +25,13 @@ constexpr int kXiN = 4096;              // xi(r) grid intervals (Alg. 4 sampler)
 constexpr int kXiQ = 8192;              // quadrature nodes for xi(r)
 constexpr uint32_t kRejectMax = 256u;   // rejection proposals per kick
 constexpr int kMaxGrid = 8192;          // blocks of a persistent launch (per-block partials)
+
+// Event parents per family tile of the particle pass.  A tile's slow family
+// walks run concurrently, so larger tiles shorten the walk-bound critical
+// path; the 1D plain and sp2 kernels have the LDS for two parents per thread,
+// the 4D and tangent ones (larger records, four stash rows) one.  Ghost passes
+// use the tangent kernel, hence kTileB.
+constexpr int fam_tile(int dim, bool tangent) { return (dim == 1 && !tangent) ? 2 * kThreads : kTileB; }
 
 enum : uint32_t { kErrCapacity = 1u, kErrDepth = 2u };
 

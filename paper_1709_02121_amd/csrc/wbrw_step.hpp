@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
         evc[b] = (int64_t)(hi - lo);
     }
     __syncthreads();
-    block_plan(d.tileB + (int64_t)ghost * (B + 1), evc, B, kTileB);
+    block_plan(d.tileB + (int64_t)ghost * (B + 1), evc, B, ghost ? kTileB : fam_tile(d.dim, d.tangent != 0));
     for (int b = tid; b < B; b += kThreads) {
         d.chc[(int64_t)ghost * B + b] = 0;
         d.stg[(int64_t)ghost * B + b] = 0;
@@ -242,13 +242,14 @@ struct Tally {
 template <int DIM, bool SP2, bool TAN>
 struct Stash {
     static constexpr int R = (TAN && !SP2) ? 4 : 2;
-    double x0[R][kTileB], k0[R][kTileB];
-    double x1[DIM == 2 ? R : 1][DIM == 2 ? kTileB : 1];
-    double k1[DIM == 2 ? R : 1][DIM == 2 ? kTileB : 1];
-    double w[SP2 ? R : 1][SP2 ? kTileB : 1];
-    double D[TAN ? 3 * R : 1][TAN ? kTileB : 1];
-    uint64_t id[R][kTileB];
-    int8_t sg[R][kTileB];
+    static constexpr int F = fam_tile(DIM, TAN);   // event parents per tile
+    double x0[R][F], k0[R][F];
+    double x1[DIM == 2 ? R : 1][DIM == 2 ? F : 1];
+    double k1[DIM == 2 ? R : 1][DIM == 2 ? F : 1];
+    double w[SP2 ? R : 1][SP2 ? F : 1];
+    double D[TAN ? 3 * R : 1][TAN ? F : 1];
+    uint64_t id[R][F];
+    int8_t sg[R][F];
 };
 
 // Records of the families that took the general walk, in order of creation
@@ -764,15 +765,19 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
 template <int DIM, bool SP2, bool TAN>
 __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
 {
+    // A tile holds FS event parents, slot = tid + h * kThreads for h < SPT.
+    constexpr int FS = Stash<DIM, SP2, TAN>::F;
+    constexpr int SPT = FS / kThreads;
     __shared__ int64_t s_t;
     __shared__ uint32_t s_wsum[4];
     __shared__ int64_t s_excl;
     __shared__ int64_t s_tal[5];
     __shared__ uint32_t s_nslow;
-    __shared__ uint16_t s_slow[kTileB];      // slots whose family needs the general walk
-    __shared__ uint32_t s_cnt[kTileB];       // their record counts
-    __shared__ int64_t s_first[kTileB];      // output offset of every slot's first record
-    __shared__ uint8_t s_pooled[kTileB];     // all records of the slot's general walk are pooled
+    __shared__ uint16_t s_slow[FS];          // slots whose family needs the general walk
+    __shared__ uint32_t s_cnt[FS];           // record count of every slot
+    __shared__ int64_t s_first[FS];          // output offset of every slot's first record
+    __shared__ uint8_t s_pooled[FS];         // all records of the slot's general walk are pooled
+    __shared__ uint8_t s_fast[FS];           // the slot's records are in the stash
     __shared__ Stash<DIM, SP2, TAN> s_stash;
     __shared__ Pool<DIM, SP2, TAN> s_pool;
 
@@ -847,25 +852,32 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t cap = ghost ? P.gcap : P.cap;
         const int64_t nev = d.evc[(int64_t)ghost * B + b];
-        const int64_t j0 = tl_i * kTileB;
-        const bool ok = j0 + tid < nev;
+        const int64_t j0 = tl_i * FS;
 
-        // 1. every family in lockstep on the common path
+        // 1. every family in lockstep on the common path; a slow family's
+        //    partial tallies are dropped (its general walk counts them)
         Tally tal{0, 0, 0, 0, 0};
-        uint32_t cnt = 0;
-        bool slow = false;
-        int64_t pi = 0;                       // the parent and its end-of-step position
-        double xend0 = 0.0, xend1 = 0.0;
-        if (ok) {
-            const Node root = load_root(base, j0, tid);
-            pi = base + (int64_t)evi[base + j0 + tid];
-            xend0 = root.x[0] + (d.vfac * root.k[0]) * d.dt;
-            xend1 = root.x[1] + (d.vfac * root.k[1]) * d.dt;
-            slow = !fast_family<DIM, SP2, TAN>(d, P, step, root, &s_stash, tid, cnt, tal);
-        }
-        if (slow) {
-            tal = Tally{0, 0, 0, 0, 0};
-            s_slow[atomicAdd(&s_nslow, 1u)] = (uint16_t)tid;
+#pragma unroll
+        for (int h = 0; h < SPT; ++h) {
+            const int slot = tid + h * kThreads;
+            uint32_t cnt = 0;
+            bool fast = false;
+            if (j0 + slot < nev) {
+                const Node root = load_root(base, j0, slot);
+                Tally th{0, 0, 0, 0, 0};
+                fast = fast_family<DIM, SP2, TAN>(d, P, step, root, &s_stash, slot, cnt, th);
+                if (fast) {
+                    tal.events += th.events;
+                    tal.pairs += th.pairs;
+                    tal.killed += th.killed;
+                    tal.cap += th.cap;
+                    tal.maxdepth = max(tal.maxdepth, th.maxdepth);
+                } else {
+                    s_slow[atomicAdd(&s_nslow, 1u)] = (uint16_t)slot;
+                }
+            }
+            s_cnt[slot] = fast ? cnt : 0u;
+            s_fast[slot] = fast ? 1 : 0;
         }
         __syncthreads();
         // 2. the rest walked in full, spread over the block's threads with
@@ -881,21 +893,30 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             s_pooled[slot] = pooled ? 1 : 0;
         }
         __syncthreads();
-        if (slow) cnt = s_cnt[tid];
 
-        // 3. ordered exclusive scan of the record counts over the tile
-        uint32_t incl = cnt;
+        // 3. ordered exclusive scan of the record counts over the tile, in
+        //    slot order (h, then tid)
+        uint32_t excl[SPT];
+        uint32_t agg = 0;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t v = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += v;
-        }
-        if (lane == 63) s_wsum[wv] = incl;
-        __syncthreads();
-        uint32_t woff = 0, agg = 0;
-        for (int q = 0; q < 4; ++q) {
-            if (q < wv) woff += s_wsum[q];
-            agg += s_wsum[q];
+        for (int h = 0; h < SPT; ++h) {
+            const uint32_t c = s_cnt[tid + h * kThreads];
+            uint32_t incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            if (lane == 63) s_wsum[wv] = incl;
+            __syncthreads();
+            uint32_t woff = 0, part = 0;
+            for (int q = 0; q < 4; ++q) {
+                if (q < wv) woff += s_wsum[q];
+                part += s_wsum[q];
+            }
+            excl[h] = agg + woff + incl - c;
+            agg += part;
+            __syncthreads();
         }
         if (tid == 0) {
             // the tile's records take a contiguous stretch of the staging
@@ -907,28 +928,33 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             tstg[t] = sb;
         }
         __syncthreads();
-        const int64_t my_first = s_excl + (int64_t)(woff + incl - cnt);
-        s_first[tid] = my_first;
+#pragma unroll
+        for (int h = 0; h < SPT; ++h) s_first[tid + h * kThreads] = s_excl + (int64_t)excl[h];
 
         // 4. records into the staging area: from the stash and the pool, or
         //    by a second full walk for a family that overflowed the pool
-        if (ok && !slow) {
+#pragma unroll
+        for (int h = 0; h < SPT; ++h) {
+            const int slot = tid + h * kThreads;
+            if (!s_fast[slot]) continue;
+            const uint32_t cnt = s_cnt[slot];
+            const int64_t my_first = s_excl + (int64_t)excl[h];
             for (uint32_t r = 0; r < cnt; ++r) {
                 const int64_t li = my_first + r;
                 if (li >= cap) { err |= kErrCapacity; continue; }
                 const int64_t o = base + li;
-                S.x0[o] = s_stash.x0[r][tid];
-                S.k0[o] = s_stash.k0[r][tid];
+                S.x0[o] = s_stash.x0[r][slot];
+                S.k0[o] = s_stash.k0[r][slot];
                 if (DIM == 2) {
-                    S.x1[o] = s_stash.x1[r][tid];
-                    S.k1[o] = s_stash.k1[r][tid];
+                    S.x1[o] = s_stash.x1[r][slot];
+                    S.k1[o] = s_stash.k1[r][slot];
                 }
-                if (SP2) S.w[o] = s_stash.w[r][tid]; else S.sg[o] = s_stash.sg[r][tid];
-                S.id[o] = s_stash.id[r][tid];
+                if (SP2) S.w[o] = s_stash.w[r][slot]; else S.sg[o] = s_stash.sg[r][slot];
+                S.id[o] = s_stash.id[r][slot];
                 if (TAN) {
-                    S.D[o] = s_stash.D[3 * r][tid];
-                    S.D[dstride + o] = s_stash.D[3 * r + 1][tid];
-                    S.D[2 * dstride + o] = s_stash.D[3 * r + 2][tid];
+                    S.D[o] = s_stash.D[3 * r][slot];
+                    S.D[dstride + o] = s_stash.D[3 * r + 1][slot];
+                    S.D[2 * dstride + o] = s_stash.D[3 * r + 2][slot];
                 }
             }
         }
@@ -981,9 +1007,14 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
         __syncthreads();
         // every walk of this tile is done: the parents move to the end of the
         // step (k_stream left them at their start positions)
-        if (ok) {
-            E.x0[pi] = xend0;
-            if (DIM == 2) E.x1[pi] = xend1;
+#pragma unroll
+        for (int h = 0; h < SPT; ++h) {
+            const int slot = tid + h * kThreads;
+            if (j0 + slot < nev) {
+                const int64_t pi = base + (int64_t)evi[base + j0 + slot];
+                E.x0[pi] = E.x0[pi] + (d.vfac * E.k0[pi]) * d.dt;
+                if (DIM == 2) E.x1[pi] = E.x1[pi] + (d.vfac * E.k1[pi]) * d.dt;
+            }
         }
     }
     if (tid == 0) {
