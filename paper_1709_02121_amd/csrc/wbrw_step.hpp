@@ -252,21 +252,38 @@ struct Stash {
     int8_t sg[R][F];
 };
 
-// Records of the families that took the general walk, in order of creation
-// across the tile, each tagged with its family's slot and its rank within
-// the family.  A family whose records do not all fit is walked again when
-// the records are written.
-constexpr int kPool = 256;
+// The families of a tile that are not of the lockstep kind, expanded level
+// by level: every node (a family root, or a kept offspring, which is a
+// record) of one level is expanded by one lane, which walks its jumps in time
+// order and appends its kept offspring with their parent, rank among the
+// parent's offspring and depth; offspring that jump again within the step
+// form the next level.  Subtree sizes and depth-first positions then give
+// every record its place in the canonical order.  The tallies are kept per
+// node, so that a family whose nodes do not all fit can be dropped and
+// walked again depth first.
+constexpr int kNodes = 256;
 template <int DIM, bool SP2, bool TAN>
-struct Pool {
-    double x0[kPool], k0[kPool];
-    double x1[DIM == 2 ? kPool : 1], k1[DIM == 2 ? kPool : 1];
-    double w[SP2 ? kPool : 1];
-    double D[TAN ? 3 : 1][TAN ? kPool : 1];
-    uint64_t id[kPool];
-    uint16_t slot[kPool], rank[kPool];
-    int8_t sg[kPool];
-    uint32_t n;
+struct Tree {
+    double x0[kNodes], k0[kNodes];   // position at birth (t0), wave vector
+    double x1[DIM == 2 ? kNodes : 1], k1[DIM == 2 ? kNodes : 1];
+    double t0[kNodes];
+    double w[SP2 ? kNodes : 1];
+    double D[TAN ? 3 : 1][TAN ? kNodes : 1];
+    uint64_t id[kNodes];
+    int64_t killed[kNodes];          // k-truncation tally of the node's jumps
+    uint32_t size[kNodes];           // records in the subtree (a root: its family's)
+    uint16_t par[kNodes];            // parent node (roots: none)
+    uint16_t rank[kNodes];           // among the parent's kept offspring
+    uint16_t slot[kNodes];           // tile slot of the family
+    uint16_t nch[kNodes];            // kept offspring
+    uint16_t cst[kNodes];            // first of its offspring in `child`
+    uint16_t child[kNodes];          // offspring grouped by parent, in rank order
+    uint16_t front[2][kNodes];       // the levels being expanded / collected
+    uint16_t events[kNodes], pairs[kNodes];
+    int16_t pos[kNodes];             // depth-first position within the family
+    int8_t sg[kNodes];
+    uint8_t depth[kNodes], capped[kNodes];
+    uint32_t n, nf[2], maxd;
 };
 
 // Pair decision and kick of component m at jump e of particle `id`
@@ -464,30 +481,6 @@ __device__ __forceinline__ void stash_record(const Dev &d, Stash<DIM, SP2, TAN> 
     }
 }
 
-template <int DIM, bool SP2, bool TAN>
-__device__ __forceinline__ bool pool_record(const Dev &d, Pool<DIM, SP2, TAN> *pl, int rank, int slot,
-                                            const double *xe, double te, const Node &ch)
-{
-    const uint32_t r = atomicAdd(&pl->n, 1u);
-    if (r >= (uint32_t)kPool) return false;
-    pl->x0[r] = xe[0] + (d.vfac * ch.k[0]) * (d.dt - te);
-    pl->k0[r] = ch.k[0];
-    if (DIM == 2) {
-        pl->x1[r] = xe[1] + (d.vfac * ch.k[1]) * (d.dt - te);
-        pl->k1[r] = ch.k[1];
-    }
-    if (SP2) pl->w[r] = ch.w; else pl->sg[r] = (int8_t)ch.sg;
-    pl->id[r] = ch.id;
-    if (TAN) {
-        pl->D[0][r] = ch.D[0];
-        pl->D[1][r] = ch.D[1];
-        pl->D[2][r] = ch.D[2];
-    }
-    pl->slot[r] = (uint16_t)slot;
-    pl->rank[r] = (uint16_t)rank;
-    return true;
-}
-
 // A pair created at time te at xe, as fast_family keeps it: both children
 // into the stash (clearing `fast` if it is full) unless the k-box removes
 // them, and `fast` cleared if either child jumps again within the step.
@@ -614,15 +607,14 @@ __device__ __forceinline__ void slot_child(const Dev &d, const InstParam &P, con
     make_child<SP2, TAN>(d, P, cur, slot, side, J, rc, ch);
 }
 
-// General depth-first walk of one family (any number of jumps and levels).
-// Counting mode (EMIT false) tallies and puts the records into the tile's
-// pool (clearing `pooled` if one did not fit); emitting mode writes every
+// General depth-first walk of one family (any number of jumps and levels),
+// for the families whose nodes do not fit the tile's Tree.  Counting mode
+// (EMIT false) tallies and counts the records; emitting mode writes every
 // record from first_rec on.
 template <int DIM, bool SP2, bool TAN, bool EMIT>
 __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step, Node cur,
                                 const Ens &out, int64_t base, int64_t first_rec, int64_t cap,
-                                int64_t dstride, Tally &tl, uint32_t &err,
-                                Pool<DIM, SP2, TAN> *pl, int slot, bool &pooled)
+                                int64_t dstride, Tally &tl, uint32_t &err)
 {
     Node stack[kMaxDepth];
     PairDraw stackJ[kMaxDepth];
@@ -713,8 +705,6 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
                 } else {
                     err |= kErrCapacity;
                 }
-            } else if (pooled) {
-                pooled = pool_record<DIM, SP2, TAN>(d, pl, (int)nrec, slot, cur.xe, cur.te, ch);
             }
             nrec++;
             ch.depth = cur.depth + 1;
@@ -762,6 +752,116 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
     return nrec;
 }
 
+// Expands node n of the tile's Tree (see Tree): walks its jumps from its
+// birth time to the end of the step and appends every kept offspring, and
+// the offspring that jump again to the next level.  The draws and the
+// arithmetic are walk_family's, so the records are the same.  A family
+// whose nodes overflow the Tree is marked in `in_tree` and left to
+// walk_family.
+template <int DIM, bool SP2, bool TAN>
+__device__ void expand_node(const Dev &d, const InstParam &P, uint32_t step, Tree<DIM, SP2, TAN> *tr, int n,
+                            int next, uint8_t *in_tree)
+{
+    const uint32_t seed = d.seed, key = P.key;
+    const int M = d.M;
+    const int fam = tr->slot[n];
+    Node cur;
+    cur.x[0] = tr->x0[n];
+    cur.k[0] = tr->k0[n];
+    cur.x[1] = DIM == 2 ? tr->x1[n] : 0.0;
+    cur.k[1] = DIM == 2 ? tr->k1[n] : 0.0;
+    cur.t0 = tr->t0[n];
+    cur.w = SP2 ? tr->w[n] : 0.0;
+    if (TAN) {
+        cur.D[0] = tr->D[0][n];
+        cur.D[1] = tr->D[1][n];
+        cur.D[2] = tr->D[2][n];
+    } else {
+        cur.D[0] = cur.D[1] = cur.D[2] = 0.0;
+    }
+    cur.id = tr->id[n];
+    cur.sg = SP2 ? 0 : (int32_t)tr->sg[n];
+    cur.depth = tr->depth[n];
+    uint32_t nkept = 0, nev = 0, npairs = 0;
+    int64_t killed = 0;
+    uint8_t capped = 0;
+    double t = cur.t0;
+    for (uint32_t e = 0;; ++e) {
+        if (e >= kEventCap) {
+            capped = 1;
+            break;
+        }
+        const W4 r = draw(cur.id, step, kTagStep, e, 0u, seed, key);
+        const double u = unit53(r.a, r.b);
+        const double te = surely_no_jump(u, t, d.dt, P.gamma0) ? d.dt + 1.0 : t + (-ln_series(1.0 - u) / P.gamma0);
+        if (!(te <= d.dt)) break;
+        nev++;
+        cur.e = e;
+        cur.te = te;
+        cur.ua0 = unit53(r.c, r.d);
+        cur.xe[0] = cur.x[0] + (d.vfac * cur.k[0]) * (te - cur.t0);
+        cur.xe[1] = DIM == 2 ? cur.x[1] + (d.vfac * cur.k[1]) * (te - cur.t0) : 0.0;
+        const int mend = slot_end<TAN>(d, cur, M);
+        for (int m = 0; m < mend; ++m) {
+            PairDraw J;
+            W4 rc;
+            if (!slot_draw<SP2, TAN>(d, P, cur, step, m, M, J, rc)) continue;
+            if (!TAN || m < M) npairs++;
+            for (int side = 0; side < 2; ++side) {
+                Node ch;
+                slot_child<SP2, TAN>(d, P, cur, m, M, side, J, rc, ch);
+                if (!in_kbox<DIM>(d, ch.k)) {          // k-truncation (Sec. 2)
+                    killed += killed_amount<SP2>(ch);
+                    continue;
+                }
+                const uint32_t c = atomicAdd(&tr->n, 1u);
+                if (c >= (uint32_t)kNodes) {
+                    in_tree[fam] = 0;
+                    continue;
+                }
+                tr->x0[c] = cur.xe[0];
+                tr->k0[c] = ch.k[0];
+                if (DIM == 2) {
+                    tr->x1[c] = cur.xe[1];
+                    tr->k1[c] = ch.k[1];
+                }
+                tr->t0[c] = te;
+                if (SP2) tr->w[c] = ch.w; else tr->sg[c] = (int8_t)ch.sg;
+                if (TAN) {
+                    tr->D[0][c] = ch.D[0];
+                    tr->D[1][c] = ch.D[1];
+                    tr->D[2][c] = ch.D[2];
+                }
+                tr->id[c] = ch.id;
+                tr->par[c] = (uint16_t)n;
+                tr->rank[c] = (uint16_t)nkept;
+                tr->slot[c] = (uint16_t)fam;
+                tr->depth[c] = (uint8_t)(cur.depth + 1);
+                atomicMax(&tr->maxd, (uint32_t)(cur.depth + 1));
+                tr->nch[c] = 0;
+                tr->size[c] = 0;
+                tr->events[c] = 0;
+                tr->pairs[c] = 0;
+                tr->killed[c] = 0;
+                tr->capped[c] = 0;
+                nkept++;
+                // the offspring's first clock draw, as its own walk takes it
+                const W4 r0 = draw(ch.id, step, kTagStep, 0u, 0u, seed, key);
+                const double u0 = unit53(r0.a, r0.b);
+                if (!surely_no_jump(u0, te, d.dt, P.gamma0) && te + (-ln_series(1.0 - u0) / P.gamma0) <= d.dt) {
+                    tr->front[next][atomicAdd(&tr->nf[next], 1u)] = (uint16_t)c;
+                }
+            }
+        }
+        t = te;
+    }
+    tr->nch[n] = (uint16_t)nkept;
+    tr->events[n] = (uint16_t)nev;
+    tr->pairs[n] = (uint16_t)npairs;
+    tr->killed[n] = killed;
+    tr->capped[n] = capped;
+}
+
 template <int DIM, bool SP2, bool TAN>
 __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
 {
@@ -776,10 +876,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     __shared__ uint16_t s_slow[FS];          // slots whose family needs the general walk
     __shared__ uint32_t s_cnt[FS];           // record count of every slot
     __shared__ int64_t s_first[FS];          // output offset of every slot's first record
-    __shared__ uint8_t s_pooled[FS];         // all records of the slot's general walk are pooled
+    __shared__ uint8_t s_tree[FS];           // the slot's family is expanded in the Tree
     __shared__ uint8_t s_fast[FS];           // the slot's records are in the stash
     __shared__ Stash<DIM, SP2, TAN> s_stash;
-    __shared__ Pool<DIM, SP2, TAN> s_pool;
+    __shared__ Tree<DIM, SP2, TAN> tree;
 
     Ctl *ctl = d.ctl;
     const uint32_t step = ctl->step;
@@ -830,7 +930,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     int cb = -1;
     if (tid < 5) s_tal[tid] = 0;
     for (;;) {
-        if (tid == 0) { s_t = next_tile(&ctl->ticket[pass], ntiles); s_nslow = 0; s_pool.n = 0; }
+        if (tid == 0) { s_t = next_tile(&ctl->ticket[pass], ntiles); s_nslow = 0; }
         __syncthreads();
         const int64_t t = s_t;
         if (t >= ntiles) break;
@@ -880,17 +980,123 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             s_fast[slot] = fast ? 1 : 0;
         }
         __syncthreads();
-        // 2. the rest walked in full, spread over the block's threads with
-        //    consecutive families in different wavefronts
+        // 2. the other families, level by level in the Tree (root k of the
+        //    slow list is node k), spread over the block's threads with
+        //    consecutive nodes in different wavefronts
         const int nslow = (int)s_nslow;
         const int kme = lane * 4 + wv;
+        for (int k = tid; k < nslow; k += kThreads) {
+            const int slot = s_slow[k];
+            s_tree[slot] = k < kNodes ? 1 : 0;
+            if (k >= kNodes) continue;
+            const Node root = load_root(base, j0, slot);
+            tree.x0[k] = root.x[0];
+            tree.k0[k] = root.k[0];
+            if (DIM == 2) {
+                tree.x1[k] = root.x[1];
+                tree.k1[k] = root.k[1];
+            }
+            tree.t0[k] = 0.0;
+            if (SP2) tree.w[k] = root.w; else tree.sg[k] = (int8_t)root.sg;
+            if (TAN) {
+                tree.D[0][k] = root.D[0];
+                tree.D[1][k] = root.D[1];
+                tree.D[2][k] = root.D[2];
+            }
+            tree.id[k] = root.id;
+            tree.slot[k] = (uint16_t)slot;
+            tree.depth[k] = 0;
+            tree.size[k] = 0;
+            tree.nch[k] = 0;
+            tree.events[k] = 0;
+            tree.pairs[k] = 0;
+            tree.killed[k] = 0;
+            tree.capped[k] = 0;
+            tree.front[0][k] = (uint16_t)k;
+        }
+        if (tid == 0) {
+            const uint32_t nr = (uint32_t)min(nslow, kNodes);
+            tree.n = nr;
+            tree.nf[0] = nr;
+            tree.nf[1] = 0;
+            tree.maxd = 0;
+        }
+        __syncthreads();
+        for (int lv = 0;; lv ^= 1) {
+            const uint32_t nf = tree.nf[lv];
+            if (nf == 0) break;
+            for (uint32_t k = kme; k < nf; k += kThreads) {
+                const int n = tree.front[lv][k];
+                if (s_tree[tree.slot[n]]) expand_node<DIM, SP2, TAN>(d, P, step, &tree, n, lv ^ 1, s_tree);
+            }
+            __syncthreads();
+            if (tid == 0) tree.nf[lv] = 0;
+            __syncthreads();
+        }
+        const int nn = (int)min(tree.n, (uint32_t)kNodes);
+        const int maxd = (int)tree.maxd;
+        // subtree sizes, deepest level first (a root gets its family's count)
+        for (int dd = maxd; dd >= 1; --dd) {
+            for (int k = tid; k < nn; k += kThreads)
+                if (tree.depth[k] == dd) {
+                    const uint32_t sz = tree.size[k] + 1u;
+                    tree.size[k] = sz;
+                    atomicAdd(&tree.size[tree.par[k]], sz);
+                }
+            __syncthreads();
+        }
+        // offspring grouped by parent (exclusive scan of the offspring counts
+        // in node order), then depth-first positions, top level first
+        {
+            const uint32_t c = tid < nn ? (uint32_t)tree.nch[tid] : 0u;
+            uint32_t incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            if (lane == 63) s_wsum[wv] = incl;
+            __syncthreads();
+            uint32_t woff = 0;
+            for (int q = 0; q < wv; ++q) woff += s_wsum[q];
+            if (tid < nn) tree.cst[tid] = (uint16_t)(woff + incl - c);
+            if (tid < nn && tree.depth[tid] == 0) tree.pos[tid] = -1;
+            __syncthreads();
+        }
+        for (int k = tid; k < nn; k += kThreads)
+            if (tree.depth[k] > 0) tree.child[tree.cst[tree.par[k]] + tree.rank[k]] = (uint16_t)k;
+        __syncthreads();
+        for (int dd = 0; dd < maxd; ++dd) {
+            for (int k = tid; k < nn; k += kThreads)
+                if (tree.depth[k] == dd) {
+                    int run = tree.pos[k] + 1;
+                    const int c0 = tree.cst[k], nc = tree.nch[k];
+                    for (int j = 0; j < nc; ++j) {
+                        const int c = tree.child[c0 + j];
+                        tree.pos[c] = (int16_t)run;
+                        run += (int)tree.size[c];
+                    }
+                }
+            __syncthreads();
+        }
+        // record counts, tallies (from the Tree, or by a counting walk for the
+        // families that did not fit)
+        for (int k = tid; k < nn; k += kThreads) {
+            if (!s_tree[tree.slot[k]]) continue;
+            tal.events += tree.events[k];
+            tal.pairs += tree.pairs[k];
+            tal.killed += tree.killed[k];
+            tal.cap += tree.capped[k];
+            tal.maxdepth = max(tal.maxdepth, (int32_t)tree.depth[k]);
+        }
         for (int k = kme; k < nslow; k += kThreads) {
             const int slot = s_slow[k];
+            if (s_tree[slot]) {
+                s_cnt[slot] = tree.size[k];
+                continue;
+            }
             const Node root = load_root(base, j0, slot);
-            bool pooled = true;
-            s_cnt[slot] = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal,
-                                                            err, &s_pool, slot, pooled);
-            s_pooled[slot] = pooled ? 1 : 0;
+            s_cnt[slot] = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal, err);
         }
         __syncthreads();
 
@@ -931,8 +1137,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
 #pragma unroll
         for (int h = 0; h < SPT; ++h) s_first[tid + h * kThreads] = s_excl + (int64_t)excl[h];
 
-        // 4. records into the staging area: from the stash and the pool, or
-        //    by a second full walk for a family that overflowed the pool
+        // 4. records into the staging area: from the stash and the Tree, or
+        //    by a second full walk for a family that did not fit the Tree
 #pragma unroll
         for (int h = 0; h < SPT; ++h) {
             const int slot = tid + h * kThreads;
@@ -959,35 +1165,32 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             }
         }
         __syncthreads();
-        const int npool = (int)min(s_pool.n, (uint32_t)kPool);
-        for (int r = tid; r < npool; r += kThreads) {
-            const int slot = s_pool.slot[r];
-            if (!s_pooled[slot]) continue;
-            const int64_t li = s_first[slot] + s_pool.rank[r];
+        for (int k = tid; k < nn; k += kThreads) {
+            if (tree.depth[k] == 0 || !s_tree[tree.slot[k]]) continue;
+            const int64_t li = s_first[tree.slot[k]] + tree.pos[k];
             if (li >= cap) { err |= kErrCapacity; continue; }
             const int64_t o = base + li;
-            S.x0[o] = s_pool.x0[r];
-            S.k0[o] = s_pool.k0[r];
+            const double t0 = tree.t0[k];
+            S.x0[o] = tree.x0[k] + (d.vfac * tree.k0[k]) * (d.dt - t0);
+            S.k0[o] = tree.k0[k];
             if (DIM == 2) {
-                S.x1[o] = s_pool.x1[r];
-                S.k1[o] = s_pool.k1[r];
+                S.x1[o] = tree.x1[k] + (d.vfac * tree.k1[k]) * (d.dt - t0);
+                S.k1[o] = tree.k1[k];
             }
-            if (SP2) S.w[o] = s_pool.w[r]; else S.sg[o] = s_pool.sg[r];
-            S.id[o] = s_pool.id[r];
+            if (SP2) S.w[o] = tree.w[k]; else S.sg[o] = tree.sg[k];
+            S.id[o] = tree.id[k];
             if (TAN) {
-                S.D[o] = s_pool.D[0][r];
-                S.D[dstride + o] = s_pool.D[1][r];
-                S.D[2 * dstride + o] = s_pool.D[2][r];
+                S.D[o] = tree.D[0][k];
+                S.D[dstride + o] = tree.D[1][k];
+                S.D[2 * dstride + o] = tree.D[2][k];
             }
         }
         for (int k = kme; k < nslow; k += kThreads) {
             const int slot = s_slow[k];
-            if (s_pooled[slot]) continue;
+            if (s_tree[slot]) continue;
             const Node root = load_root(base, j0, slot);
             Tally none{0, 0, 0, 0, 0};
-            bool unused = false;
-            walk_family<DIM, SP2, TAN, true>(d, P, step, root, S, base, s_first[slot], cap, dstride, none, err,
-                                             &s_pool, slot, unused);
+            walk_family<DIM, SP2, TAN, true>(d, P, step, root, S, base, s_first[slot], cap, dstride, none, err);
         }
 
         // per-instance tallies, summed over the wavefront first
