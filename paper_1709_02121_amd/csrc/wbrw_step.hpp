@@ -18,6 +18,8 @@
 // k_close_records scans the tiles' record counts and k_place_records copies
 // the records to their ordered place after the instance's particles.
 #pragma once
+#include <type_traits>
+
 #include "wbrw_dev.hpp"
 #include "wbrw_math.hpp"
 #include "wbrw_stream.hpp"
@@ -261,9 +263,9 @@ struct Stash {
 // every record its place in the canonical order.  The tallies are kept per
 // node, so that a family whose nodes do not all fit can be dropped and
 // walked again depth first.
-constexpr int kNodes = 256;
 template <int DIM, bool SP2, bool TAN>
 struct Tree {
+    static constexpr int kNodes = 256;
     double x0[kNodes], k0[kNodes];   // position at birth (t0), wave vector
     double x1[DIM == 2 ? kNodes : 1], k1[DIM == 2 ? kNodes : 1];
     double t0[kNodes];
@@ -284,6 +286,25 @@ struct Tree {
     int8_t sg[kNodes];
     uint8_t depth[kNodes], capped[kNodes];
     uint32_t n, nf[2], maxd;
+};
+
+// 4D and tangent kernels: the records of the families that took the general
+// walk, in order of creation across the tile, each tagged with its family's
+// slot and its rank within the family.  A family whose records do not all
+// fit is walked again when the records are written.  (In 4D about half the
+// families of a tile are not of the lockstep kind, too many for a Tree in an
+// LDS budget that keeps three blocks per CU.)
+constexpr int kPool = 256;
+template <int DIM, bool SP2, bool TAN>
+struct Pool {
+    double x0[kPool], k0[kPool];
+    double x1[DIM == 2 ? kPool : 1], k1[DIM == 2 ? kPool : 1];
+    double w[SP2 ? kPool : 1];
+    double D[TAN ? 3 : 1][TAN ? kPool : 1];
+    uint64_t id[kPool];
+    uint16_t slot[kPool], rank[kPool];
+    int8_t sg[kPool];
+    uint32_t n;
 };
 
 // Pair decision and kick of component m at jump e of particle `id`
@@ -481,6 +502,30 @@ __device__ __forceinline__ void stash_record(const Dev &d, Stash<DIM, SP2, TAN> 
     }
 }
 
+template <int DIM, bool SP2, bool TAN>
+__device__ __forceinline__ bool pool_record(const Dev &d, Pool<DIM, SP2, TAN> *pl, int rank, int slot,
+                                            const double *xe, double te, const Node &ch)
+{
+    const uint32_t r = atomicAdd(&pl->n, 1u);
+    if (r >= (uint32_t)kPool) return false;
+    pl->x0[r] = xe[0] + (d.vfac * ch.k[0]) * (d.dt - te);
+    pl->k0[r] = ch.k[0];
+    if (DIM == 2) {
+        pl->x1[r] = xe[1] + (d.vfac * ch.k[1]) * (d.dt - te);
+        pl->k1[r] = ch.k[1];
+    }
+    if (SP2) pl->w[r] = ch.w; else pl->sg[r] = (int8_t)ch.sg;
+    pl->id[r] = ch.id;
+    if (TAN) {
+        pl->D[0][r] = ch.D[0];
+        pl->D[1][r] = ch.D[1];
+        pl->D[2][r] = ch.D[2];
+    }
+    pl->slot[r] = (uint16_t)slot;
+    pl->rank[r] = (uint16_t)rank;
+    return true;
+}
+
 // A pair created at time te at xe, as fast_family keeps it: both children
 // into the stash (clearing `fast` if it is full) unless the k-box removes
 // them, and `fast` cleared if either child jumps again within the step.
@@ -607,14 +652,17 @@ __device__ __forceinline__ void slot_child(const Dev &d, const InstParam &P, con
     make_child<SP2, TAN>(d, P, cur, slot, side, J, rc, ch);
 }
 
-// General depth-first walk of one family (any number of jumps and levels),
-// for the families whose nodes do not fit the tile's Tree.  Counting mode
-// (EMIT false) tallies and counts the records; emitting mode writes every
+// General depth-first walk of one family (any number of jumps and levels):
+// in the 4D and tangent kernels for every family that is not of the lockstep
+// kind, in the others for those whose nodes do not fit the tile's Tree.  Counting mode (EMIT false)
+// tallies, counts the records and puts them into the tile's pool if one is
+// given (clearing `pooled` if one did not fit); emitting mode writes every
 // record from first_rec on.
 template <int DIM, bool SP2, bool TAN, bool EMIT>
 __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step, Node cur,
                                 const Ens &out, int64_t base, int64_t first_rec, int64_t cap,
-                                int64_t dstride, Tally &tl, uint32_t &err)
+                                int64_t dstride, Tally &tl, uint32_t &err,
+                                Pool<DIM, SP2, TAN> *pl, int slot, bool &pooled)
 {
     Node stack[kMaxDepth];
     PairDraw stackJ[kMaxDepth];
@@ -705,6 +753,8 @@ __device__ uint32_t walk_family(const Dev &d, const InstParam &P, uint32_t step,
                 } else {
                     err |= kErrCapacity;
                 }
+            } else if (pooled) {
+                pooled = pool_record<DIM, SP2, TAN>(d, pl, (int)nrec, slot, cur.xe, cur.te, ch);
             }
             nrec++;
             ch.depth = cur.depth + 1;
@@ -815,7 +865,7 @@ __device__ void expand_node(const Dev &d, const InstParam &P, uint32_t step, Tre
                     continue;
                 }
                 const uint32_t c = atomicAdd(&tr->n, 1u);
-                if (c >= (uint32_t)kNodes) {
+                if (c >= (uint32_t)Tree<DIM, SP2, TAN>::kNodes) {
                     in_tree[fam] = 0;
                     continue;
                 }
@@ -868,6 +918,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     // A tile holds FS event parents, slot = tid + h * kThreads for h < SPT.
     constexpr int FS = Stash<DIM, SP2, TAN>::F;
     constexpr int SPT = FS / kThreads;
+    constexpr int NN = Tree<DIM, SP2, TAN>::kNodes;
+    // level-by-level expansion for the 1D plain and sp2 kernels; the 4D and
+    // tangent ones (more or larger slow families per tile, more LDS per
+    // record) keep the pool and one depth-first walk per lane
+    constexpr bool kTree = DIM == 1 && !TAN;
     __shared__ int64_t s_t;
     __shared__ uint32_t s_wsum[4];
     __shared__ int64_t s_excl;
@@ -876,10 +931,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     __shared__ uint16_t s_slow[FS];          // slots whose family needs the general walk
     __shared__ uint32_t s_cnt[FS];           // record count of every slot
     __shared__ int64_t s_first[FS];          // output offset of every slot's first record
-    __shared__ uint8_t s_tree[FS];           // the slot's family is expanded in the Tree
+    __shared__ uint8_t s_tree[FS];           // the slot's family is in the Tree (or the pool)
     __shared__ uint8_t s_fast[FS];           // the slot's records are in the stash
     __shared__ Stash<DIM, SP2, TAN> s_stash;
-    __shared__ Tree<DIM, SP2, TAN> tree;
+    __shared__ typename std::conditional<kTree, Tree<DIM, SP2, TAN>, Pool<DIM, SP2, TAN>>::type s_walk;
 
     Ctl *ctl = d.ctl;
     const uint32_t step = ctl->step;
@@ -930,7 +985,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     int cb = -1;
     if (tid < 5) s_tal[tid] = 0;
     for (;;) {
-        if (tid == 0) { s_t = next_tile(&ctl->ticket[pass], ntiles); s_nslow = 0; }
+        if (tid == 0) {
+            s_t = next_tile(&ctl->ticket[pass], ntiles);
+            s_nslow = 0;
+            if constexpr (!kTree) s_walk.n = 0;
+        }
         __syncthreads();
         const int64_t t = s_t;
         if (t >= ntiles) break;
@@ -980,125 +1039,158 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             s_fast[slot] = fast ? 1 : 0;
         }
         __syncthreads();
-        // 2. the other families, level by level in the Tree (root k of the
-        //    slow list is node k), spread over the block's threads with
-        //    consecutive nodes in different wavefronts
+        // 2. the other families: level by level in the Tree, or walked depth
+        //    first, one family per lane, with their records pooled
         const int nslow = (int)s_nslow;
         const int kme = lane * 4 + wv;
-        for (int k = tid; k < nslow; k += kThreads) {
-            const int slot = s_slow[k];
-            s_tree[slot] = k < kNodes ? 1 : 0;
-            if (k >= kNodes) continue;
-            const Node root = load_root(base, j0, slot);
-            tree.x0[k] = root.x[0];
-            tree.k0[k] = root.k[0];
-            if (DIM == 2) {
-                tree.x1[k] = root.x[1];
-                tree.k1[k] = root.k[1];
-            }
-            tree.t0[k] = 0.0;
-            if (SP2) tree.w[k] = root.w; else tree.sg[k] = (int8_t)root.sg;
-            if (TAN) {
-                tree.D[0][k] = root.D[0];
-                tree.D[1][k] = root.D[1];
-                tree.D[2][k] = root.D[2];
-            }
-            tree.id[k] = root.id;
-            tree.slot[k] = (uint16_t)slot;
-            tree.depth[k] = 0;
-            tree.size[k] = 0;
-            tree.nch[k] = 0;
-            tree.events[k] = 0;
-            tree.pairs[k] = 0;
-            tree.killed[k] = 0;
-            tree.capped[k] = 0;
-            tree.front[0][k] = (uint16_t)k;
-        }
-        if (tid == 0) {
-            const uint32_t nr = (uint32_t)min(nslow, kNodes);
-            tree.n = nr;
-            tree.nf[0] = nr;
-            tree.nf[1] = 0;
-            tree.maxd = 0;
-        }
-        __syncthreads();
-        for (int lv = 0;; lv ^= 1) {
-            const uint32_t nf = tree.nf[lv];
-            if (nf == 0) break;
-            for (uint32_t k = kme; k < nf; k += kThreads) {
-                const int n = tree.front[lv][k];
-                if (s_tree[tree.slot[n]]) expand_node<DIM, SP2, TAN>(d, P, step, &tree, n, lv ^ 1, s_tree);
-            }
-            __syncthreads();
-            if (tid == 0) tree.nf[lv] = 0;
-            __syncthreads();
-        }
-        const int nn = (int)min(tree.n, (uint32_t)kNodes);
-        const int maxd = (int)tree.maxd;
-        // subtree sizes, deepest level first (a root gets its family's count)
-        for (int dd = maxd; dd >= 1; --dd) {
-            for (int k = tid; k < nn; k += kThreads)
-                if (tree.depth[k] == dd) {
-                    const uint32_t sz = tree.size[k] + 1u;
-                    tree.size[k] = sz;
-                    atomicAdd(&tree.size[tree.par[k]], sz);
+        int nn = 0;                          // Tree nodes
+        if constexpr (kTree) {
+            auto &tree = s_walk;
+            // root k of the slow list is node k; nodes are spread over the
+            // block's threads with consecutive ones in different wavefronts
+            for (int k = tid; k < nslow; k += kThreads) {
+                const int slot = s_slow[k];
+                s_tree[slot] = k < NN ? 1 : 0;
+                if (k >= NN) continue;
+                const Node root = load_root(base, j0, slot);
+                tree.x0[k] = root.x[0];
+                tree.k0[k] = root.k[0];
+                if (DIM == 2) {
+                    tree.x1[k] = root.x[1];
+                    tree.k1[k] = root.k[1];
                 }
-            __syncthreads();
-        }
-        // offspring grouped by parent (exclusive scan of the offspring counts
-        // in node order), then depth-first positions, top level first
-        {
-            const uint32_t c = tid < nn ? (uint32_t)tree.nch[tid] : 0u;
-            uint32_t incl = c;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t v = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += v;
+                tree.t0[k] = 0.0;
+                if (SP2) tree.w[k] = root.w; else tree.sg[k] = (int8_t)root.sg;
+                if (TAN) {
+                    tree.D[0][k] = root.D[0];
+                    tree.D[1][k] = root.D[1];
+                    tree.D[2][k] = root.D[2];
+                }
+                tree.id[k] = root.id;
+                tree.slot[k] = (uint16_t)slot;
+                tree.depth[k] = 0;
+                tree.size[k] = 0;
+                tree.nch[k] = 0;
+                tree.events[k] = 0;
+                tree.pairs[k] = 0;
+                tree.killed[k] = 0;
+                tree.capped[k] = 0;
+                tree.front[0][k] = (uint16_t)k;
             }
-            if (lane == 63) s_wsum[wv] = incl;
+            if (tid == 0) {
+                const uint32_t nr = (uint32_t)min(nslow, NN);
+                tree.n = nr;
+                tree.nf[0] = nr;
+                tree.nf[1] = 0;
+                tree.maxd = 0;
+            }
             __syncthreads();
-            uint32_t woff = 0;
-            for (int q = 0; q < wv; ++q) woff += s_wsum[q];
-            if (tid < nn) tree.cst[tid] = (uint16_t)(woff + incl - c);
-            if (tid < nn && tree.depth[tid] == 0) tree.pos[tid] = -1;
-            __syncthreads();
-        }
-        for (int k = tid; k < nn; k += kThreads)
-            if (tree.depth[k] > 0) tree.child[tree.cst[tree.par[k]] + tree.rank[k]] = (uint16_t)k;
-        __syncthreads();
-        for (int dd = 0; dd < maxd; ++dd) {
-            for (int k = tid; k < nn; k += kThreads)
-                if (tree.depth[k] == dd) {
-                    int run = tree.pos[k] + 1;
-                    const int c0 = tree.cst[k], nc = tree.nch[k];
-                    for (int j = 0; j < nc; ++j) {
-                        const int c = tree.child[c0 + j];
-                        tree.pos[c] = (int16_t)run;
-                        run += (int)tree.size[c];
+            for (int lv = 0;; lv ^= 1) {
+                const uint32_t nf = tree.nf[lv];
+                if (nf == 0) break;
+                for (uint32_t k = kme; k < nf; k += kThreads) {
+                    const int n = tree.front[lv][k];
+                    if (s_tree[tree.slot[n]]) expand_node<DIM, SP2, TAN>(d, P, step, &tree, n, lv ^ 1, s_tree);
+                }
+                __syncthreads();
+                if (tid == 0) tree.nf[lv] = 0;
+                __syncthreads();
+            }
+            nn = (int)min(tree.n, (uint32_t)NN);
+            const int maxd = (int)tree.maxd;
+            // subtree sizes, deepest level first (a root gets its family's count)
+            for (int dd = maxd; dd >= 1; --dd) {
+                for (int k = tid; k < nn; k += kThreads)
+                    if (tree.depth[k] == dd) {
+                        const uint32_t sz = tree.size[k] + 1u;
+                        tree.size[k] = sz;
+                        atomicAdd(&tree.size[tree.par[k]], sz);
                     }
+                __syncthreads();
+            }
+            // offspring grouped by parent (exclusive scan of the offspring counts
+            // in node order), then depth-first positions, top level first
+            {
+                constexpr int NPT = NN / kThreads;    // nodes tid * NPT + q, q < NPT
+                uint32_t c[NPT], csum = 0;
+    #pragma unroll
+                for (int q = 0; q < NPT; ++q) {
+                    const int k = tid * NPT + q;
+                    c[q] = k < nn ? (uint32_t)tree.nch[k] : 0u;
+                    csum += c[q];
                 }
+                uint32_t incl = csum;
+    #pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t v = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += v;
+                }
+                if (lane == 63) s_wsum[wv] = incl;
+                __syncthreads();
+                uint32_t run = incl - csum;
+                for (int q = 0; q < wv; ++q) run += s_wsum[q];
+    #pragma unroll
+                for (int q = 0; q < NPT; ++q) {
+                    const int k = tid * NPT + q;
+                    if (k < nn) {
+                        tree.cst[k] = (uint16_t)run;
+                        if (tree.depth[k] == 0) tree.pos[k] = -1;
+                    }
+                    run += c[q];
+                }
+                __syncthreads();
+            }
+            for (int k = tid; k < nn; k += kThreads)
+                if (tree.depth[k] > 0) tree.child[tree.cst[tree.par[k]] + tree.rank[k]] = (uint16_t)k;
+            __syncthreads();
+            for (int dd = 0; dd < maxd; ++dd) {
+                for (int k = tid; k < nn; k += kThreads)
+                    if (tree.depth[k] == dd) {
+                        int run = tree.pos[k] + 1;
+                        const int c0 = tree.cst[k], nc = tree.nch[k];
+                        for (int j = 0; j < nc; ++j) {
+                            const int c = tree.child[c0 + j];
+                            tree.pos[c] = (int16_t)run;
+                            run += (int)tree.size[c];
+                        }
+                    }
+                __syncthreads();
+            }
+            // record counts, tallies (from the Tree, or by a counting walk for the
+            // families that did not fit)
+            for (int k = tid; k < nn; k += kThreads) {
+                if (!s_tree[tree.slot[k]]) continue;
+                tal.events += tree.events[k];
+                tal.pairs += tree.pairs[k];
+                tal.killed += tree.killed[k];
+                tal.cap += tree.capped[k];
+                tal.maxdepth = max(tal.maxdepth, (int32_t)tree.depth[k]);
+            }
+            for (int k = kme; k < nslow; k += kThreads) {
+                const int slot = s_slow[k];
+                if (s_tree[slot]) {
+                    s_cnt[slot] = tree.size[k];
+                    continue;
+                }
+                const Node root = load_root(base, j0, slot);
+                bool unused = false;
+                s_cnt[slot] = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal, err,
+                                                                nullptr, slot, unused);
+            }
+            __syncthreads();
+
+        } else {
+            auto &s_pool = s_walk;
+            for (int k = kme; k < nslow; k += kThreads) {
+                const int slot = s_slow[k];
+                const Node root = load_root(base, j0, slot);
+                bool pooled = true;
+                s_cnt[slot] = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal,
+                                                                err, &s_pool, slot, pooled);
+                s_tree[slot] = pooled ? 1 : 0;
+            }
             __syncthreads();
         }
-        // record counts, tallies (from the Tree, or by a counting walk for the
-        // families that did not fit)
-        for (int k = tid; k < nn; k += kThreads) {
-            if (!s_tree[tree.slot[k]]) continue;
-            tal.events += tree.events[k];
-            tal.pairs += tree.pairs[k];
-            tal.killed += tree.killed[k];
-            tal.cap += tree.capped[k];
-            tal.maxdepth = max(tal.maxdepth, (int32_t)tree.depth[k]);
-        }
-        for (int k = kme; k < nslow; k += kThreads) {
-            const int slot = s_slow[k];
-            if (s_tree[slot]) {
-                s_cnt[slot] = tree.size[k];
-                continue;
-            }
-            const Node root = load_root(base, j0, slot);
-            s_cnt[slot] = walk_family<DIM, SP2, TAN, false>(d, P, step, root, E, base, 0, cap, dstride, tal, err);
-        }
-        __syncthreads();
 
         // 3. ordered exclusive scan of the record counts over the tile, in
         //    slot order (h, then tid)
@@ -1137,8 +1229,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
 #pragma unroll
         for (int h = 0; h < SPT; ++h) s_first[tid + h * kThreads] = s_excl + (int64_t)excl[h];
 
-        // 4. records into the staging area: from the stash and the Tree, or
-        //    by a second full walk for a family that did not fit the Tree
+        // 4. records into the staging area: from the stash and the Tree (or
+        //    the pool), or by a second full walk for a family that did not fit
 #pragma unroll
         for (int h = 0; h < SPT; ++h) {
             const int slot = tid + h * kThreads;
@@ -1165,32 +1257,69 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             }
         }
         __syncthreads();
-        for (int k = tid; k < nn; k += kThreads) {
-            if (tree.depth[k] == 0 || !s_tree[tree.slot[k]]) continue;
-            const int64_t li = s_first[tree.slot[k]] + tree.pos[k];
-            if (li >= cap) { err |= kErrCapacity; continue; }
-            const int64_t o = base + li;
-            const double t0 = tree.t0[k];
-            S.x0[o] = tree.x0[k] + (d.vfac * tree.k0[k]) * (d.dt - t0);
-            S.k0[o] = tree.k0[k];
-            if (DIM == 2) {
-                S.x1[o] = tree.x1[k] + (d.vfac * tree.k1[k]) * (d.dt - t0);
-                S.k1[o] = tree.k1[k];
+        if constexpr (kTree) {
+            auto &tree = s_walk;
+            for (int k = tid; k < nn; k += kThreads) {
+                if (tree.depth[k] == 0 || !s_tree[tree.slot[k]]) continue;
+                const int64_t li = s_first[tree.slot[k]] + tree.pos[k];
+                if (li >= cap) { err |= kErrCapacity; continue; }
+                const int64_t o = base + li;
+                const double t0 = tree.t0[k];
+                S.x0[o] = tree.x0[k] + (d.vfac * tree.k0[k]) * (d.dt - t0);
+                S.k0[o] = tree.k0[k];
+                if (DIM == 2) {
+                    S.x1[o] = tree.x1[k] + (d.vfac * tree.k1[k]) * (d.dt - t0);
+                    S.k1[o] = tree.k1[k];
+                }
+                if (SP2) S.w[o] = tree.w[k]; else S.sg[o] = tree.sg[k];
+                S.id[o] = tree.id[k];
+                if (TAN) {
+                    S.D[o] = tree.D[0][k];
+                    S.D[dstride + o] = tree.D[1][k];
+                    S.D[2 * dstride + o] = tree.D[2][k];
+                }
             }
-            if (SP2) S.w[o] = tree.w[k]; else S.sg[o] = tree.sg[k];
-            S.id[o] = tree.id[k];
-            if (TAN) {
-                S.D[o] = tree.D[0][k];
-                S.D[dstride + o] = tree.D[1][k];
-                S.D[2 * dstride + o] = tree.D[2][k];
+            for (int k = kme; k < nslow; k += kThreads) {
+                const int slot = s_slow[k];
+                if (s_tree[slot]) continue;
+                const Node root = load_root(base, j0, slot);
+                Tally none{0, 0, 0, 0, 0};
+                bool unused = false;
+                walk_family<DIM, SP2, TAN, true>(d, P, step, root, S, base, s_first[slot], cap, dstride, none, err,
+                                                 nullptr, slot, unused);
             }
-        }
-        for (int k = kme; k < nslow; k += kThreads) {
-            const int slot = s_slow[k];
-            if (s_tree[slot]) continue;
-            const Node root = load_root(base, j0, slot);
-            Tally none{0, 0, 0, 0, 0};
-            walk_family<DIM, SP2, TAN, true>(d, P, step, root, S, base, s_first[slot], cap, dstride, none, err);
+        } else {
+            auto &s_pool = s_walk;
+            const int npool = (int)min(s_pool.n, (uint32_t)kPool);
+            for (int r = tid; r < npool; r += kThreads) {
+                const int slot = s_pool.slot[r];
+                if (!s_tree[slot]) continue;
+                const int64_t li = s_first[slot] + s_pool.rank[r];
+                if (li >= cap) { err |= kErrCapacity; continue; }
+                const int64_t o = base + li;
+                S.x0[o] = s_pool.x0[r];
+                S.k0[o] = s_pool.k0[r];
+                if (DIM == 2) {
+                    S.x1[o] = s_pool.x1[r];
+                    S.k1[o] = s_pool.k1[r];
+                }
+                if (SP2) S.w[o] = s_pool.w[r]; else S.sg[o] = s_pool.sg[r];
+                S.id[o] = s_pool.id[r];
+                if (TAN) {
+                    S.D[o] = s_pool.D[0][r];
+                    S.D[dstride + o] = s_pool.D[1][r];
+                    S.D[2 * dstride + o] = s_pool.D[2][r];
+                }
+            }
+            for (int k = kme; k < nslow; k += kThreads) {
+                const int slot = s_slow[k];
+                if (s_tree[slot]) continue;
+                const Node root = load_root(base, j0, slot);
+                Tally none{0, 0, 0, 0, 0};
+                bool unused = false;
+                walk_family<DIM, SP2, TAN, true>(d, P, step, root, S, base, s_first[slot], cap, dstride, none, err,
+                                                 &s_pool, slot, unused);
+            }
         }
 
         // per-instance tallies, summed over the wavefront first
