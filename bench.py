@@ -112,6 +112,30 @@ def roofline_of(res, dim):
             "bytes_per_particle_step": stream_bytes_per_particle_step(dim)}
 
 
+def copy_rate(torch):
+    """Read+write rate of a plain 1 GiB device-to-device copy on the same GPU
+    (torch's copy kernel, HIP events): what a streaming kernel can reach on
+    this part in practice, beside the nominal peak."""
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(4):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        gbs = 4 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        best = gbs if best is None else max(best, gbs)
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
 def measured_traffic(dim, bytes_per_launch):
     """HBM bytes per launch from the committed counter summary of k_stream,
     only if that summary was taken on the current kernel source."""
@@ -194,6 +218,9 @@ def main():
     roof = roofline_of(main_res, 1)
     if roof is not None:
         roof["traffic"] = measured_traffic(1, roof["bytes_per_launch"])
+        cr = copy_rate(torch)
+        roof["attainable"] = {"what": "plain 1 GiB device copy, read + write, same GPU",
+                              "GBps": round(cr, 1), "frac": round(roof["achieved"] / cr, 4)}
     step_ms = main_res["profile"]["stream"][0] + main_res["profile"]["family"][0]
     log(f"sp1 1e7: {main_res['rate']:.4g} particle-steps/s, n_end={main_res['n_end']}, "
         f"profile={ {k: (round(v[0], 3), v[1]) for k, v in main_res['profile'].items()} }")
