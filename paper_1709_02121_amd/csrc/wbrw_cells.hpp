@@ -218,7 +218,10 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     for (int64_t t = t0; t < t1; ++t) {
         __syncthreads();
         const int b = segment_of(plan, B, t);
-        if (cb >= 0 && (b != cb || s_nkeys > (uint32_t)(kSlots / 2))) flush(cb);
+        // every thread reads the fill level before the flush resets it
+        const bool full = cb >= 0 && (b != cb || s_nkeys > (uint32_t)(kSlots / 2));
+        __syncthreads();
+        if (full) flush(cb);
         cb = b;
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
