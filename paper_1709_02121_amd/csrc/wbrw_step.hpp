@@ -158,22 +158,25 @@ __global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
 // lane, as in the particle array).
 __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost)
 {
+    // One wavefront per streaming tile, so that every tile's loads are in
+    // flight at once (the grid holds about as many wavefronts as tiles).
     const int B = d.B;
     const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
     const int64_t ntiles = plan[B];
     const uint64_t *tc = ghost ? d.tcAg : d.tcA;
     const uint64_t *emask = ghost ? d.emAg : d.emA;
     uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int kWaves = kThreads / 64;
     static_assert(kPPT * 4 <= 64, "one lane per (particle slot, wavefront) ballot");
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + wv; t < ntiles; t += (int64_t)gridDim.x * kWaves) {
         const int b = segment_of(plan, B, t);
         const int64_t tl = t - plan[b];
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
         const uint64_t rel = tc[t] - tc[plan[b]];
-        // exclusive scan of the ballot popcounts in (slot, wave) order, by
-        // each wave for itself
+        // ballot q = j * 4 + w holds particle slot j of the streaming
+        // kernel's wavefront w; exclusive scan of their popcounts in q order
         const uint64_t *em = emask + t * (kPPT * 4);
         const uint64_t mine = lane < kPPT * 4 ? em[lane] : 0ull;
         const uint32_t c = (uint32_t)__popcll(mine);
@@ -184,14 +187,16 @@ __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost)
             if (lane >= o) inc += v;
         }
         const uint32_t exc = inc - c;
-#pragma unroll
-        for (int j = 0; j < kPPT; ++j) {
-            const int q = j * 4 + wv;
-            const uint64_t m = __shfl(mine, q, 64);
-            const uint32_t off = __shfl(exc, q, 64);
+        const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
+#pragma unroll 4
+        for (int q = 0; q < kPPT * 4; ++q) {
+            const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, q) << 32) |
+                               (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mlo, q);
+            if (m == 0ull) continue;
+            const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)exc, q);
             if ((m >> lane) & 1ull) {
                 const int64_t pos = base + (int64_t)rel + off + lane_rank(m);
-                evi[pos] = (uint32_t)(tl * kTileA + (int64_t)j * kThreads + tid);
+                evi[pos] = (uint32_t)(tl * kTileA + (int64_t)(q >> 2) * kThreads + (q & 3) * 64 + lane);
             }
         }
     }
