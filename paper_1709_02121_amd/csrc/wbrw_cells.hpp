@@ -551,9 +551,14 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
                     atomicAdd(&acc[2 * d.max_bins + bin], t2);
                 }
             } else {
+                // sp1: a wavefront's sign sum fits 32 bits (half the shuffles)
                 int64_t v = 0;
-                if (bin >= 0) v = SP2 ? (int64_t)(wv[j] * 4294967296.0) : (int64_t)wv[j];
-                v = run_sum<int64_t>(bin, v, commit);
+                if (SP2) {
+                    if (bin >= 0) v = (int64_t)(wv[j] * 4294967296.0);
+                    v = run_sum<int64_t>(bin, v, commit);
+                } else {
+                    v = run_sum<int32_t>(bin, bin >= 0 ? (int32_t)wv[j] : 0, commit);
+                }
                 if (!commit || v == 0) continue;
                 if (priv)
                     atomicAdd((unsigned long long *)&s_raw[bin], (unsigned long long)v);
