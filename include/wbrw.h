@@ -123,7 +123,9 @@ typedef struct wbrw_config {
                                  Alg. 3 (Sec. 4.1) instead of the Gaussian f0 */
     double x_lo, x_hi;        /* annihilation grid and K box: every position axis */
     double k_lo, k_hi;        /* ... every wave-vector axis; offspring outside K are removed */
-    int32_t nx, nk;           /* cells per position / wave-vector axis */
+    int32_t nx, nk;           /* cells per position / wave-vector axis; N_h = nx nk (dim 1) or
+                                 nx^2 nk^2 (dim 2) must be < 2^31 (sp2: < 2^30), else
+                                 WBRW_EINVAL */
 } wbrw_config;
 
 typedef struct wbrw_stats {

@@ -111,6 +111,7 @@ int validate(const wbrw_config *c)
     const int64_t nh = c->dim == 1 ? (int64_t)c->nx * c->nk
                                    : (int64_t)c->nx * c->nx * (int64_t)c->nk * c->nk;
     if (nh >= (1ll << 31)) return WBRW_EINVAL;
+    if (c->strategy == WBRW_SP2 && nh >= (1ll << 30)) return WBRW_EINVAL;   // (cell, class) keys
     return WBRW_OK;
 }
 

@@ -47,25 +47,66 @@ __device__ __forceinline__ u128 ld128(const uint64_t *p)
     return ((u128)p[1] << 64) | (u128)p[0];
 }
 
+// Sum of v over the block (all threads call it; the result is in thread 0).
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v, unsigned long long *s_w)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if (lane == 0) s_w[wv] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kThreads / 64; ++q) t += s_w[q];
+    return t;
+}
+
 // ---- stage 1: classes, quantised weights, cells; class sizes and sums ------
+// Each block takes a contiguous run of tiles and sums N+, N-, S+, S- and the
+// escaped weight per instance; a block's last instance is left in its slot
+// of fpart for k_sp2_close_classify (others, rare, go to the counters
+// directly).  Per-tile atomics on the instance's counters would serialise.
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
 {
-    __shared__ unsigned long long s_acc[5];   // N0, N1, S0, S1, escaped
+    __shared__ unsigned long long s_w[kThreads / 64];
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t *plan = d.tileA;
     const int64_t ntiles = plan[B];
     const Ens E = pick_set(d, 0, ctl->cur);
     const int tid = threadIdx.x;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        if (tid < 5) s_acc[tid] = 0ull;
-        __syncthreads();
+    unsigned long long acc[5] = {0, 0, 0, 0, 0};   // N0, N1, S0, S1, escaped
+    auto publish = [&](int fb, bool last) {
+        unsigned long long tot[5];
+        for (int q = 0; q < 5; ++q) tot[q] = block_sum(acc[q], s_w);
+        if (tid == 0) {
+            if (last) {
+                int64_t *F = d.fpart + (int64_t)blockIdx.x * 8;
+                F[0] = fb;
+                for (int q = 0; q < 5; ++q) F[1 + q] = (int64_t)tot[q];
+            } else {
+                unsigned long long *st = (unsigned long long *)(d.bcls_stat + (int64_t)fb * 8);
+                for (int q = 0; q < 4; ++q)
+                    if (tot[q]) atomicAdd(&st[q], tot[q]);
+                if (tot[4])
+                    atomicAdd((unsigned long long *)&d.tally[(int64_t)fb * kTalCount + kTalEscaped], tot[4]);
+            }
+        }
+        for (int q = 0; q < 5; ++q) acc[q] = 0;
+    };
+    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = min((int64_t)blockIdx.x * per, ntiles), t1 = min(t0 + per, ntiles);
+    int cb = -1;
+    for (int64_t t = t0; t < t1; ++t) {
         const int b = segment_of(plan, B, t);
+        if (b != cb) {
+            if (cb >= 0) publish(cb, false);
+            cb = b;
+        }
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
-        unsigned long long a_n0 = 0, a_n1 = 0, a_s0 = 0, a_s1 = 0;
-        long long a_esc = 0;
         for (int j = 0; j < kPPT; ++j) {
             const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
             if (li >= n) continue;
@@ -76,53 +117,105 @@ __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
                                                DIM == 2 ? E.k1[i] : 0.0);
             int8_t cls = -1;
             if (nu < 0) {
-                a_esc += w < 0.0 ? -(long long)A : (long long)A;
+                acc[4] += w < 0.0 ? (unsigned long long)(-(long long)A) : (unsigned long long)A;
             } else if (w > 0.0) {
-                cls = 0; a_n0 += 1; a_s0 += A;
+                cls = 0; acc[0] += 1; acc[2] += A;
             } else if (w < 0.0) {
-                cls = 1; a_n1 += 1; a_s1 += A;
+                cls = 1; acc[1] += 1; acc[3] += A;
             }
             d.bcls[i] = cls;
             d.bA[i] = cls >= 0 ? A : 0ull;
             d.bcell[i] = nu;
         }
-        if (a_n0) atomicAdd(&s_acc[0], a_n0);
-        if (a_n1) atomicAdd(&s_acc[1], a_n1);
-        if (a_s0) atomicAdd(&s_acc[2], a_s0);
-        if (a_s1) atomicAdd(&s_acc[3], a_s1);
-        if (a_esc) atomicAdd(&s_acc[4], (unsigned long long)a_esc);
-        __syncthreads();
-        if (tid == 0) {
-            unsigned long long *st = (unsigned long long *)(d.bcls_stat + (int64_t)b * 8);
-            for (int q = 0; q < 4; ++q)
-                if (s_acc[q]) atomicAdd(&st[q], s_acc[q]);
-            if (s_acc[4])
-                atomicAdd((unsigned long long *)&d.tally[(int64_t)b * kTalCount + kTalEscaped], s_acc[4]);
-        }
-        __syncthreads();
     }
+    publish(cb, true);
+}
+
+// After k_sp2_classify (one block): the blocks' last-instance sums into the
+// class counters (summed per instance in LDS when the instances fit).
+__global__ __launch_bounds__(kThreads) void k_sp2_close_classify(Dev d, int grid)
+{
+    constexpr int kLdsB = 512;
+    __shared__ unsigned long long s_acc[5][kLdsB];
+    const int B = d.B;
+    const int tid = threadIdx.x;
+    const bool lds = B <= kLdsB;
+    if (lds)
+        for (int b = tid; b < B; b += kThreads)
+            for (int q = 0; q < 5; ++q) s_acc[q][b] = 0;
+    __syncthreads();
+    for (int g = tid; g < grid; g += kThreads) {
+        const int64_t *F = d.fpart + (int64_t)g * 8;
+        if (F[0] < 0) continue;
+        const int b = (int)F[0];
+        for (int q = 0; q < 5; ++q) {
+            if (!F[1 + q]) continue;
+            if (lds) {
+                atomicAdd(&s_acc[q][b], (unsigned long long)F[1 + q]);
+            } else if (q < 4) {
+                atomicAdd((unsigned long long *)&d.bcls_stat[(int64_t)b * 8 + q], (unsigned long long)F[1 + q]);
+            } else {
+                atomicAdd((unsigned long long *)&d.tally[(int64_t)b * kTalCount + kTalEscaped],
+                          (unsigned long long)F[5]);
+            }
+        }
+    }
+    __syncthreads();
+    if (lds)
+        for (int b = tid; b < B; b += kThreads) {
+            int64_t *st = d.bcls_stat + (int64_t)b * 8;
+            for (int q = 0; q < 4; ++q) st[q] += (int64_t)s_acc[q][b];
+            d.tally[(int64_t)b * kTalCount + kTalEscaped] += (int64_t)s_acc[4][b];
+        }
 }
 
 // ---- stage 2: kept copies k_i, residuals r_i, per-tile residual sums --------
+// Each block takes a contiguous run of tiles; the kept-copy sums per class
+// are summed per instance and left in fpart (instance changes, rare, add to
+// the counters) for k_sp2_tilescan.  The 128-bit residual sums are per tile.
 __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
 {
-    __shared__ unsigned long long s_acc[6];    // sumk0, sumk1, tile sums (lo,hi) x 2
+    __shared__ unsigned long long s_acc[4];    // tile sums (lo,hi) x 2
+    __shared__ unsigned long long s_w[kThreads / 64];
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t *plan = d.tileA;
     const int64_t ntiles = plan[B];
     const int tid = threadIdx.x;
     const int64_t C = d.cap_total;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        if (tid < 6) s_acc[tid] = 0ull;
-        __syncthreads();
+    unsigned long long ks[2] = {0, 0};       // this thread's kept copies per class
+    auto publish = [&](int fb, bool last) {
+        const unsigned long long k0 = block_sum(ks[0], s_w), k1 = block_sum(ks[1], s_w);
+        if (tid == 0) {
+            if (last) {
+                int64_t *F = d.fpart + (int64_t)blockIdx.x * 8;
+                F[0] = fb;
+                F[1] = (int64_t)k0;
+                F[2] = (int64_t)k1;
+            } else {
+                unsigned long long *bs = (unsigned long long *)(d.bcls_stat + (int64_t)fb * 8);
+                if (k0) atomicAdd(&bs[kBK0], k0);
+                if (k1) atomicAdd(&bs[kBK1], k1);
+            }
+        }
+        ks[0] = ks[1] = 0;
+    };
+    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t ta = min((int64_t)blockIdx.x * per, ntiles), tb = min(ta + per, ntiles);
+    int cb = -1;
+    for (int64_t t = ta; t < tb; ++t) {
         const int b = segment_of(plan, B, t);
+        if (b != cb) {
+            if (cb >= 0) publish(cb, false);
+            cb = b;
+        }
+        if (tid < 4) s_acc[tid] = 0ull;
+        __syncthreads();
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
         const int64_t *st = d.bcls_stat + (int64_t)b * 8;
         const uint64_t Nc[2] = {(uint64_t)st[kBN0], (uint64_t)st[kBN1]};
         const uint64_t Sc[2] = {(uint64_t)st[kBS0], (uint64_t)st[kBS1]};
-        unsigned long long sk[2] = {0, 0};
         u128 rs[2] = {0, 0};
         for (int j = 0; j < kPPT; ++j) {
             const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
@@ -134,7 +227,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
                 const uint64_t num = Nc[c] * d.bA[i];       // < 2^63
                 k = num / Sc[c];
                 r = num - k * Sc[c];
-                sk[c] += k;
+                ks[c] += k;
                 rs[c] += r;
             }
             d.bcopies[i] = (int32_t)k;
@@ -143,38 +236,50 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
         }
         // block sums: 64-bit halves of the 128-bit residual sums
         for (int c = 0; c < 2; ++c) {
-            if (sk[c]) atomicAdd(&s_acc[c], sk[c]);
             // residual sums of a thread stay < 2^66: add as lo + carry-free hi
             const uint64_t lo = (uint64_t)rs[c], hi = (uint64_t)(rs[c] >> 64);
-            const unsigned long long old = atomicAdd(&s_acc[2 + 2 * c], (unsigned long long)lo);
+            const unsigned long long old = atomicAdd(&s_acc[2 * c], (unsigned long long)lo);
             const uint64_t carry = (old + lo < old) ? 1ull : 0ull;
-            if (hi + carry) atomicAdd(&s_acc[3 + 2 * c], (unsigned long long)(hi + carry));
+            if (hi + carry) atomicAdd(&s_acc[1 + 2 * c], (unsigned long long)(hi + carry));
         }
         __syncthreads();
         if (tid == 0) {
-            unsigned long long *bs = (unsigned long long *)(d.bcls_stat + (int64_t)b * 8);
-            if (s_acc[0]) atomicAdd(&bs[kBK0], s_acc[0]);
-            if (s_acc[1]) atomicAdd(&bs[kBK1], s_acc[1]);
             for (int c = 0; c < 2; ++c) {
                 uint64_t *ts = d.bTile + 2 * ((int64_t)c * d.tstride + t);
-                ts[0] = s_acc[2 + 2 * c];
-                ts[1] = s_acc[3 + 2 * c];
+                ts[0] = s_acc[2 * c];
+                ts[1] = s_acc[1 + 2 * c];
             }
         }
         __syncthreads();
     }
+    publish(cb, true);
 }
 
 // ---- stage 3: exclusive scan of the tile sums per instance and class; the
 // draw counts N_r and the draw-tile plan.  One block per instance. ----------
-__global__ __launch_bounds__(kThreads) void k_sp2_tilescan(Dev d)
+__global__ __launch_bounds__(kThreads) void k_sp2_tilescan(Dev d, int rgrid)
 {
     __shared__ uint64_t s_lo[kThreads], s_hi[kThreads];
     __shared__ uint64_t s_clo, s_chi;
+    __shared__ unsigned long long s_w[kThreads / 64];
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int tid = threadIdx.x;
     for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        // the k_sp2_resid blocks' kept-copy sums of this instance
+        unsigned long long k0 = 0, k1 = 0;
+        for (int g = tid; g < rgrid; g += kThreads) {
+            const int64_t *F = d.fpart + (int64_t)g * 8;
+            if (F[0] != b) continue;
+            k0 += (unsigned long long)F[1];
+            k1 += (unsigned long long)F[2];
+        }
+        k0 = block_sum(k0, s_w);
+        k1 = block_sum(k1, s_w);
+        if (tid == 0) {
+            d.bcls_stat[(int64_t)b * 8 + kBK0] += (int64_t)k0;
+            d.bcls_stat[(int64_t)b * 8 + kBK1] += (int64_t)k1;
+        }
         const int64_t t0 = d.tileA[b], t1 = d.tileA[b + 1];
         for (int c = 0; c < 2; ++c) {
             uint64_t *ts = d.bTile + 2 * ((int64_t)c * d.tstride);
@@ -325,29 +430,86 @@ __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
 }
 
 // ---- stage 6: filtered counts per cell and class ---------------------------
+// Copies are summed per (cell, class) in an LDS hash table per block (open
+// addressing, 8 probes), over a contiguous run of tiles, and added to the
+// count grids when the block moves to another instance, when the table is
+// half full, and at the end: the ensemble's regenerated part puts thousands
+// of particles in each cell, whose device-wide atomics would serialise.  An
+// update whose probes all fail adds directly.
 __global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
 {
-    Ctl *ctl = d.ctl;
+    constexpr int kSlots = 4096;
+    __shared__ int32_t s_key[kSlots];
+    __shared__ int32_t s_val[kSlots];
+    __shared__ uint32_t s_nkeys;
     const int B = d.B;
     const int64_t *plan = d.tileA;
     const int64_t ntiles = plan[B];
     const int tid = threadIdx.x;
     const int64_t plane = (int64_t)B * d.Nh;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
+    if (tid == 0) s_nkeys = 0;
+    // key = 2 cell + class (N_h < 2^30)
+    auto flush = [&](int fb) {
+        for (int j = tid; j < kSlots; j += kThreads) {
+            const int k = s_key[j];
+            if (k < 0) continue;
+            const int v = s_val[j];
+            if (v != 0) atomicAdd(&d.ntil[(int64_t)(k & 1) * plane + (int64_t)fb * d.Nh + (k >> 1)], v);
+            s_key[j] = -1;
+            s_val[j] = 0;
+        }
+        if (tid == 0) s_nkeys = 0;
+        __syncthreads();
+    };
+    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = min((int64_t)blockIdx.x * per, ntiles), t1 = min(t0 + per, ntiles);
+    int cb = -1;
+    for (int64_t t = t0; t < t1; ++t) {
         __syncthreads();
         const int b = segment_of(plan, B, t);
+        // every thread reads the fill level before the flush resets it
+        const bool full = cb >= 0 && (b != cb || s_nkeys > (uint32_t)(kSlots / 2));
+        __syncthreads();
+        if (full) flush(cb);
+        cb = b;
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
+        const int64_t li0 = (t - plan[b]) * kTileA + tid;
+        int8_t cl[kPPT];
+        int32_t cp[kPPT];
+        int64_t cell[kPPT];
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {      // loads first
+            const int64_t li = li0 + (int64_t)j * kThreads;
+            const int64_t i = P.base + (li < n ? li : 0);
+            cl[j] = li < n ? d.bcls[i] : (int8_t)-1;
+            cp[j] = d.bcopies[i];
+            cell[j] = d.bcell[i];
+        }
+#pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
-            if (li >= n) continue;
-            const int64_t i = P.base + li;
-            const int8_t c = d.bcls[i];
-            const int32_t cp = d.bcopies[i];
-            if (c < 0 || cp == 0) continue;
-            atomicAdd(&d.ntil[(int64_t)c * plane + (int64_t)b * d.Nh + d.bcell[i]], cp);
+            if (cl[j] < 0 || cp[j] == 0) continue;
+            const int key = (int)(cell[j] << 1) | (int)cl[j];
+            const uint32_t h = ((uint32_t)key * 2654435761u) >> 20;
+            bool done = false;
+            for (int pr = 0; pr < 8 && !done; ++pr) {
+                const int slot = (int)((h + (uint32_t)pr) & (uint32_t)(kSlots - 1));
+                int k = __hip_atomic_load(&s_key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (k == -1) {
+                    k = atomicCAS(&s_key[slot], -1, key);
+                    if (k == -1) atomicAdd(&s_nkeys, 1u);
+                }
+                if (k == -1 || k == key) {
+                    atomicAdd(&s_val[slot], cp[j]);
+                    done = true;
+                }
+            }
+            if (!done) atomicAdd(&d.ntil[(int64_t)cl[j] * plane + (int64_t)b * d.Nh + cell[j]], cp[j]);
         }
     }
+    __syncthreads();
+    if (cb >= 0) flush(cb);
 }
 
 // ---- stage 7: exact rational cell values and the rounding step -------------
@@ -410,8 +572,9 @@ template <int DIM>
 int enqueue_sp2_bootstrap(const Dev &d, hipStream_t s, int grid, int grid_scan)
 {
     hipLaunchKernelGGL(k_sp2_classify<DIM>, dim3(grid), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_close_classify, dim3(1), dim3(kThreads), 0, s, d, grid);
     hipLaunchKernelGGL(k_sp2_resid, dim3(grid), dim3(kThreads), 0, s, d);
-    hipLaunchKernelGGL(k_sp2_tilescan, dim3(std::min(d.B, grid_scan)), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_tilescan, dim3(std::min(d.B, grid_scan)), dim3(kThreads), 0, s, d, grid);
     hipLaunchKernelGGL(k_close_sp2_tilescan, dim3(1), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_prefix, dim3(grid), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_draw, dim3(grid), dim3(kThreads), 0, s, d);
