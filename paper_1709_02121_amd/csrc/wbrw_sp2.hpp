@@ -333,62 +333,90 @@ __global__ __launch_bounds__(kThreads) void k_close_sp2_tilescan(Dev d)
 // ---- stage 4: per-particle exclusive prefixes P_0, P_1 (128-bit) -----------
 __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
 {
-    __shared__ uint64_t s_lo[2][kThreads], s_hi[2][kThreads];
+    // Lanes take consecutive particles (coalesced): particle j * kThreads +
+    // tid of the tile.  Per class, each of the kPPT rows is scanned within the
+    // wavefront (shuffles of the 64-bit halves with carry); the (row,
+    // wavefront) totals are then scanned in that order by one wavefront.
+    constexpr int kW = kThreads / 64;
+    __shared__ uint64_t s_lo[2][kPPT * kW], s_hi[2][kPPT * kW];
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t *plan = d.tileA;
     const int64_t ntiles = plan[B];
     const int64_t C = d.cap_total;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         __syncthreads();
         const int b = segment_of(plan, B, t);
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
-        // this thread's kPPT particles are consecutive: li0 .. li0 + kPPT - 1
-        const int64_t li0 = (t - plan[b]) * kTileA + (int64_t)tid * kPPT;
+        const int64_t li0 = (t - plan[b]) * kTileA + tid;
         uint64_t r[kPPT];
         int8_t cl[kPPT];
-        u128 sum[2] = {0, 0};
+#pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = li0 + j;
-            r[j] = 0;
-            cl[j] = -1;
-            if (li < n) {
-                const int64_t i = P.base + li;
-                r[j] = d.bP[2 * i];
-                cl[j] = d.bcls[i];
-                if (cl[j] >= 0) sum[cl[j]] += r[j];
-            }
+            const int64_t li = li0 + (int64_t)j * kThreads;
+            const int64_t i = P.base + (li < n ? li : 0);
+            r[j] = d.bP[2 * i];
+            cl[j] = li < n ? d.bcls[i] : (int8_t)-1;
         }
-        for (int c = 0; c < 2; ++c) { s_lo[c][tid] = (uint64_t)sum[c]; s_hi[c][tid] = (uint64_t)(sum[c] >> 64); }
+        uint64_t elo[2][kPPT], ehi[2][kPPT];     // exclusive within (row, wavefront)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int j = 0; j < kPPT; ++j) {
+                const uint64_t v = cl[j] == c ? r[j] : 0ull;
+                uint64_t lo = v, hi = 0;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint64_t plo = __shfl_up(lo, o, 64), phi = __shfl_up(hi, o, 64);
+                    if (lane >= o) {
+                        const uint64_t nlo = lo + plo;
+                        hi = hi + phi + (nlo < lo ? 1ull : 0ull);
+                        lo = nlo;
+                    }
+                }
+                if (lane == 63) { s_lo[c][j * kW + wv] = lo; s_hi[c][j * kW + wv] = hi; }
+                elo[c][j] = lo - v;
+                ehi[c][j] = hi - (lo < v ? 1ull : 0ull);
+            }
         __syncthreads();
-        for (int o = 1; o < kThreads; o <<= 1) {
-            u128 add[2] = {0, 0};
-            if (tid >= o)
-                for (int c = 0; c < 2; ++c) add[c] = ((u128)s_hi[c][tid - o] << 64) | s_lo[c][tid - o];
-            __syncthreads();
+        if (wv == 0) {   // exclusive scan of the kPPT * kW totals, in place
+#pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const u128 cur = (((u128)s_hi[c][tid] << 64) | s_lo[c][tid]) + add[c];
-                s_lo[c][tid] = (uint64_t)cur;
-                s_hi[c][tid] = (uint64_t)(cur >> 64);
+                const uint64_t v0 = lane < kPPT * kW ? s_lo[c][lane] : 0ull;
+                const uint64_t v1 = lane < kPPT * kW ? s_hi[c][lane] : 0ull;
+                uint64_t lo = v0, hi = v1;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint64_t plo = __shfl_up(lo, o, 64), phi = __shfl_up(hi, o, 64);
+                    if (lane >= o) {
+                        const uint64_t nlo = lo + plo;
+                        hi = hi + phi + (nlo < lo ? 1ull : 0ull);
+                        lo = nlo;
+                    }
+                }
+                const uint64_t xlo = lo - v0, xhi = hi - v1 - (lo < v0 ? 1ull : 0ull);
+                if (lane < kPPT * kW) { s_lo[c][lane] = xlo; s_hi[c][lane] = xhi; }
             }
-            __syncthreads();
         }
-        u128 run[2];
-        for (int c = 0; c < 2; ++c) {
-            const uint64_t *ts = d.bTile + 2 * ((int64_t)c * d.tstride + t);
-            run[c] = ld128(ts) + ((((u128)s_hi[c][tid] << 64) | s_lo[c][tid]) - sum[c]);
-        }
+        __syncthreads();
+        u128 tb[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) tb[c] = ld128(d.bTile + 2 * ((int64_t)c * d.tstride + t));
+#pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = li0 + j;
+            const int64_t li = li0 + (int64_t)j * kThreads;
             if (li >= n) continue;
             const int64_t i = P.base + li;
-            st128(d.bP + 2 * i, run[0]);
-            st128(d.bP + 2 * C + 2 * i, run[1]);
-            if (cl[j] >= 0) run[cl[j]] += r[j];
+            u128 pc[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                pc[c] = tb[c] + (((u128)s_hi[c][j * kW + wv] << 64) | s_lo[c][j * kW + wv]) +
+                        (((u128)ehi[c][j] << 64) | elo[c][j]);
+            st128(d.bP + 2 * i, pc[0]);
+            st128(d.bP + 2 * C + 2 * i, pc[1]);
         }
-        __syncthreads();
     }
 }
 
