@@ -371,6 +371,15 @@ void stage_end(wbrw_t h)
     h->open_ev = nullptr;
 }
 
+// Ordered scan of |n_nu| (see k_scan_sums): tile sums, their one-block scan
+// with the new counts, then the offsets and regeneration-tile starts.
+void enqueue_scan(int grid, hipStream_t s, const Dev &d, int zero_counts)
+{
+    hipLaunchKernelGGL(k_scan_sums, dim3(grid), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_scan, dim3(grid), dim3(kThreads), 0, s, d, zero_counts);
+}
+
 template <int DIM>
 void enqueue_step_dim(wbrw_t h)
 {
@@ -445,8 +454,7 @@ int enqueue_annihilate_dim(wbrw_t h)
         if (rc) return rc;
         stage_begin(h, WBRW_STAGE_SCAN);
         // with tangents the counts stay for the ghost pass, which clears them
-        hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, tan ? 0 : 1);
-        hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
+        enqueue_scan(h->grid[G_SCAN], s, d, tan ? 0 : 1);
         stage_end(h);
         stage_begin(h, WBRW_STAGE_REGEN);
         if (tan) hipLaunchKernelGGL((k_regen<DIM, true, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
@@ -467,8 +475,7 @@ int enqueue_annihilate_dim(wbrw_t h)
         hipLaunchKernelGGL((k_bin<DIM, false, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 1);
         stage_end(h);
         stage_begin(h, WBRW_STAGE_SCAN);
-        hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 0);
-        hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
+        enqueue_scan(h->grid[G_SCAN], s, d, 0);
         stage_end(h);
         stage_begin(h, WBRW_STAGE_REGEN);
         hipLaunchKernelGGL((k_regen<DIM, false, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
@@ -484,8 +491,7 @@ int enqueue_annihilate_dim(wbrw_t h)
     hipLaunchKernelGGL((k_bin<DIM, false, false>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
     stage_begin(h, WBRW_STAGE_SCAN);
-    hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
-    hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
+    enqueue_scan(h->grid[G_SCAN], s, d, 1);
     stage_end(h);
     stage_begin(h, WBRW_STAGE_REGEN);
     hipLaunchKernelGGL((k_regen<DIM, false, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
@@ -755,8 +761,7 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         const double mu = cfg->dim == 1 ? d.dx * d.dk : ((d.dx * d.dx) * d.dk) * d.dk;
         const int nb = std::max(1, std::min(h->cus * 8, (int)ceil_div((int64_t)h->B * L.Nh, kThreads)));
         hipLaunchKernelGGL(k_hist_round, dim3(nb), dim3(kThreads), 0, s, d, (const double *)hd, mu);
-        hipLaunchKernelGGL(k_scan, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d, 1);
-        hipLaunchKernelGGL(k_close_scan, dim3(1), dim3(kThreads), 0, s, d);
+        enqueue_scan(h->grid[G_SCAN], s, d, 1);
         if (h->dim == 1) {
             if (h->strategy == WBRW_SP2 && h->tangent) hipLaunchKernelGGL((k_regen<1, true, true>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);
             else if (h->strategy == WBRW_SP2) hipLaunchKernelGGL((k_regen<1, true, false>), dim3(h->grid[G_REGEN]), dim3(kThreads), 0, s, d);

@@ -297,26 +297,76 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
 }
 
 // ---------------------------------------------------------------------------
-// sp1 annihilation, pass 2: ordered scan of |n_nu| per instance.
-// off[nu] = exclusive prefix | (n_nu < 0 ? bit 62 : 0); Nnew[b] = total.
-// With zero_counts the count grid is cleared for the next annihilation.
+// sp1 annihilation, pass 2: ordered scan of |n_nu| per instance, in three
+// launches with no tile waiting for another: k_scan_sums (the sum of every
+// scan tile), k_close_scan (one block: their exclusive scan, the new counts
+// Nnew[b] with the capacity clamp, the regeneration-tile plan), k_scan
+// (off[nu] = exclusive prefix | (n_nu < 0 ? bit 62 : 0), the first cell of
+// every regeneration tile; with zero_counts the count grid is cleared for the
+// next annihilation).  A look-back chain over the tiles of an instance cost
+// more than the extra launch.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
+__global__ __launch_bounds__(kThreads) void k_scan_sums(Dev d)
 {
-    __shared__ int64_t s_t;
-    __shared__ uint32_t s_wsum[4];
-    __shared__ uint32_t s_excl;
-    Ctl *ctl = d.ctl;
-    const uint32_t epoch = ctl->ann_seq + 1u;
+    __shared__ uint64_t s_w[kThreads / 64];
     const int B = d.B;
     const int64_t tiles_per = (d.Nh + kTileS - 1) / kTileS;
     const int64_t ntiles = tiles_per * B;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (;;) {
-        if (tid == 0) s_t = next_tile(&ctl->ticket[kPassScan], ntiles);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int b = (int)(t / tiles_per);
+        const int64_t tl = t - (int64_t)b * tiles_per;
+        const int64_t cbase = (int64_t)b * d.Nh;
+        uint64_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {      // lanes take consecutive cells
+            const int64_t c = tl * kTileS + (int64_t)j * kThreads + tid;
+            const int32_t v = c < d.Nh ? d.cnt[cbase + c] : 0;
+            sum += (uint64_t)(v < 0 ? -v : v);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (lane == 0) s_w[wv] = sum;
         __syncthreads();
-        const int64_t t = s_t;
-        if (t >= ntiles) break;
+        if (tid == 0) {
+            uint64_t tot = 0;
+            for (int q = 0; q < kThreads / 64; ++q) tot += s_w[q];
+            d.stS[t] = tot;
+        }
+        __syncthreads();
+    }
+}
+
+// After k_scan_sums (one block): the scan of the tile sums (in place), the
+// new counts with the capacity clamp, and the regeneration-tile plan.
+__global__ __launch_bounds__(kThreads) void k_close_scan(Dev d)
+{
+    Ctl *ctl = d.ctl;
+    const int B = d.B;
+    const int64_t tiles_per = (d.Nh + kTileS - 1) / kTileS;
+    const int64_t T = tiles_per * B;
+    const uint64_t total = scan_tile_counts(d.stS, d.stS, T);
+    for (int b = threadIdx.x; b < B; b += kThreads) {
+        const int64_t f = (int64_t)b * tiles_per, l = f + tiles_per;
+        int64_t n = (int64_t)((l < T ? d.stS[l] : total) - d.stS[f]);
+        if (n > d.ip[b].cap) {
+            atomicOr(&ctl->err, kErrCapacity);
+            n = d.ip[b].cap;
+        }
+        d.Nnew[b] = n;
+    }
+    __syncthreads();
+    block_plan(d.tileR, d.Nnew, B, kTileR);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
+{
+    __shared__ uint32_t s_wsum[4];
+    const int B = d.B;
+    const int64_t tiles_per = (d.Nh + kTileS - 1) / kTileS;
+    const int64_t ntiles = tiles_per * B;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int b = (int)(t / tiles_per);
         const int64_t tl = t - (int64_t)b * tiles_per;
         const int64_t cbase = (int64_t)b * d.Nh;
@@ -338,17 +388,9 @@ __global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
         }
         if (lane == 63) s_wsum[wv] = incl;
         __syncthreads();
-        uint32_t woff = 0, agg = 0;
-        for (int q = 0; q < 4; ++q) { if (q < wv) woff += s_wsum[q]; agg += s_wsum[q]; }
-        if (wv == 0) {
-            const uint32_t excl = tile_prefix(d.stS, t, (int64_t)b * tiles_per, epoch, agg);
-            if (lane == 0) {
-                if (tl == tiles_per - 1) d.Nnew[b] = (int64_t)(excl + agg);
-                s_excl = excl;
-            }
-        }
-        __syncthreads();
-        int64_t run = (int64_t)s_excl + (int64_t)(woff + incl - sum);
+        uint32_t woff = 0;
+        for (int q = 0; q < wv; ++q) woff += s_wsum[q];
+        int64_t run = (int64_t)(d.stS[t] - d.stS[(int64_t)b * tiles_per]) + (int64_t)(woff + incl - sum);
         const InstParam &P = d.ip[b];
         int64_t *rst = d.rstart + P.rbase;
 #pragma unroll
@@ -367,21 +409,6 @@ __global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
         }
         __syncthreads();
     }
-}
-
-// After k_scan (one block): capacity clamp and the regeneration-tile plan.
-__global__ __launch_bounds__(kThreads) void k_close_scan(Dev d)
-{
-    Ctl *ctl = d.ctl;
-    const int B = d.B;
-    for (int b = threadIdx.x; b < B; b += kThreads) {
-        if (d.Nnew[b] > d.ip[b].cap) {
-            atomicOr(&ctl->err, kErrCapacity);
-            d.Nnew[b] = d.ip[b].cap;
-        }
-    }
-    __syncthreads();
-    block_plan(d.tileR, d.Nnew, B, kTileR);
 }
 
 // largest cell nu in [lo, hi] with (off[nu] & mask) <= o

@@ -43,8 +43,7 @@ enum : int {
 
 // ticket counters of the persistent passes
 enum : int {
-    kPassStream = 0, kPassFamily = 1, kPassStreamG = 2, kPassFamilyG = 3,
-    kPassScan = 4, kPassRegen = 5, kPassTiles = 6, kPassGhost = 7, kPassCount = 8
+    kPassFamily = 1, kPassFamilyG = 3, kPassGhost = 7, kPassCount = 8
 };
 
 struct InstParam {
@@ -121,7 +120,8 @@ struct Dev {
     int64_t *rstart;            // first cell of every regeneration tile (written by k_scan)
     uint32_t *ev_idx;           // [cap_total] event-parent index within its instance
     uint32_t *gev_idx;          // ghosts
-    uint64_t *stS, *stG;                // look-back status words
+    uint64_t *stS;              // scan-tile sums of |n_nu|, then their exclusive prefix
+    uint64_t *stG;              // look-back status words of k_ghosts
     uint64_t *tcB, *tcBg;               // per family tile: record count
     uint64_t *toB, *toBg;               // per family tile: exclusive prefix of the counts
     int64_t *tsB, *tsBg;                // per family tile: where its records were staged
@@ -255,6 +255,38 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *ctr, int64_t ntiles)
     if ((int64_t)t == ntiles + (int64_t)gridDim.x - 1)
         __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return (int64_t)t;
+}
+
+// Exclusive scan of the per-tile counts cnt[0..T) into pre[0..T) by one
+// block (pre may be cnt); returns the total.  Each thread scans a
+// contiguous chunk whose loads are independent of each other.
+__device__ uint64_t scan_tile_counts(const uint64_t *cnt, uint64_t *pre, int64_t T)
+{
+    __shared__ uint64_t s_sum[kThreads];
+    const int tid = threadIdx.x;
+    const int64_t per = (T + kThreads - 1) / kThreads;
+    const int64_t c0 = min((int64_t)tid * per, T), c1 = min(c0 + per, T);
+    uint64_t acc = 0;
+#pragma unroll 16
+    for (int64_t q = c0; q < c1; ++q) acc += cnt[q];
+    s_sum[tid] = acc;
+    __syncthreads();
+    for (int o = 1; o < kThreads; o <<= 1) {
+        const uint64_t v = tid >= o ? s_sum[tid - o] : 0ull;
+        __syncthreads();
+        s_sum[tid] += v;
+        __syncthreads();
+    }
+    uint64_t run = s_sum[tid] - acc;
+#pragma unroll 16
+    for (int64_t q = c0; q < c1; ++q) {
+        const uint64_t c = cnt[q];
+        pre[q] = run;
+        run += c;
+    }
+    const uint64_t total = s_sum[kThreads - 1];
+    __syncthreads();
+    return total;
 }
 
 // plan[b] = sum_{b' < b} ceil(cnt[b'] / tile), plan[B] = total; one block.

@@ -93,37 +93,6 @@ __device__ __forceinline__ bool in_kbox(const Dev &d, const double *k)
     return true;
 }
 
-// Exclusive scan of the per-tile counts cnt[0..T) into pre[0..T) by one
-// block (pre may be cnt); returns the total.  Each thread scans a
-// contiguous chunk whose loads are independent of each other.
-__device__ uint64_t scan_tile_counts(const uint64_t *cnt, uint64_t *pre, int64_t T)
-{
-    __shared__ uint64_t s_sum[kThreads];
-    const int tid = threadIdx.x;
-    const int64_t per = (T + kThreads - 1) / kThreads;
-    const int64_t c0 = min((int64_t)tid * per, T), c1 = min(c0 + per, T);
-    uint64_t acc = 0;
-#pragma unroll 16
-    for (int64_t q = c0; q < c1; ++q) acc += cnt[q];
-    s_sum[tid] = acc;
-    __syncthreads();
-    for (int o = 1; o < kThreads; o <<= 1) {
-        const uint64_t v = tid >= o ? s_sum[tid - o] : 0ull;
-        __syncthreads();
-        s_sum[tid] += v;
-        __syncthreads();
-    }
-    uint64_t run = s_sum[tid] - acc;
-#pragma unroll 16
-    for (int64_t q = c0; q < c1; ++q) {
-        const uint64_t c = cnt[q];
-        pre[q] = run;
-        run += c;
-    }
-    const uint64_t total = s_sum[kThreads - 1];
-    __syncthreads();
-    return total;
-}
 
 // After k_stream (one block): exclusive scan of the tile event counts over
 // all tiles (in place), the event count of every instance, the family-tile
