@@ -361,7 +361,11 @@ __global__ __launch_bounds__(kThreads) void k_close_scan(Dev d)
 
 __global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
 {
-    __shared__ uint32_t s_wsum[4];
+    // Lanes take consecutive cells (coalesced): cell j * kThreads + tid of the
+    // tile.  Each of the kPPT rows is scanned within the wavefront; the
+    // (row, wavefront) totals are scanned in that order by one wavefront.
+    constexpr int kW = kThreads / 64;
+    __shared__ uint32_t s_tot[kPPT * kW];
     const int B = d.B;
     const int64_t tiles_per = (d.Nh + kTileS - 1) / kTileS;
     const int64_t ntiles = tiles_per * B;
@@ -370,42 +374,53 @@ __global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
         const int b = (int)(t / tiles_per);
         const int64_t tl = t - (int64_t)b * tiles_per;
         const int64_t cbase = (int64_t)b * d.Nh;
-        // thread owns kPPT consecutive cells
-        const int64_t c0 = tl * kTileS + (int64_t)tid * kPPT;
+        const int64_t c0 = tl * kTileS + tid;
         int32_t v[kPPT];
-        uint32_t sum = 0;
+        uint32_t ex[kPPT];
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t c = c0 + j;
+            const int64_t c = c0 + (int64_t)j * kThreads;
             v[j] = (c < d.Nh) ? d.cnt[cbase + c] : 0;
-            sum += (uint32_t)(v[j] < 0 ? -v[j] : v[j]);
         }
-        uint32_t incl = sum;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += y;
+        for (int j = 0; j < kPPT; ++j) {
+            const uint32_t a = (uint32_t)(v[j] < 0 ? -v[j] : v[j]);
+            uint32_t incl = a;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+            if (lane == 63) s_tot[j * kW + wv] = incl;
+            ex[j] = incl - a;
         }
-        if (lane == 63) s_wsum[wv] = incl;
         __syncthreads();
-        uint32_t woff = 0;
-        for (int q = 0; q < wv; ++q) woff += s_wsum[q];
-        int64_t run = (int64_t)(d.stS[t] - d.stS[(int64_t)b * tiles_per]) + (int64_t)(woff + incl - sum);
+        if (wv == 0) {   // exclusive scan of the kPPT * kW totals, in place
+            const uint32_t a = lane < kPPT * kW ? s_tot[lane] : 0u;
+            uint32_t incl = a;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+            if (lane < kPPT * kW) s_tot[lane] = incl - a;
+        }
+        __syncthreads();
+        const int64_t tbase = (int64_t)(d.stS[t] - d.stS[(int64_t)b * tiles_per]);
         const InstParam &P = d.ip[b];
         int64_t *rst = d.rstart + P.rbase;
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t c = c0 + j;
-            if (c < d.Nh) {
-                const int64_t a = v[j] < 0 ? -v[j] : v[j];
-                d.off[cbase + c] = run | (v[j] < 0 ? kOffNeg : 0);
-                // this cell holds the first output of every regeneration tile
-                // that starts inside [run, run + a)
-                for (int64_t q = (run + kTileR - 1) / kTileR; q * kTileR < run + a && q < P.rtiles; ++q)
-                    rst[q] = c;
-                run += a;
-                if (zero_counts && v[j] != 0) d.cnt[cbase + c] = 0;
-            }
+            const int64_t c = c0 + (int64_t)j * kThreads;
+            if (c >= d.Nh) continue;
+            const int64_t run = tbase + (int64_t)s_tot[j * kW + wv] + (int64_t)ex[j];
+            const int64_t a = v[j] < 0 ? -v[j] : v[j];
+            d.off[cbase + c] = run | (v[j] < 0 ? kOffNeg : 0);
+            // this cell holds the first output of every regeneration tile
+            // that starts inside [run, run + a)
+            for (int64_t q = (run + kTileR - 1) / kTileR; q * kTileR < run + a && q < P.rtiles; ++q)
+                rst[q] = c;
+            if (zero_counts && v[j] != 0) d.cnt[cbase + c] = 0;
         }
         __syncthreads();
     }
