@@ -31,9 +31,9 @@ struct Layout {
     // offsets
     size_t ens[2][8] = {}, gens[2][8] = {};
     size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
-    size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, chc = 0, tileA = 0, tileB = 0, tileR = 0,
+    size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, chc = 0, tileA = 0, Nsrt = 0, srtS = 0, tileB = 0, tileR = 0,
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
-           tcA = 0, tcAg = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, toB = 0, toBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, off = 0,
+           tcA = 0, tcAg = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, toB = 0, toBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
            bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0, xitab = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
@@ -115,6 +115,19 @@ int validate(const wbrw_config *c)
     return WBRW_OK;
 }
 
+// Plain sp1 binning adds its counts into one grid per XCD, so that the
+// atomics of an XCD's blocks stay in that XCD's L2; the scan folds the copies
+// together.  Worth it while the extra grids (read once per annihilation) are
+// small beside the ensemble that is binned.
+bool xcd_counts(const wbrw_config *c)
+{
+    if (c->strategy == WBRW_SP2 || c->track_tangent != 0) return false;
+    const int64_t nh = c->dim == 1 ? (int64_t)c->nx * c->nk : (int64_t)c->nx * c->nx * (int64_t)c->nk * c->nk;
+    int64_t n0 = 0;
+    for (int b = 0; b < c->n_instances; ++b) n0 += c->N0[b];
+    return (int64_t)(kXcd - 1) * nh * c->n_instances <= n0;
+}
+
 Layout make_layout(const wbrw_config *c)
 {
     Layout L;
@@ -182,6 +195,8 @@ Layout make_layout(const wbrw_config *c)
     L.evc = take(cur, 2 * BB * 8);
     L.chc = take(cur, 2 * BB * 8);
     L.tileA = take(cur, 2 * (BB + 1) * 8);
+    L.Nsrt = take(cur, BB * 8);
+    L.srtS = take(cur, (BB + 1) * 8);
     L.tileB = take(cur, 2 * (BB + 1) * 8);
     L.tileR = take(cur, (BB + 1) * 8);
     L.tileG = take(cur, (BB + 1) * 8);
@@ -204,6 +219,7 @@ Layout make_layout(const wbrw_config *c)
     }
     L.stS = take(cur, (size_t)L.tilesS * 8);
     L.cnt = take(cur, BB * Nh * 4);
+    if (xcd_counts(c)) L.cntx = take(cur, (size_t)(kXcd - 1) * BB * Nh * 4);
     if (tan) {
         L.occ = take(cur, BB * Nh * 4);
         L.Tcell = take(cur, 3 * BB * Nh * 8);
@@ -684,6 +700,8 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.evc = at<int64_t>(w, L.evc);
     d.chc = at<int64_t>(w, L.chc);
     d.tileA = at<int64_t>(w, L.tileA);
+    d.Nsrt = at<int64_t>(w, L.Nsrt);
+    d.srtS = at<int64_t>(w, L.srtS);
     d.tileB = at<int64_t>(w, L.tileB);
     d.tileR = at<int64_t>(w, L.tileR);
     d.tileG = at<int64_t>(w, L.tileG);
@@ -706,6 +724,7 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.stG = h->tangent ? at<uint64_t>(w, L.stG) : nullptr;
     d.stS = at<uint64_t>(w, L.stS);
     d.cnt = at<int32_t>(w, L.cnt);
+    d.cntx = L.cntx ? at<int32_t>(w, L.cntx) : nullptr;
     d.off = at<int64_t>(w, L.off);
     d.occ = h->tangent ? at<int32_t>(w, L.occ) : nullptr;
     d.Tcell = h->tangent ? at<double>(w, L.Tcell) : nullptr;
@@ -1058,6 +1077,10 @@ int wbrw_restore(wbrw_t h, const void *src, size_t bytes)
     plan_host(gplan, NG.data(), h->B, kTileA);
     HIPCHK(hipMemcpyAsync(h->d.N, N.data(), 8 * h->B, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(h->d.tileA, plan.data(), 8 * (h->B + 1), hipMemcpyHostToDevice, h->stream));
+    // the restored order is not known to be cell order (Nsrt = 0)
+    std::vector<int64_t> zeros(h->B + 1, 0);
+    HIPCHK(hipMemcpyAsync(h->d.Nsrt, zeros.data(), 8 * h->B, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d.srtS, zeros.data(), 8 * (h->B + 1), hipMemcpyHostToDevice, h->stream));
     if (h->tangent) {
         HIPCHK(hipMemcpyAsync(h->d.NG, NG.data(), 8 * h->B, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->d.tileA + h->B + 1, gplan.data(), 8 * (h->B + 1), hipMemcpyHostToDevice, h->stream));

@@ -165,6 +165,29 @@ __global__ __launch_bounds__(kThreads) void k_hist_round(Dev d, const double *hi
 // tangents, also the occupancy and the tangent sums T_nu per cell (for sp2
 // only these: its counts come from the bootstrap).
 // ---------------------------------------------------------------------------
+// Binning cost of the particle tiles before instance b (see kBinLateCost).
+__device__ __forceinline__ int64_t bin_cost_before(const Dev &d, const int64_t *plan, int b)
+{
+    return kBinLateCost * plan[b] - (kBinLateCost - 1) * d.srtS[b];
+}
+
+// The first particle tile whose cost prefix reaches c, or the tile count
+// when c reaches the total.
+__device__ __forceinline__ int64_t tile_at_cost(const Dev &d, const int64_t *plan, int64_t c)
+{
+    const int B = d.B;
+    if (c >= bin_cost_before(d, plan, B)) return plan[B];
+    int lo = 0, hi = B - 1;   // the last instance whose cost prefix is <= c
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bin_cost_before(d, plan, mid) <= c) lo = mid; else hi = mid - 1;
+    }
+    const int64_t r = c - bin_cost_before(d, plan, lo);
+    const int64_t srt = d.srtS[lo + 1] - d.srtS[lo];
+    // cost before tile l of the instance: l up to srt, then srt + kBinLateCost (l - srt)
+    return plan[lo] + (r <= srt ? r : srt + (r - srt + kBinLateCost - 1) / kBinLateCost);
+}
+
 template <int DIM, bool SP2, bool TAN>
 __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
 {
@@ -188,6 +211,11 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     const int64_t *Ncur = ghost ? d.NG : d.N;
     const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
     const int tid = threadIdx.x;
+    // plain sp1: this block's XCD copy of the count grid (blocks are dealt
+    // to the XCDs round robin; any other placement is still correct)
+    const int xc = (int)(blockIdx.x % kXcd);
+    int32_t *const cg = (TAN || d.cntx == nullptr || xc == 0) ? d.cnt
+                        : d.cntx + (int64_t)(xc - 1) * d.Nh * B;
     if (!TAN)
         for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
     if (tid == 0) { s_esc = 0; s_nkeys = 0; }
@@ -198,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 const int k = s_key[j];
                 if (k < 0) continue;
                 const int v = s_val[j];
-                if (v != 0) atomicAdd(&d.cnt[fbase + k], v);
+                if (v != 0) atomicAdd(&cg[fbase + k], v);
                 s_key[j] = -1;
                 s_val[j] = 0;
             }
@@ -212,8 +240,17 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
         }
         __syncthreads();
     };
-    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-    const int64_t t0 = min((int64_t)blockIdx.x * per, ntiles), t1 = min(t0 + per, ntiles);
+    // The block's contiguous run of tiles: an equal share of the binning cost
+    // for the particles, an equal share of the tiles for the ghosts.
+    int64_t t0, t1;
+    if (ghost) {
+        t0 = ntiles * blockIdx.x / gridDim.x;
+        t1 = ntiles * (blockIdx.x + 1) / gridDim.x;
+    } else {
+        const int64_t W = bin_cost_before(d, plan, B);
+        t0 = tile_at_cost(d, plan, (W * blockIdx.x + gridDim.x - 1) / gridDim.x);
+        t1 = tile_at_cost(d, plan, (W * (blockIdx.x + 1) + gridDim.x - 1) / gridDim.x);
+    }
     int cb = -1;
     for (int64_t t = t0; t < t1; ++t) {
         __syncthreads();
@@ -266,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                         done = true;
                     }
                 }
-                if (!done) atomicAdd(&d.cnt[cbase + nu], s);
+                if (!done) atomicAdd(&cg[cbase + nu], s);
             } else {
                 // lanes hold consecutive particles: sum equal-cell runs in
                 // registers, then one atomic per run
@@ -318,11 +355,37 @@ __global__ __launch_bounds__(kThreads) void k_scan_sums(Dev d)
         const int64_t tl = t - (int64_t)b * tiles_per;
         const int64_t cbase = (int64_t)b * d.Nh;
         uint64_t sum = 0;
+        if (d.cntx == nullptr) {
 #pragma unroll
-        for (int j = 0; j < kPPT; ++j) {      // lanes take consecutive cells
-            const int64_t c = tl * kTileS + (int64_t)j * kThreads + tid;
-            const int32_t v = c < d.Nh ? d.cnt[cbase + c] : 0;
-            sum += (uint64_t)(v < 0 ? -v : v);
+            for (int j = 0; j < kPPT; ++j) {      // lanes take consecutive cells
+                const int64_t c = tl * kTileS + (int64_t)j * kThreads + tid;
+                const int32_t v = c < d.Nh ? d.cnt[cbase + c] : 0;
+                sum += (uint64_t)(v < 0 ? -v : v);
+            }
+        } else {
+            // fold the XCD copies of the sp1 counts into cnt and clear them
+            const int64_t nc = d.Nh * B;
+#pragma unroll 2
+            for (int j = 0; j < kPPT; ++j) {
+                const int64_t c = tl * kTileS + (int64_t)j * kThreads + tid;
+                if (c >= d.Nh) continue;
+                const int64_t g = cbase + c;
+                int32_t part[kXcd - 1];
+#pragma unroll
+                for (int x = 0; x < kXcd - 1; ++x) part[x] = d.cntx[(int64_t)x * nc + g];
+                int32_t v = d.cnt[g];
+                bool moved = false;
+#pragma unroll
+                for (int x = 0; x < kXcd - 1; ++x) {
+                    v += part[x];
+                    if (part[x] != 0) {
+                        d.cntx[(int64_t)x * nc + g] = 0;
+                        moved = true;
+                    }
+                }
+                if (moved) d.cnt[g] = v;
+                sum += (uint64_t)(v < 0 ? -v : v);
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
@@ -495,9 +558,13 @@ __global__ __launch_bounds__(kThreads) void k_close_regen(Dev d)
 {
     Ctl *ctl = d.ctl;
     const int B = d.B;
-    for (int b = threadIdx.x; b < B; b += kThreads) d.N[b] = d.Nnew[b];
+    for (int b = threadIdx.x; b < B; b += kThreads) {
+        d.N[b] = d.Nnew[b];
+        d.Nsrt[b] = d.Nnew[b];   // the regenerated ensemble is in cell order
+    }
     __syncthreads();
     block_plan(d.tileA, d.N, B, kTileA);
+    block_prefix(d.srtS, B, [&](int b) { return d.Nsrt[b] / kTileA; });
     if (threadIdx.x == 0) {
         ctl->cur ^= 1u;
         ctl->ann_seq += 1u;

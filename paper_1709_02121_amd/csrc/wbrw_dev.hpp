@@ -18,6 +18,7 @@ constexpr int kPPT = 8;                 // particles (or cells) per thread in st
 constexpr int kTileA = kThreads * kPPT; // particles per streaming tile
 constexpr int kTileB = kThreads;        // event-parents per family tile (the smallest; see fam_tile)
 constexpr int kTileS = kThreads * kPPT; // cells per scan tile
+constexpr int kXcd = 8;                 // accelerator complexes (XCDs), each with its own L2
 constexpr int kTileR = kThreads * 4;    // regenerated particles per tile
 constexpr int kMaxDepth = 16;           // deepest family tree walked within one step
 constexpr uint32_t kEventCap = 4096u;   // jumps per particle-step
@@ -128,7 +129,11 @@ struct Dev {
     int64_t *stg;                       // [2][B] staging fill of the inactive buffer sets
     uint64_t *tcA, *tcAg;               // per streaming tile: event count, then its prefix
     uint64_t *emA, *emAg;               // per streaming tile: kPPT x 4 wavefront event ballots
+    int64_t *Nsrt;              // [B] particles in cell order at the front of each instance
+    int64_t *srtS;              // [B+1] prefix of floor(Nsrt[b] / kTileA)
     int32_t *cnt;               // [B][Nh] signed counts (sp1) / rounded counts (sp2)
+    int32_t *cntx;              // [kXcd - 1][B][Nh] partial sp1 counts of the blocks on the
+                                // other XCDs (cnt is copy 0); null when not used
     int64_t *off;               // [B][Nh] exclusive prefix of |n_nu|, bit 62 = negative cell
     int32_t *occ;               // [B][Nh] occupancy (tangents)
     double *Tcell;              // [3][B][Nh] tangent sums per cell
@@ -258,63 +263,137 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *ctr, int64_t ntiles)
 }
 
 // Exclusive scan of the per-tile counts cnt[0..T) into pre[0..T) by one
-// block (pre may be cnt); returns the total.  Each thread scans a
-// contiguous chunk whose loads are independent of each other.
-__device__ uint64_t scan_tile_counts(const uint64_t *cnt, uint64_t *pre, int64_t T)
+// block (pre may be cnt); returns the total to every thread.  Chunks of
+// kThreads x P counts are loaded coalesced (all loads in flight together)
+// into LDS, padded by one slot per P so that the per-thread runs below fall
+// in different banks; every thread scans its own run of P, the run totals are
+// scanned within each wavefront and across the four wavefronts, and the
+// prefixes leave LDS coalesced.
+constexpr int kScanP = 24;
+template <int P>
+__device__ __forceinline__ uint64_t scan_chunks(const uint64_t *cnt, uint64_t *pre, int64_t T,
+                                                uint64_t *s_v, uint64_t *s_w)
 {
-    __shared__ uint64_t s_sum[kThreads];
-    const int tid = threadIdx.x;
-    const int64_t per = (T + kThreads - 1) / kThreads;
-    const int64_t c0 = min((int64_t)tid * per, T), c1 = min(c0 + per, T);
-    uint64_t acc = 0;
-#pragma unroll 16
-    for (int64_t q = c0; q < c1; ++q) acc += cnt[q];
-    s_sum[tid] = acc;
-    __syncthreads();
-    for (int o = 1; o < kThreads; o <<= 1) {
-        const uint64_t v = tid >= o ? s_sum[tid - o] : 0ull;
+    constexpr int C = kThreads * P, W = kThreads / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int run0 = tid * (P + 1);
+    uint64_t carry = 0;
+    for (int64_t c0 = 0; c0 < T; c0 += C) {
+        const int n = (int)min((int64_t)C, T - c0);
         __syncthreads();
-        s_sum[tid] += v;
+        uint64_t v[P], acc = 0;
+#pragma unroll
+        for (int r = 0; r < P; ++r)   // clamped, unconditional: no branch between the loads
+            v[r] = cnt[c0 + min(r * kThreads + tid, n - 1)];
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const int i = r * kThreads + tid;
+            s_v[i + i / P] = v[r];
+        }
         __syncthreads();
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            v[r] = tid * P + r < n ? s_v[run0 + r] : 0ull;
+            acc += v[r];
+        }
+        uint64_t incl = acc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) s_w[wv] = incl;
+        __syncthreads();
+        uint64_t below = 0, chunk = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t t = s_w[w];
+            below += w < wv ? t : 0ull;
+            chunk += t;
+        }
+        uint64_t run = carry + below + (incl - acc);
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            s_v[run0 + r] = run;
+            run += v[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const int i = r * kThreads + tid;
+            if (i < n) pre[c0 + i] = s_v[i + i / P];
+        }
+        carry += chunk;
     }
-    uint64_t run = s_sum[tid] - acc;
-#pragma unroll 16
-    for (int64_t q = c0; q < c1; ++q) {
-        const uint64_t c = cnt[q];
-        pre[q] = run;
-        run += c;
-    }
-    const uint64_t total = s_sum[kThreads - 1];
     __syncthreads();
-    return total;
+    return carry;
+}
+
+__device__ __forceinline__ uint64_t scan_tile_counts(const uint64_t *cnt, uint64_t *pre, int64_t T)
+{
+    __shared__ uint64_t s_v[kThreads * (kScanP + 1)];
+    __shared__ uint64_t s_w[kThreads / 64];
+    // a short list takes one small chunk: fewer loads and LDS passes per thread
+    if (T <= kThreads * 4) return scan_chunks<4>(cnt, pre, T, s_v, s_w);
+    return scan_chunks<kScanP>(cnt, pre, T, s_v, s_w);
+}
+
+// plan[b] = sum_{b' < b} value(b'), plan[B] = total; one block.  Values are
+// scanned within each wavefront, then across the four wavefronts.
+template <class F>
+__device__ __forceinline__ void block_prefix(int64_t *plan, int B, F value)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (B == 1) {
+        if (tid == 0) {
+            plan[1] = value(0);
+            plan[0] = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    __shared__ int64_t s_w[kThreads / 64];
+    int64_t carry = 0;
+    for (int c0 = 0; c0 < B; c0 += kThreads) {
+        const int b = c0 + tid;
+        const int64_t v = b < B ? value(b) : 0;
+        int64_t incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        __syncthreads();
+        if (lane == 63) s_w[wv] = incl;
+        __syncthreads();
+        int64_t below = 0, chunk = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            const int64_t t = s_w[w];
+            below += w < wv ? t : 0;
+            chunk += t;
+        }
+        if (b < B) plan[b] = carry + below + incl - v;
+        carry += chunk;
+    }
+    if (tid == 0) plan[B] = carry;
+    __syncthreads();
 }
 
 // plan[b] = sum_{b' < b} ceil(cnt[b'] / tile), plan[B] = total; one block.
 __device__ __forceinline__ void block_plan(int64_t *plan, const int64_t *cnt, int B, int64_t tile)
 {
-    __shared__ int64_t s_v[kThreads];
-    __shared__ int64_t s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 < B; c0 += kThreads) {
-        const int b = c0 + (int)threadIdx.x;
-        const int64_t v = (b < B) ? (cnt[b] + tile - 1) / tile : 0;
-        s_v[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < kThreads; o <<= 1) {
-            const int64_t add = (threadIdx.x >= (unsigned)o) ? s_v[threadIdx.x - o] : 0;
-            __syncthreads();
-            s_v[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (b < B) plan[b] = s_carry + s_v[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == kThreads - 1) s_carry += s_v[kThreads - 1];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) plan[B] = s_carry;
-    __syncthreads();
+    block_prefix(plan, B, [&](int b) { return (cnt[b] + tile - 1) / tile; });
 }
+
+// Cost of binning a streaming tile: 1 inside the cell-ordered front of its
+// instance (the first Nsrt[b] particles, as the last regeneration left
+// them), kBinLateCost after it, where the offspring appended since then
+// scatter over many more cells per tile.  With srtS[b] = sum_{b' < b}
+// floor(Nsrt[b'] / kTileA), the cost of the tiles before instance b is
+// kBinLateCost tileA[b] - (kBinLateCost - 1) srtS[b]; it needs N[b] >=
+// Nsrt[b], which holds because steps only append.
+constexpr int64_t kBinLateCost = 3;
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 {
