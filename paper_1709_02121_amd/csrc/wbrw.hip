@@ -31,9 +31,9 @@ struct Layout {
     // offsets
     size_t ens[2][8] = {}, gens[2][8] = {};
     size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
-    size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, chc = 0, tileA = 0, Nsrt = 0, srtS = 0, tileB = 0, tileR = 0,
+    size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, tileA = 0, Nsrt = 0, srtS = 0, tileB = 0, tileR = 0,
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
-           tcA = 0, tcAg = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, toB = 0, toBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, off = 0,
+           tcA = 0, tcAg = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
            bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0, xitab = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
@@ -193,7 +193,6 @@ Layout make_layout(const wbrw_config *c)
     L.Nnew = take(cur, BB * 8);
     L.NGnew = take(cur, BB * 8);
     L.evc = take(cur, 2 * BB * 8);
-    L.chc = take(cur, 2 * BB * 8);
     L.tileA = take(cur, 2 * (BB + 1) * 8);
     L.Nsrt = take(cur, BB * 8);
     L.srtS = take(cur, (BB + 1) * 8);
@@ -206,14 +205,14 @@ Layout make_layout(const wbrw_config *c)
     L.tcA = take(cur, (size_t)L.tilesA * 8);
     L.emA = take(cur, (size_t)L.tilesA * kPPT * 4 * 8);
     L.tcB = take(cur, (size_t)L.tilesB * 8);
-    L.toB = take(cur, (size_t)L.tilesB * 8);
+    L.supB = take(cur, (size_t)(L.tilesB / kSupGroup + 1) * kSupStride * 8);
     L.tsB = take(cur, (size_t)L.tilesB * 8);
     L.stg = take(cur, 2 * BB * 8);
     if (tan) {
         L.tcAg = take(cur, (size_t)L.tilesAg * 8);
         L.emAg = take(cur, (size_t)L.tilesAg * kPPT * 4 * 8);
         L.tcBg = take(cur, (size_t)L.tilesBg * 8);
-        L.toBg = take(cur, (size_t)L.tilesBg * 8);
+        L.supBg = take(cur, (size_t)(L.tilesBg / kSupGroup + 1) * kSupStride * 8);
         L.tsBg = take(cur, (size_t)L.tilesBg * 8);
         L.stG = take(cur, (size_t)L.tilesS * 8);
     }
@@ -419,7 +418,6 @@ void enqueue_step_dim(wbrw_t h)
     else
         hipLaunchKernelGGL((k_family<DIM, false, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
-    hipLaunchKernelGGL(k_close_records, dim3(1), dim3(kThreads), 0, s, d, 0);
     if (h->strategy == WBRW_SP2 && tan)
         hipLaunchKernelGGL((k_place_records<DIM, true, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
     else if (h->strategy == WBRW_SP2)
@@ -436,7 +434,6 @@ void enqueue_step_dim(wbrw_t h)
         hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1);
-        hipLaunchKernelGGL(k_close_records, dim3(1), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL((k_place_records<DIM, false, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 1, 1, h->grid[G_FAMILY]);
         stage_end(h);
@@ -698,7 +695,6 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.Nnew = at<int64_t>(w, L.Nnew);
     d.NGnew = at<int64_t>(w, L.NGnew);
     d.evc = at<int64_t>(w, L.evc);
-    d.chc = at<int64_t>(w, L.chc);
     d.tileA = at<int64_t>(w, L.tileA);
     d.Nsrt = at<int64_t>(w, L.Nsrt);
     d.srtS = at<int64_t>(w, L.srtS);
@@ -713,13 +709,13 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.tcA = at<uint64_t>(w, L.tcA);
     d.emA = at<uint64_t>(w, L.emA);
     d.tcB = at<uint64_t>(w, L.tcB);
-    d.toB = at<uint64_t>(w, L.toB);
+    d.supB = at<uint64_t>(w, L.supB);
     d.tsB = at<int64_t>(w, L.tsB);
     d.stg = at<int64_t>(w, L.stg);
     d.tcAg = h->tangent ? at<uint64_t>(w, L.tcAg) : nullptr;
     d.emAg = h->tangent ? at<uint64_t>(w, L.emAg) : nullptr;
     d.tcBg = h->tangent ? at<uint64_t>(w, L.tcBg) : nullptr;
-    d.toBg = h->tangent ? at<uint64_t>(w, L.toBg) : nullptr;
+    d.supBg = h->tangent ? at<uint64_t>(w, L.supBg) : nullptr;
     d.tsBg = h->tangent ? at<int64_t>(w, L.tsBg) : nullptr;
     d.stG = h->tangent ? at<uint64_t>(w, L.stG) : nullptr;
     d.stS = at<uint64_t>(w, L.stS);

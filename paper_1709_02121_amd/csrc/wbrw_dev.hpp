@@ -18,6 +18,8 @@ constexpr int kPPT = 8;                 // particles (or cells) per thread in st
 constexpr int kTileA = kThreads * kPPT; // particles per streaming tile
 constexpr int kTileB = kThreads;        // event-parents per family tile (the smallest; see fam_tile)
 constexpr int kTileS = kThreads * kPPT; // cells per scan tile
+constexpr int kSupGroup = 64;           // family tiles per record-count group sum
+constexpr int kSupStride = 16;          // u64 slots between group sums (one per 128 B line)
 constexpr int kXcd = 8;                 // accelerator complexes (XCDs), each with its own L2
 constexpr int kTileR = kThreads * 4;    // regenerated particles per tile
 constexpr int kMaxDepth = 16;           // deepest family tree walked within one step
@@ -111,7 +113,6 @@ struct Dev {
     Ctl *ctl;
     int64_t *N, *NG, *Nnew, *NGnew;
     int64_t *evc;               // [2][B] event counts (real, ghost)
-    int64_t *chc;               // [2][B] child counts
     int64_t *tileA;             // [2][B+1] streaming-tile plan (real, ghost)
     int64_t *tileB;             // [2][B+1] family-tile plan
     int64_t *tileR;             // [B+1] regeneration-tile plan
@@ -124,7 +125,8 @@ struct Dev {
     uint64_t *stS;              // scan-tile sums of |n_nu|, then their exclusive prefix
     uint64_t *stG;              // look-back status words of k_ghosts
     uint64_t *tcB, *tcBg;               // per family tile: record count
-    uint64_t *toB, *toBg;               // per family tile: exclusive prefix of the counts
+    uint64_t *supB, *supBg;             // per kSupGroup family tiles: sum of their record
+                                        // counts (entries kSupStride apart)
     int64_t *tsB, *tsBg;                // per family tile: where its records were staged
     int64_t *stg;                       // [2][B] staging fill of the inactive buffer sets
     uint64_t *tcA, *tcAg;               // per streaming tile: event count, then its prefix

@@ -14,9 +14,10 @@
 // before the end of the step) is evaluated for all parents in lockstep; the
 // others take the general walk, spread over the block.  Records hold the
 // end-of-step state, so no generation is revisited in a later launch.  Each
-// tile stages its records contiguously in the inactive buffer set;
-// k_close_records scans the tiles' record counts and k_place_records copies
-// the records to their ordered place after the instance's particles.
+// tile stages its records contiguously in the inactive buffer set and adds
+// its record count to the sum of its group of kSupGroup tiles;
+// k_place_records finds each tile's place from those sums and copies the
+// records there, after the instance's particles.
 #pragma once
 #include <type_traits>
 
@@ -115,7 +116,6 @@ __global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
     __syncthreads();
     block_plan(d.tileB + (int64_t)ghost * (B + 1), evc, B, ghost ? kTileB : fam_tile(d.dim, d.tangent != 0));
     for (int b = tid; b < B; b += kThreads) {
-        d.chc[(int64_t)ghost * B + b] = 0;
         d.stg[(int64_t)ghost * B + b] = 0;
         if (!ghost) d.tally[(int64_t)b * kTalCount + kTalPSteps] += Ncur[b];
     }
@@ -921,6 +921,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     // placed after the ordered scan by k_place_records
     const Ens S = pick_set(d, ghost, set ^ 1u);
     uint64_t *tcnt = ghost ? d.tcBg : d.tcB;
+    uint64_t *tsup = ghost ? d.supBg : d.supB;
     int64_t *tstg = ghost ? d.tsBg : d.tsB;
     const uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
     const int pass = ghost ? kPassFamilyG : kPassFamily;
@@ -1198,6 +1199,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             s_excl = sb;
             tcnt[t] = agg;
             tstg[t] = sb;
+            if (agg)
+                atomicAdd((unsigned long long *)&tsup[(t / kSupGroup) * kSupStride], (unsigned long long)agg);
         }
         __syncthreads();
 #pragma unroll
@@ -1331,21 +1334,33 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     if (err) atomicOr(&ctl->err, err);
 }
 
-// After k_family (one block): exclusive scan of the family tiles' record
-// counts and the record count of every instance.
-__global__ __launch_bounds__(kThreads) void k_close_records(Dev d, int ghost)
+// Sum of the record counts of family tiles [a, c) for every thread of the
+// block: the tiles before the first whole group of kSupGroup, the group sums,
+// and the tiles after the last whole group.
+__device__ __forceinline__ int64_t tile_range_sum(const uint64_t *tc, const uint64_t *sup, int64_t a,
+                                                  int64_t c, uint64_t *s_w)
 {
-    const int B = d.B;
-    const int64_t *plan = d.tileB + (int64_t)ghost * (B + 1);
-    const uint64_t *tc = ghost ? d.tcBg : d.tcB;
-    uint64_t *to = ghost ? d.toBg : d.toB;
-    const int64_t T = plan[B];
-    const uint64_t total = scan_tile_counts(tc, to, T);
-    for (int b = threadIdx.x; b < B; b += kThreads) {
-        const uint64_t lo = plan[b] < T ? to[plan[b]] : total;
-        const uint64_t hi = plan[b + 1] < T ? to[plan[b + 1]] : total;
-        d.chc[(int64_t)ghost * B + b] = (int64_t)(hi - lo);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t ga = (a + kSupGroup - 1) / kSupGroup * kSupGroup, gc = c / kSupGroup * kSupGroup;
+    const bool groups = ga <= gc;
+    const int64_t nh = c <= a ? 0 : (groups ? ga - a : c - a);
+    const int64_t ng = groups ? (gc - ga) / kSupGroup : 0;
+    const int64_t nt = groups ? c - gc : 0;
+    uint64_t v = 0;
+    for (int64_t e = tid; e < nh + ng + nt; e += kThreads) {
+        if (e < nh) v += tc[a + e];
+        else if (e < nh + ng) v += sup[(ga / kSupGroup + (e - nh)) * kSupStride];
+        else v += tc[gc + (e - nh - ng)];
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) s_w[wv] = v;
+    __syncthreads();
+    uint64_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < kThreads / 64; ++q) tot += s_w[q];
+    __syncthreads();
+    return (int64_t)tot;
 }
 
 // Every family tile's staged records (contiguous in the inactive buffer set)
@@ -1363,8 +1378,9 @@ __global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost)
     const Ens E = pick_set(d, ghost, set);
     const Ens S = pick_set(d, ghost, set ^ 1u);
     const uint64_t *tc = ghost ? d.tcBg : d.tcB;
-    const uint64_t *to = ghost ? d.toBg : d.toB;
+    const uint64_t *sup = ghost ? d.supBg : d.supB;
     const int64_t *ts = ghost ? d.tsBg : d.tsB;
+    __shared__ uint64_t s_w[kThreads / 64];
     const int64_t dstride = ghost ? d.gcap_total : d.cap_total;
     uint32_t err = 0;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -1373,7 +1389,7 @@ __global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost)
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t cap = ghost ? P.gcap : P.cap;
         const int64_t n = (int64_t)tc[t], src = ts[t];
-        const int64_t dst = Ncur[b] + (int64_t)(to[t] - to[plan[b]]);
+        const int64_t dst = Ncur[b] + tile_range_sum(tc, sup, plan[b], t, s_w);
         for (int64_t r = threadIdx.x; r < n; r += kThreads) {
             if (src + r >= cap) break;                 // never staged (flagged by k_family)
             if (dst + r >= cap) { err |= kErrCapacity; break; }
@@ -1442,19 +1458,23 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
             T[kTalEventCap] += s_acc[3][b];
             if (s_acc[4][b] > T[kTalMaxDepth]) T[kTalMaxDepth] = s_acc[4][b];
         }
-    int64_t *chc = d.chc + (int64_t)ghost * B;
+    const int64_t *rec = d.stg + (int64_t)ghost * B;   // records of the step (staging fill)
     int64_t *evc = d.evc + (int64_t)ghost * B;
     for (int b = tid; b < B; b += kThreads) {
         const InstParam &P = d.ip[b];
         const int64_t cap = ghost ? P.gcap : P.cap;
-        int64_t n = Ncur[b] + chc[b];
+        int64_t n = Ncur[b] + rec[b];
         if (n > cap) {
             atomicOr(&ctl->err, kErrCapacity);
             n = cap;
         }
         Ncur[b] = n;
-        chc[b] = 0;
         evc[b] = 0;
+    }
+    {   // clear the record-count group sums of this step's family tiles
+        uint64_t *sup = ghost ? d.supBg : d.supB;
+        const int64_t ng = (d.tileB[(int64_t)ghost * (B + 1) + B] + kSupGroup - 1) / kSupGroup;
+        for (int64_t g = tid; g < ng; g += kThreads) sup[g * kSupStride] = 0;
     }
     __syncthreads();
     block_plan(d.tileA + (int64_t)ghost * (B + 1), Ncur, B, kTileA);
