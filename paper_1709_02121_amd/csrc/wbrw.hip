@@ -33,7 +33,7 @@ struct Layout {
     size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
     size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, tileA = 0, Nsrt = 0, srtS = 0, tileB = 0, tileR = 0,
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
-           tcA = 0, tcAg = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, off = 0,
+           tcA = 0, tcAg = 0, supA = 0, supAg = 0, spart = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
            bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0, xitab = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
@@ -203,6 +203,8 @@ Layout make_layout(const wbrw_config *c)
     L.fpart = take(cur, (size_t)kMaxGrid * 8 * 8);
     L.rstart = take(cur, (size_t)L.rtiles * 8);
     L.tcA = take(cur, (size_t)L.tilesA * 8);
+    L.supA = take(cur, (size_t)(L.tilesA / kSupGroup + 1) * kSupStride * 8);
+    L.spart = take(cur, (size_t)kMaxGrid * 2 * 8);
     L.emA = take(cur, (size_t)L.tilesA * kPPT * 4 * 8);
     L.tcB = take(cur, (size_t)L.tilesB * 8);
     L.supB = take(cur, (size_t)(L.tilesB / kSupGroup + 1) * kSupStride * 8);
@@ -210,6 +212,7 @@ Layout make_layout(const wbrw_config *c)
     L.stg = take(cur, 2 * BB * 8);
     if (tan) {
         L.tcAg = take(cur, (size_t)L.tilesAg * 8);
+        L.supAg = take(cur, (size_t)(L.tilesAg / kSupGroup + 1) * kSupStride * 8);
         L.emAg = take(cur, (size_t)L.tilesAg * kPPT * 4 * 8);
         L.tcBg = take(cur, (size_t)L.tilesBg * 8);
         L.supBg = take(cur, (size_t)(L.tilesBg / kSupGroup + 1) * kSupStride * 8);
@@ -406,8 +409,7 @@ void enqueue_step_dim(wbrw_t h)
     stage_begin(h, WBRW_STAGE_STREAM);
     hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
-    hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 0);
-    hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
+    hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS] + 1), dim3(kThreads), 0, s, d, 0, h->grid[G_STREAM]);
     stage_begin(h, WBRW_STAGE_FAMILY);
     if (h->strategy == WBRW_SP2 && tan)
         hipLaunchKernelGGL((k_family<DIM, true, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
@@ -431,8 +433,7 @@ void enqueue_step_dim(wbrw_t h)
         // ghosts (weight 0) branch by the sp1 rule in either strategy
         stage_begin(h, WBRW_STAGE_GHOST);
         hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 1);
-        hipLaunchKernelGGL(k_close_stream, dim3(1), dim3(kThreads), 0, s, d, 1);
-        hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 1);
+        hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS] + 1), dim3(kThreads), 0, s, d, 1, h->grid[G_STREAM]);
         hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL((k_place_records<DIM, false, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 1, 1, h->grid[G_FAMILY]);
@@ -707,12 +708,15 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.ev_idx = at<uint32_t>(w, L.ev_idx);
     d.gev_idx = h->tangent ? at<uint32_t>(w, L.gev_idx) : nullptr;
     d.tcA = at<uint64_t>(w, L.tcA);
+    d.supA = at<uint64_t>(w, L.supA);
+    d.spart = at<int64_t>(w, L.spart);
     d.emA = at<uint64_t>(w, L.emA);
     d.tcB = at<uint64_t>(w, L.tcB);
     d.supB = at<uint64_t>(w, L.supB);
     d.tsB = at<int64_t>(w, L.tsB);
     d.stg = at<int64_t>(w, L.stg);
     d.tcAg = h->tangent ? at<uint64_t>(w, L.tcAg) : nullptr;
+    d.supAg = h->tangent ? at<uint64_t>(w, L.supAg) : nullptr;
     d.emAg = h->tangent ? at<uint64_t>(w, L.emAg) : nullptr;
     d.tcBg = h->tangent ? at<uint64_t>(w, L.tcBg) : nullptr;
     d.supBg = h->tangent ? at<uint64_t>(w, L.supBg) : nullptr;

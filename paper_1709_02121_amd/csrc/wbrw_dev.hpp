@@ -18,7 +18,7 @@ constexpr int kPPT = 8;                 // particles (or cells) per thread in st
 constexpr int kTileA = kThreads * kPPT; // particles per streaming tile
 constexpr int kTileB = kThreads;        // event-parents per family tile (the smallest; see fam_tile)
 constexpr int kTileS = kThreads * kPPT; // cells per scan tile
-constexpr int kSupGroup = 64;           // family tiles per record-count group sum
+constexpr int kSupGroup = 64;           // tiles per group sum of per-tile counts
 constexpr int kSupStride = 16;          // u64 slots between group sums (one per 128 B line)
 constexpr int kXcd = 8;                 // accelerator complexes (XCDs), each with its own L2
 constexpr int kTileR = kThreads * 4;    // regenerated particles per tile
@@ -129,7 +129,11 @@ struct Dev {
                                         // counts (entries kSupStride apart)
     int64_t *tsB, *tsBg;                // per family tile: where its records were staged
     int64_t *stg;                       // [2][B] staging fill of the inactive buffer sets
-    uint64_t *tcA, *tcAg;               // per streaming tile: event count, then its prefix
+    uint64_t *tcA, *tcAg;               // per streaming tile: event count
+    uint64_t *supA, *supAg;             // per kSupGroup streaming tiles: sum of their event
+                                        // counts (entries kSupStride apart)
+    int64_t *spart;                     // [kMaxGrid][2]: each streaming block's last
+                                        // instance and its events there
     uint64_t *emA, *emAg;               // per streaming tile: kPPT x 4 wavefront event ballots
     int64_t *Nsrt;              // [B] particles in cell order at the front of each instance
     int64_t *srtS;              // [B+1] prefix of floor(Nsrt[b] / kTileA)
@@ -171,6 +175,60 @@ __device__ __forceinline__ int segment_of(const int64_t *plan, int B, int64_t t)
         if (plan[mid] <= t) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Sum over tiles [a, c) of per-tile counts tc, with sup holding the sums of
+// whole groups of kSupGroup tiles (kSupStride apart): the tiles before the
+// first whole group, the group sums, the tiles after the last whole group.
+// Element e < n() of that list is load(e).
+struct TileRange {
+    const uint64_t *tc, *sup;
+    int64_t a, ga, gc, nh, ng, nt;
+    __device__ __forceinline__ TileRange(const uint64_t *tc_, const uint64_t *sup_, int64_t a_, int64_t c)
+        : tc(tc_), sup(sup_), a(a_)
+    {
+        ga = (a + kSupGroup - 1) / kSupGroup * kSupGroup;
+        gc = c / kSupGroup * kSupGroup;
+        const bool groups = ga <= gc;
+        nh = c <= a ? 0 : (groups ? ga - a : c - a);
+        ng = groups ? (gc - ga) / kSupGroup : 0;
+        nt = groups ? c - gc : 0;
+    }
+    __device__ __forceinline__ int64_t n() const { return nh + ng + nt; }
+    __device__ __forceinline__ uint64_t load(int64_t e) const
+    {
+        if (e < nh) return tc[a + e];
+        if (e < nh + ng) return sup[(ga / kSupGroup + (e - nh)) * kSupStride];
+        return tc[gc + (e - nh - ng)];
+    }
+};
+
+// TileRange sum for every lane of the wavefront
+__device__ __forceinline__ uint64_t wave_range_sum(const TileRange &R)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t v = 0;
+    for (int64_t e = lane; e < R.n(); e += 64) v += R.load(e);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// TileRange sum for every thread of the block (s_w: kThreads / 64 slots)
+__device__ __forceinline__ uint64_t block_range_sum(const TileRange &R, uint64_t *s_w)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint64_t v = 0;
+    for (int64_t e = tid; e < R.n(); e += kThreads) v += R.load(e);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) s_w[wv] = v;
+    __syncthreads();
+    uint64_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < kThreads / 64; ++q) tot += s_w[q];
+    __syncthreads();
+    return tot;
 }
 
 // ---- decoupled look-back (single-pass ordered scans) ----------------------

@@ -1,9 +1,9 @@
 // One time step of the Wigner branching random walk (Alg. 1, Sec. 2), after
 // the streaming pass (wbrw_stream.hpp):
 //
-// k_close_stream, k_events: the tiles' event counts are scanned by one block,
-// and every tile turns its wavefront ballots into the ordered list of event
-// parents (instance by instance, in particle order).
+// k_events: every tile turns its wavefront ballots into the ordered list of
+// event parents (instance by instance, in particle order), at an offset
+// taken from group sums of the tiles' event counts.
 //
 // k_family (latency-bound, ~3% of particles): one thread per event parent
 // walks the parent's whole family within the step, depth first: for each
@@ -95,55 +95,62 @@ __device__ __forceinline__ bool in_kbox(const Dev &d, const double *k)
 }
 
 
-// After k_stream (one block): exclusive scan of the tile event counts over
-// all tiles (in place), the event count of every instance, the family-tile
-// plan, cleared record counts and staging, and the particle-step tally.
-__global__ __launch_bounds__(kThreads) void k_close_stream(Dev d, int ghost)
+// After k_stream: the ordered event list.  Every streaming tile turns its
+// ballots into the within-instance indices of its event parents, at the
+// tile's offset in its instance's list (order: particle slot, wavefront,
+// lane, as in the particle array); the offset is the sum of the event counts
+// of the instance's earlier tiles, taken from the 64-tile group sums.  The
+// last block instead adds up the streaming blocks' per-instance event counts
+// and lays out the family tiles.
+__global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost, int sgrid)
 {
     const int B = d.B;
     const int tid = threadIdx.x;
-    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
-    const int64_t *Ncur = ghost ? d.NG : d.N;
-    uint64_t *tc = ghost ? d.tcAg : d.tcA;
-    int64_t *evc = d.evc + (int64_t)ghost * B;
-    const int64_t T = plan[B];
-    const uint64_t total = scan_tile_counts(tc, tc, T);
-    for (int b = tid; b < B; b += kThreads) {
-        const uint64_t lo = plan[b] < T ? tc[plan[b]] : total;
-        const uint64_t hi = plan[b + 1] < T ? tc[plan[b + 1]] : total;
-        evc[b] = (int64_t)(hi - lo);
+    if (blockIdx.x == gridDim.x - 1) {
+        constexpr int kLdsB = 512;
+        __shared__ int64_t s_ev[kLdsB];
+        int64_t *evc = d.evc + (int64_t)ghost * B;
+        const bool lds = B <= kLdsB;
+        if (lds)
+            for (int b = tid; b < B; b += kThreads) s_ev[b] = 0;
+        __syncthreads();
+        for (int g = tid; g < sgrid; g += kThreads) {
+            const int64_t cb = d.spart[2 * g], c = d.spart[2 * g + 1];
+            if (cb < 0 || c == 0) continue;
+            if (lds) atomicAdd((unsigned long long *)&s_ev[cb], (unsigned long long)c);
+            else atomicAdd((unsigned long long *)&evc[cb], (unsigned long long)c);
+        }
+        __syncthreads();
+        // evc already holds what k_stream's blocks added on changing instance
+        if (lds)
+            for (int b = tid; b < B; b += kThreads)
+                if (s_ev[b]) atomicAdd((unsigned long long *)&evc[b], (unsigned long long)s_ev[b]);
+        __syncthreads();
+        const int64_t ftile = ghost ? kTileB : fam_tile(d.dim, d.tangent != 0);
+        block_prefix(d.tileB + (int64_t)ghost * (B + 1), B, [&](int b) {
+            const int64_t e = (int64_t)__hip_atomic_load((unsigned long long *)&evc[b], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            return (e + ftile - 1) / ftile;
+        });
+        return;
     }
-    __syncthreads();
-    block_plan(d.tileB + (int64_t)ghost * (B + 1), evc, B, ghost ? kTileB : fam_tile(d.dim, d.tangent != 0));
-    for (int b = tid; b < B; b += kThreads) {
-        d.stg[(int64_t)ghost * B + b] = 0;
-        if (!ghost) d.tally[(int64_t)b * kTalCount + kTalPSteps] += Ncur[b];
-    }
-}
-
-// After k_close_stream: the ordered event list.  Every streaming tile turns
-// its ballots into the within-instance indices of its event parents, at the
-// tile's offset in its instance's list (order: particle slot, wavefront,
-// lane, as in the particle array).
-__global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost)
-{
     // One wavefront per streaming tile, so that every tile's loads are in
     // flight at once (the grid holds about as many wavefronts as tiles).
-    const int B = d.B;
     const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
     const int64_t ntiles = plan[B];
     const uint64_t *tc = ghost ? d.tcAg : d.tcA;
+    const uint64_t *sup = ghost ? d.supAg : d.supA;
     const uint64_t *emask = ghost ? d.emAg : d.emA;
     uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = tid & 63, wv = tid >> 6;
     constexpr int kWaves = kThreads / 64;
     static_assert(kPPT * 4 <= 64, "one lane per (particle slot, wavefront) ballot");
-    for (int64_t t = (int64_t)blockIdx.x * kWaves + wv; t < ntiles; t += (int64_t)gridDim.x * kWaves) {
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + wv; t < ntiles; t += (int64_t)(gridDim.x - 1) * kWaves) {
         const int b = segment_of(plan, B, t);
         const int64_t tl = t - plan[b];
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
-        const uint64_t rel = tc[t] - tc[plan[b]];
+        const uint64_t rel = wave_range_sum(TileRange(tc, sup, plan[b], t));
         // ballot q = j * 4 + w holds particle slot j of the streaming
         // kernel's wavefront w; exclusive scan of their popcounts in q order
         const uint64_t *em = emask + t * (kPPT * 4);
@@ -1334,35 +1341,6 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     if (err) atomicOr(&ctl->err, err);
 }
 
-// Sum of the record counts of family tiles [a, c) for every thread of the
-// block: the tiles before the first whole group of kSupGroup, the group sums,
-// and the tiles after the last whole group.
-__device__ __forceinline__ int64_t tile_range_sum(const uint64_t *tc, const uint64_t *sup, int64_t a,
-                                                  int64_t c, uint64_t *s_w)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t ga = (a + kSupGroup - 1) / kSupGroup * kSupGroup, gc = c / kSupGroup * kSupGroup;
-    const bool groups = ga <= gc;
-    const int64_t nh = c <= a ? 0 : (groups ? ga - a : c - a);
-    const int64_t ng = groups ? (gc - ga) / kSupGroup : 0;
-    const int64_t nt = groups ? c - gc : 0;
-    uint64_t v = 0;
-    for (int64_t e = tid; e < nh + ng + nt; e += kThreads) {
-        if (e < nh) v += tc[a + e];
-        else if (e < nh + ng) v += sup[(ga / kSupGroup + (e - nh)) * kSupStride];
-        else v += tc[gc + (e - nh - ng)];
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) s_w[wv] = v;
-    __syncthreads();
-    uint64_t tot = 0;
-#pragma unroll
-    for (int q = 0; q < kThreads / 64; ++q) tot += s_w[q];
-    __syncthreads();
-    return (int64_t)tot;
-}
-
 // Every family tile's staged records (contiguous in the inactive buffer set)
 // go to their place after the instance's particles: tile order, then the
 // order of the family walks within the tile.
@@ -1389,7 +1367,7 @@ __global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost)
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t cap = ghost ? P.gcap : P.cap;
         const int64_t n = (int64_t)tc[t], src = ts[t];
-        const int64_t dst = Ncur[b] + tile_range_sum(tc, sup, plan[b], t, s_w);
+        const int64_t dst = Ncur[b] + (int64_t)block_range_sum(TileRange(tc, sup, plan[b], t), s_w);
         for (int64_t r = threadIdx.x; r < n; r += kThreads) {
             if (src + r >= cap) break;                 // never staged (flagged by k_family)
             if (dst + r >= cap) { err |= kErrCapacity; break; }
@@ -1458,12 +1436,14 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
             T[kTalEventCap] += s_acc[3][b];
             if (s_acc[4][b] > T[kTalMaxDepth]) T[kTalMaxDepth] = s_acc[4][b];
         }
-    const int64_t *rec = d.stg + (int64_t)ghost * B;   // records of the step (staging fill)
+    int64_t *rec = d.stg + (int64_t)ghost * B;   // records of the step (staging fill)
     int64_t *evc = d.evc + (int64_t)ghost * B;
     for (int b = tid; b < B; b += kThreads) {
         const InstParam &P = d.ip[b];
         const int64_t cap = ghost ? P.gcap : P.cap;
+        if (!ghost) d.tally[(int64_t)b * kTalCount + kTalPSteps] += Ncur[b];
         int64_t n = Ncur[b] + rec[b];
+        rec[b] = 0;
         if (n > cap) {
             atomicOr(&ctl->err, kErrCapacity);
             n = cap;
@@ -1471,10 +1451,12 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
         Ncur[b] = n;
         evc[b] = 0;
     }
-    {   // clear the record-count group sums of this step's family tiles
-        uint64_t *sup = ghost ? d.supBg : d.supB;
-        const int64_t ng = (d.tileB[(int64_t)ghost * (B + 1) + B] + kSupGroup - 1) / kSupGroup;
-        for (int64_t g = tid; g < ng; g += kThreads) sup[g * kSupStride] = 0;
+    {   // clear the group sums of this step's streaming and family tiles
+        uint64_t *supA = ghost ? d.supAg : d.supA, *supB = ghost ? d.supBg : d.supB;
+        const int64_t na = (d.tileA[(int64_t)ghost * (B + 1) + B] + kSupGroup - 1) / kSupGroup;
+        const int64_t nb = (d.tileB[(int64_t)ghost * (B + 1) + B] + kSupGroup - 1) / kSupGroup;
+        for (int64_t g = tid; g < na; g += kThreads) supA[g * kSupStride] = 0;
+        for (int64_t g = tid; g < nb; g += kThreads) supB[g * kSupStride] = 0;
     }
     __syncthreads();
     block_plan(d.tileA + (int64_t)ghost * (B + 1), Ncur, B, kTileA);

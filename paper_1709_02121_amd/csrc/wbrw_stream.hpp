@@ -15,10 +15,12 @@ namespace wbrw {
 
 // ---------------------------------------------------------------------------
 // Pass 1: streaming clock test + free flight; the event flags of every tile
-// are kept as wavefront ballots, and the tile's event count is stored.
-// No tile waits for another: tiles are assigned statically and the ordered
-// event list is built by k_close_stream (scan of the tile counts) and
-// k_events (expansion of the ballots).
+// are kept as wavefront ballots, and the tile's event count is stored and
+// added to the sum of its group of kSupGroup tiles.  No tile waits for
+// another: tiles are assigned statically, and k_events builds the ordered
+// event list from the ballots.  Each block also counts its events per
+// instance: added to the instance's count when the block moves on to
+// another instance, left in the block's slot of spart at the end.
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
@@ -32,8 +34,12 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
     const int64_t *Ncur = ghost ? d.NG : d.N;
     const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
     uint64_t *tcnt = ghost ? d.tcAg : d.tcA;
+    uint64_t *tsup = ghost ? d.supAg : d.supA;
+    int64_t *evc = d.evc + (int64_t)ghost * B;
     uint64_t *emask = ghost ? d.emAg : d.emA;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int cb = -1;        // instance of the block's event count acc (thread 0)
+    uint64_t acc = 0;
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int b = segment_of(plan, B, t);
@@ -105,8 +111,22 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
         }
         if (lane == 0) s_wcnt[wv] = nev;
         __syncthreads();
-        if (tid == 0) tcnt[t] = (uint64_t)(s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3]);
+        if (tid == 0) {
+            const uint64_t c = (uint64_t)(s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3]);
+            tcnt[t] = c;
+            if (c) atomicAdd((unsigned long long *)&tsup[(t / kSupGroup) * kSupStride], (unsigned long long)c);
+            if (b != cb) {
+                if (cb >= 0 && acc) atomicAdd((unsigned long long *)&evc[cb], (unsigned long long)acc);
+                cb = b;
+                acc = 0;
+            }
+            acc += c;
+        }
         __syncthreads();
+    }
+    if (tid == 0) {
+        d.spart[2 * (int64_t)blockIdx.x] = cb;
+        d.spart[2 * (int64_t)blockIdx.x + 1] = (int64_t)acc;
     }
 }
 
