@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--forms", default="all",
+                    help="comma-separated forms to run besides the main line (default: all)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first copy 1 GiB device to device (a reference for HBM byte counters)")
     args = ap.parse_args()
@@ -237,6 +239,8 @@ def main():
                 ("fwd_adjoint_x0_deriv_pairs", lambda: W.differentiation(track_tangent=2), 50, 10),
                 ("fwd_adjoint_sp2", lambda: W.differentiation(strategy="sp2"), 50, 10),
                 ("helium_4d", lambda: W.helium_soft_coulomb(), 10, 0)):
+            if args.forms != "all" and name not in args.forms.split(","):
+                continue
             try:
                 torch.cuda.empty_cache()
                 batched = name == "batched_256"
