@@ -1397,9 +1397,25 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
 {
     Ctl *ctl = d.ctl;
     const int B = d.B;
-    const uint32_t step = ctl->step;
     int64_t *Ncur = ghost ? d.NG : d.N;
+    int64_t *rec = d.stg + (int64_t)ghost * B;   // records of the step (staging fill)
+    int64_t *evc = d.evc + (int64_t)ghost * B;
     const int tid = threadIdx.x;
+    // Loads that do not depend on the family blocks' tallies go first, so
+    // that their latency overlaps the reduction below; thread b < kThreads
+    // keeps instance b's values in registers.
+    const uint32_t step = ctl->step;
+    const int64_t tilesA = d.tileA[(int64_t)ghost * (B + 1) + B];
+    const int64_t tilesB = d.tileB[(int64_t)ghost * (B + 1) + B];
+    const bool own = tid < B;
+    int64_t n_own = 0, rec_own = 0, cap_own = 0, tal_own[kTalCount] = {};
+    if (own) {
+        n_own = Ncur[tid];
+        rec_own = rec[tid];
+        cap_own = ghost ? d.ip[tid].gcap : d.ip[tid].cap;
+#pragma unroll
+        for (int q = 0; q < kTalCount; ++q) tal_own[q] = d.tally[(int64_t)tid * kTalCount + q];
+    }
     // the family blocks' last tallies, summed per instance in LDS when the
     // instances fit (global atomics from one block on one line serialise)
     constexpr int kLdsB = 512;
@@ -1427,39 +1443,48 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
         }
     }
     __syncthreads();
-    if (lds)
-        for (int b = tid; b < B; b += kThreads) {
-            int64_t *T = d.tally + (int64_t)b * kTalCount;
-            T[kTalEvents] += s_acc[0][b];
-            T[kTalPairs] += s_acc[1][b];
-            T[kTalKilled] += s_acc[2][b];
-            T[kTalEventCap] += s_acc[3][b];
-            if (s_acc[4][b] > T[kTalMaxDepth]) T[kTalMaxDepth] = s_acc[4][b];
-        }
-    int64_t *rec = d.stg + (int64_t)ghost * B;   // records of the step (staging fill)
-    int64_t *evc = d.evc + (int64_t)ghost * B;
+    int64_t n_next = 0;   // instance tid's count for the next step
     for (int b = tid; b < B; b += kThreads) {
-        const InstParam &P = d.ip[b];
-        const int64_t cap = ghost ? P.gcap : P.cap;
-        if (!ghost) d.tally[(int64_t)b * kTalCount + kTalPSteps] += Ncur[b];
-        int64_t n = Ncur[b] + rec[b];
+        const bool mine = b == tid;
+        int64_t *T = d.tally + (int64_t)b * kTalCount;
+        if (lds) {   // (the global path above already added its atomics)
+            const int64_t ev = mine ? tal_own[kTalEvents] : T[kTalEvents];
+            const int64_t pr = mine ? tal_own[kTalPairs] : T[kTalPairs];
+            const int64_t kl = mine ? tal_own[kTalKilled] : T[kTalKilled];
+            const int64_t ec = mine ? tal_own[kTalEventCap] : T[kTalEventCap];
+            const int64_t md = mine ? tal_own[kTalMaxDepth] : T[kTalMaxDepth];
+            T[kTalEvents] = ev + s_acc[0][b];
+            T[kTalPairs] = pr + s_acc[1][b];
+            T[kTalKilled] = kl + s_acc[2][b];
+            T[kTalEventCap] = ec + s_acc[3][b];
+            if (s_acc[4][b] > md) T[kTalMaxDepth] = s_acc[4][b];
+        }
+        const int64_t n0 = mine ? n_own : Ncur[b];
+        const int64_t cap = mine ? cap_own : (ghost ? d.ip[b].gcap : d.ip[b].cap);
+        if (!ghost) T[kTalPSteps] = (mine ? tal_own[kTalPSteps] : T[kTalPSteps]) + n0;
+        int64_t n = n0 + (mine ? rec_own : rec[b]);
         rec[b] = 0;
         if (n > cap) {
             atomicOr(&ctl->err, kErrCapacity);
             n = cap;
         }
         Ncur[b] = n;
+        if (mine) n_next = n;
         evc[b] = 0;
     }
     {   // clear the group sums of this step's streaming and family tiles
         uint64_t *supA = ghost ? d.supAg : d.supA, *supB = ghost ? d.supBg : d.supB;
-        const int64_t na = (d.tileA[(int64_t)ghost * (B + 1) + B] + kSupGroup - 1) / kSupGroup;
-        const int64_t nb = (d.tileB[(int64_t)ghost * (B + 1) + B] + kSupGroup - 1) / kSupGroup;
+        const int64_t na = (tilesA + kSupGroup - 1) / kSupGroup, nb = (tilesB + kSupGroup - 1) / kSupGroup;
         for (int64_t g = tid; g < na; g += kThreads) supA[g * kSupStride] = 0;
         for (int64_t g = tid; g < nb; g += kThreads) supB[g * kSupStride] = 0;
     }
     __syncthreads();
-    block_plan(d.tileA + (int64_t)ghost * (B + 1), Ncur, B, kTileA);
+    // the next step's tile plan (block_prefix evaluates instance b on thread
+    // b mod kThreads, which wrote Ncur[b] above)
+    block_prefix(d.tileA + (int64_t)ghost * (B + 1), B, [&](int b) {
+        const int64_t n = b == tid ? n_next : Ncur[b];
+        return (n + kTileA - 1) / kTileA;
+    });
     if (tid == 0 && advance) ctl->step = step + 1u;
 }
 
