@@ -594,7 +594,7 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
     const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
     const double *X = (axis == 1) ? E.x1 : E.x0;
     const int64_t ds = ghost ? d.gcap_total : d.cap_total;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int width = TAN ? 3 * nbins : nbins;
     const bool priv = width <= kLds;
     if (priv)
@@ -660,20 +660,36 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
                     atomicAdd(&acc[2 * d.max_bins + bin], t2);
                 }
             } else {
-                // sp1: a wavefront's sign sum fits 32 bits (half the shuffles)
-                int64_t v = 0;
+                uint64_t *acc = priv ? s_raw : (uint64_t *)d.dacc + (int64_t)b * d.max_bins;
                 if (SP2) {
-                    if (bin >= 0) v = (int64_t)(wv[j] * 4294967296.0);
+                    int64_t v = bin >= 0 ? (int64_t)(wv[j] * 4294967296.0) : 0;
                     v = run_sum<int64_t>(bin, v, commit);
-                } else {
-                    v = run_sum<int32_t>(bin, bin >= 0 ? (int32_t)wv[j] : 0, commit);
+                    if (commit && v != 0) atomicAdd((unsigned long long *)&acc[bin], (unsigned long long)v);
+                    continue;
                 }
-                if (!commit || v == 0) continue;
-                if (priv)
-                    atomicAdd((unsigned long long *)&s_raw[bin], (unsigned long long)v);
-                else
-                    atomicAdd((unsigned long long *)&d.dacc[(int64_t)b * d.max_bins + bin],
-                              (unsigned long long)v);
+                // sp1 signs are +-1: a run of equal bins across the wavefront
+                // sums to (# plus) - (# minus) of its lanes.  A wavefront with
+                // few runs (the cell-ordered front) commits one atomic per run;
+                // one with many (scattered offspring) adds lane by lane.
+                const int key = (int)bin;
+                const int sgn = bin >= 0 ? (int)wv[j] : 0;
+                const uint64_t plus = __ballot(sgn > 0), minus = __ballot(sgn < 0);
+                const int prev = __shfl_up(key, 1, 64);
+                const uint64_t heads = __ballot(lane == 0 || key != prev);
+                if (__popcll(heads) > 8) {
+                    if (sgn != 0) atomicAdd((unsigned long long *)&acc[bin], (unsigned long long)(int64_t)sgn);
+                    continue;
+                }
+                for (uint64_t hm = heads; hm != 0ull;) {
+                    const int h = __builtin_ctzll(hm);
+                    hm &= hm - 1ull;
+                    const uint64_t upto = hm ? ((1ull << __builtin_ctzll(hm)) - 1ull) : ~0ull;
+                    const uint64_t seg = upto & ~((1ull << h) - 1ull);
+                    const int v = __popcll(plus & seg) - __popcll(minus & seg);
+                    const int kh = __builtin_amdgcn_readlane(key, h);
+                    if (lane == h && kh >= 0 && v != 0)
+                        atomicAdd((unsigned long long *)&acc[kh], (unsigned long long)(int64_t)v);
+                }
             }
         }
     }
