@@ -511,6 +511,10 @@ __global__ __launch_bounds__(kThreads) void k_regen(Dev d)
     const int64_t ntiles = d.tileR[B];
     const Ens O = pick_set(d, 0, ctl->cur ^ 1u);
     const int tid = threadIdx.x;
+    // the offsets of a tile's cells, staged in LDS when they fit, so that the
+    // searches below cost LDS rather than dependent global loads
+    constexpr int kCells = 2048;
+    __shared__ int64_t s_off[kCells];
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         __syncthreads();
         const int b = segment_of(d.tileR, B, t);
@@ -524,11 +528,28 @@ __global__ __launch_bounds__(kThreads) void k_regen(Dev d)
         const int64_t q = t - d.tileR[b];
         const int64_t nu_lo = d.rstart[P.rbase + q];
         const int64_t nu_hi = (q + 1) * kTileR < nout ? d.rstart[P.rbase + q + 1] : d.Nh - 1;
+        const int64_t span = nu_hi - nu_lo + 1;
+        const bool staged = span <= kCells;
+        if (staged)
+            for (int c = tid; c < (int)span; c += kThreads) s_off[c] = off[nu_lo + c];
+        __syncthreads();
+#pragma unroll
         for (int j = 0; j < kTileR / kThreads; ++j) {
             const int64_t o = q * kTileR + (int64_t)j * kThreads + tid;
-            if (o >= nout) break;
-            const int64_t nu = cell_of_output(off, nu_lo, nu_hi, o);
-            const int64_t onu = off[nu];
+            if (o >= nout) continue;
+            int64_t nu, onu;
+            if (staged) {
+                int lo = 0, hi = (int)span - 1;   // the last staged cell with offset <= o
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((s_off[mid] & kOffMask) <= o) lo = mid; else hi = mid - 1;
+                }
+                nu = nu_lo + lo;
+                onu = s_off[lo];
+            } else {
+                nu = cell_of_output(off, nu_lo, nu_hi, o);
+                onu = off[nu];
+            }
             const int64_t jj = o - (onu & kOffMask);
             const uint64_t id = ((uint64_t)nu << 32) | (uint64_t)jj;
             double x[2] = {0.0, 0.0}, k[2] = {0.0, 0.0};
