@@ -127,6 +127,22 @@ def test_batched_equals_oracle(P, O):
     assert np.array_equal(dg[1:], dr[1:])
 
 
+def test_xcd_count_grids_and_cost_split(P, O):
+    """A coarse 40 x 32 grid under instances of 1e4 particles switches on the
+    per-XCD count grids of the binning pass (7 B N_h <= sum N0); after the
+    first annihilation the binning split weighs the cell-ordered front of
+    every instance against the offspring appended since."""
+    grid = dict(W.gaussian_barrier_small()["grid"], nx=40, nk=32)
+    cfg = W.batched_barriers(B=3, N0=np.array([12000, 2049, 20000], dtype=np.int64), grid=grid)
+    assert 7 * 3 * 40 * 32 <= int(cfg["N0"].sum())
+    say("xcd count grids: B=3, 40 x 32 grid")
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.run(35, 10)
+    r.run(35, 10)
+    compare(g, r, "xcd grids", B=3)
+    assert np.array_equal(g.density().cpu().numpy(), r.density())
+
+
 def test_helium_4d_parity(P, O):
     cfg = W.helium_soft_coulomb(N0=np.array([6000]))
     cfg["grid"] = {"x_lo": -10.0, "x_hi": 10.0, "nx": 24, "k_lo": -4.0, "k_hi": 4.0, "nk": 24}
