@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kThreads) void k_hist_round(Dev d, const double *hi
 // Binning cost of the particle tiles before instance b (see kBinLateCost).
 __device__ __forceinline__ int64_t bin_cost_before(const Dev &d, const int64_t *plan, int b)
 {
-    return kBinLateCost * plan[b] - (kBinLateCost - 1) * d.srtS[b];
+    return kBinLateCost * plan[b] - (kBinLateCost - kBinSortedCost) * d.srtS[b];
 }
 
 // The first particle tile whose cost prefix reaches c, or the tile count
@@ -184,8 +184,11 @@ __device__ __forceinline__ int64_t tile_at_cost(const Dev &d, const int64_t *pla
     }
     const int64_t r = c - bin_cost_before(d, plan, lo);
     const int64_t srt = d.srtS[lo + 1] - d.srtS[lo];
-    // cost before tile l of the instance: l up to srt, then srt + kBinLateCost (l - srt)
-    return plan[lo] + (r <= srt ? r : srt + (r - srt + kBinLateCost - 1) / kBinLateCost);
+    // cost before tile l of the instance: kBinSortedCost l up to srt, then
+    // kBinSortedCost srt + kBinLateCost (l - srt)
+    const int64_t rs = kBinSortedCost * srt;
+    return plan[lo] + (r <= rs ? (r + kBinSortedCost - 1) / kBinSortedCost
+                               : srt + (r - rs + kBinLateCost - 1) / kBinLateCost);
 }
 
 template <int DIM, bool SP2, bool TAN>

@@ -446,14 +446,14 @@ __device__ __forceinline__ void block_plan(int64_t *plan, const int64_t *cnt, in
     block_prefix(plan, B, [&](int b) { return (cnt[b] + tile - 1) / tile; });
 }
 
-// Cost of binning a streaming tile: 1 inside the cell-ordered front of its
-// instance (the first Nsrt[b] particles, as the last regeneration left
-// them), kBinLateCost after it, where the offspring appended since then
-// scatter over many more cells per tile.  With srtS[b] = sum_{b' < b}
-// floor(Nsrt[b'] / kTileA), the cost of the tiles before instance b is
-// kBinLateCost tileA[b] - (kBinLateCost - 1) srtS[b]; it needs N[b] >=
-// Nsrt[b], which holds because steps only append.
-constexpr int64_t kBinLateCost = 3;
+// Cost of binning a streaming tile: kBinSortedCost inside the cell-ordered
+// front of its instance (the first Nsrt[b] particles, as the last
+// regeneration left them), kBinLateCost after it, where the offspring
+// appended since then scatter over many more cells per tile.  With srtS[b] =
+// sum_{b' < b} floor(Nsrt[b'] / kTileA), the cost of the tiles before
+// instance b is kBinLateCost tileA[b] - (kBinLateCost - kBinSortedCost)
+// srtS[b]; it needs N[b] >= Nsrt[b], which holds because steps only append.
+constexpr int64_t kBinSortedCost = 1, kBinLateCost = 3;
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 {
