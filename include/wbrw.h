@@ -177,8 +177,9 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes,
               void *hip_stream, wbrw_t *out);
 
 /* Advances every instance by nsteps time steps (Alg. 1 between t_l and
- * t_{l+1} = t_l + dt; Sec. 2).  Enqueues 2 kernels per step (4 with tangents);
- * no host synchronisation. */
+ * t_{l+1} = t_l + dt; Sec. 2).  Enqueues 5 kernels per step (streaming, event
+ * list, families, record placement, one-block bookkeeping; 10 with tangents,
+ * whose ghosts take a second such pass); no host synchronisation. */
 int wbrw_step(wbrw_t h, int32_t nsteps);
 
 /* Annihilation (Sec. 4.3): particles outside the grid are removed (escaped
