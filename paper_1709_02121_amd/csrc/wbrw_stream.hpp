@@ -99,14 +99,16 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
             evbits |= (ev ? 1u : 0u) << j;
         }
         // free flight to the end of the step; an event parent keeps its
-        // start position, which its family walk needs, and k_family moves it
+        // start position, which its family walk needs, and k_family moves it.
+        // The positions are not read again in this launch: non-temporal
+        // stores keep them from displacing cached lines.
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const int64_t li = li0 + (int64_t)j * kThreads;
             if ((full || li < n) && !((evbits >> j) & 1u)) {
                 const int64_t i = base + li;
-                E.x0[i] = xs0[j] + (d.vfac * kv0[j]) * d.dt;
-                if (DIM == 2) E.x1[i] = xs1[j] + (d.vfac * kv1[j]) * d.dt;
+                __builtin_nontemporal_store(xs0[j] + (d.vfac * kv0[j]) * d.dt, &E.x0[i]);
+                if (DIM == 2) __builtin_nontemporal_store(xs1[j] + (d.vfac * kv1[j]) * d.dt, &E.x1[i]);
             }
         }
         if (lane == 0) s_wcnt[wv] = nev;
