@@ -557,13 +557,18 @@ __global__ __launch_bounds__(kThreads) void k_regen(Dev d)
             const uint64_t id = ((uint64_t)nu << 32) | (uint64_t)jj;
             double x[2] = {0.0, 0.0}, k[2] = {0.0, 0.0};
             cell_point<DIM>(d, nu, id, kTagRegen, step, P.key, x, k);
+            // the ensemble is read again only by the next launches: its
+            // writes bypass the caches (non-temporal)
             const int64_t i = P.base + o;
-            O.x0[i] = x[0];
-            O.k0[i] = k[0];
-            if (DIM == 2) { O.x1[i] = x[1]; O.k1[i] = k[1]; }
+            __builtin_nontemporal_store(x[0], &O.x0[i]);
+            __builtin_nontemporal_store(k[0], &O.k0[i]);
+            if (DIM == 2) {
+                __builtin_nontemporal_store(x[1], &O.x1[i]);
+                __builtin_nontemporal_store(k[1], &O.k1[i]);
+            }
             const bool neg = (onu & kOffNeg) != 0;
             if (SP2) O.w[i] = neg ? -1.0 : 1.0; else O.sg[i] = neg ? (int8_t)-1 : (int8_t)1;
-            O.id[i] = id;
+            __builtin_nontemporal_store(id, &O.id[i]);
             if (TAN) {
                 const int64_t nxt = (nu + 1 < d.Nh) ? (off[nu + 1] & kOffMask) : nout;
                 const double an = (double)(nxt - (onu & kOffMask));
