@@ -42,6 +42,13 @@ __device__ __forceinline__ void st128(uint64_t *p, u128 v)
     p[1] = (uint64_t)(v >> 64);
 }
 
+// st128 past the caches, for data that only a later launch reads
+__device__ __forceinline__ void st128_nt(uint64_t *p, u128 v)
+{
+    __builtin_nontemporal_store((uint64_t)v, p);
+    __builtin_nontemporal_store((uint64_t)(v >> 64), p + 1);
+}
+
 __device__ __forceinline__ u128 ld128(const uint64_t *p)
 {
     return ((u128)p[1] << 64) | (u128)p[0];
@@ -414,8 +421,8 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
             for (int c = 0; c < 2; ++c)
                 pc[c] = tb[c] + (((u128)s_hi[c][j * kW + wv] << 64) | s_lo[c][j * kW + wv]) +
                         (((u128)ehi[c][j] << 64) | elo[c][j]);
-            st128(d.bP + 2 * i, pc[0]);
-            st128(d.bP + 2 * C + 2 * i, pc[1]);
+            st128_nt(d.bP + 2 * i, pc[0]);
+            st128_nt(d.bP + 2 * C + 2 * i, pc[1]);
         }
     }
 }
