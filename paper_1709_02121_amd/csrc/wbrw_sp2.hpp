@@ -114,14 +114,26 @@ __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
         }
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
+        const int64_t li0 = (t - plan[b]) * kTileA + tid;
+        double wv[kPPT], xa[kPPT], xb[kPPT], ka[kPPT], kb[kPPT];
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {      // loads first: kPPT in flight per thread
+            const int64_t li = li0 + (int64_t)j * kThreads;
+            const int64_t i = P.base + (li < n ? li : 0);
+            wv[j] = E.w[i];
+            xa[j] = E.x0[i];
+            ka[j] = E.k0[i];
+            xb[j] = DIM == 2 ? E.x1[i] : 0.0;
+            kb[j] = DIM == 2 ? E.k1[i] : 0.0;
+        }
+#pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            const int64_t li = li0 + (int64_t)j * kThreads;
             if (li >= n) continue;
             const int64_t i = P.base + li;
-            const double w = E.w[i];
+            const double w = wv[j];
             const uint64_t A = (uint64_t)floor(fabs(w) * 4294967296.0);
-            const int64_t nu = cell_index<DIM>(d, E.x0[i], DIM == 2 ? E.x1[i] : 0.0, E.k0[i],
-                                               DIM == 2 ? E.k1[i] : 0.0);
+            const int64_t nu = cell_index<DIM>(d, xa[j], xb[j], ka[j], kb[j]);
             int8_t cls = -1;
             if (nu < 0) {
                 acc[4] += w < 0.0 ? (unsigned long long)(-(long long)A) : (unsigned long long)A;
@@ -180,6 +192,19 @@ __global__ __launch_bounds__(kThreads) void k_sp2_close_classify(Dev d, int grid
 // Each block takes a contiguous run of tiles; the kept-copy sums per class
 // are summed per instance and left in fpart (instance changes, rare, add to
 // the counters) for k_sp2_tilescan.  The 128-bit residual sums are per tile.
+// floor(num / den) for num < 2^63, den > 0: a double-precision estimate,
+// exact to within one when the quotient is below 2^40, corrected with
+// integer arithmetic; larger quotients take the integer division.
+__device__ __forceinline__ uint64_t udiv_floor(uint64_t num, uint64_t den)
+{
+    uint64_t q = (uint64_t)((double)num / (double)den);
+    if (q >= (1ull << 40)) return num / den;
+    const u128 p = (u128)q * den;
+    if (p > (u128)num) --q;
+    else if ((u128)num - p >= (u128)den) ++q;
+    return q;
+}
+
 __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
 {
     __shared__ unsigned long long s_acc[4];    // tile sums (lo,hi) x 2
@@ -224,15 +249,26 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
         const uint64_t Nc[2] = {(uint64_t)st[kBN0], (uint64_t)st[kBN1]};
         const uint64_t Sc[2] = {(uint64_t)st[kBS0], (uint64_t)st[kBS1]};
         u128 rs[2] = {0, 0};
+        const int64_t li0 = (t - plan[b]) * kTileA + tid;
+        int8_t cv[kPPT];
+        uint64_t av[kPPT];
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {      // loads first: kPPT in flight per thread
+            const int64_t li = li0 + (int64_t)j * kThreads;
+            const int64_t i = P.base + (li < n ? li : 0);
+            cv[j] = d.bcls[i];
+            av[j] = d.bA[i];
+        }
+#pragma unroll
         for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
+            const int64_t li = li0 + (int64_t)j * kThreads;
             if (li >= n) continue;
             const int64_t i = P.base + li;
-            const int8_t c = d.bcls[i];
+            const int8_t c = cv[j];
             uint64_t k = 0, r = 0;
             if (c >= 0 && Sc[c] > 0) {
-                const uint64_t num = Nc[c] * d.bA[i];       // < 2^63
-                k = num / Sc[c];
+                const uint64_t num = Nc[c] * av[j];       // < 2^63
+                k = udiv_floor(num, Sc[c]);
                 r = num - k * Sc[c];
                 ks[c] += k;
                 rs[c] += r;
