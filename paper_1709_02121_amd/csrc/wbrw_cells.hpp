@@ -775,16 +775,30 @@ __global__ __launch_bounds__(kThreads) void k_vjp(Dev d, int ghost, int nbins, d
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t n = Ncur[b];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = (t - plan[b]) * kTileA + (int64_t)j * kThreads + tid;
-            if (li >= n) continue;
-            const int64_t i = base + li;
-            const double q = (E.x0[i] - lo) / dxb;
-            if (!(q >= 0.0 && q < (double)nbins)) continue;
-            const double gv = g[(int64_t)b * nbins + (int64_t)q];
-            a0 += E.D[i] * gv;
-            a1 += E.D[ds + i] * gv;
-            a2 += E.D[2 * ds + i] * gv;
+        const int64_t li0 = (t - plan[b]) * kTileA + tid;
+        double xv[kPPT], d0[kPPT], d1[kPPT], d2[kPPT], gv[kPPT];
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {      // loads first: kPPT in flight per thread
+            const int64_t li = li0 + (int64_t)j * kThreads;
+            const int64_t i = base + (li < n ? li : 0);
+            xv[j] = E.x0[i];
+            d0[j] = E.D[i];
+            d1[j] = E.D[ds + i];
+            d2[j] = E.D[2 * ds + i];
+        }
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {      // then the bins' cotangents
+            const double q = (xv[j] - lo) / dxb;
+            const bool in = li0 + (int64_t)j * kThreads < n && q >= 0.0 && q < (double)nbins;
+            gv[j] = in ? g[(int64_t)b * nbins + (int64_t)q] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) {      // accumulated in slot order
+            const double q = (xv[j] - lo) / dxb;
+            if (li0 + (int64_t)j * kThreads >= n || !(q >= 0.0 && q < (double)nbins)) continue;
+            a0 += d0[j] * gv[j];
+            a1 += d1[j] * gv[j];
+            a2 += d2[j] * gv[j];
         }
         for (int o = 32; o > 0; o >>= 1) {
             a0 += __shfl_down(a0, o, 64);
