@@ -300,10 +300,79 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
 
 // ---- stage 3: exclusive scan of the tile sums per instance and class; the
 // draw counts N_r and the draw-tile plan.  One block per instance. ----------
+// Exclusive scan of the 128-bit values v[t0..t1) in place, by one block.
+// Chunks of kThreads x 8 values are loaded coalesced (all loads in flight)
+// into LDS, padded by one slot per 8 so that the per-thread runs fall in
+// different banks; every thread sums its run of 8, the run sums are scanned
+// within each wavefront (64-bit halves with carry) and across the four
+// wavefronts, and the prefixes leave LDS coalesced.
+__device__ __forceinline__ void scan_u128_exclusive(uint64_t *v, int64_t t0, int64_t t1)
+{
+    constexpr int P = 8, C = kThreads * P, W = kThreads / 64;
+    __shared__ uint64_t s_lo[C + C / P], s_hi[C + C / P];
+    __shared__ uint64_t s_wlo[W], s_whi[W];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int run0 = tid * (P + 1);
+    u128 carry = 0;
+    for (int64_t c0 = t0; c0 < t1; c0 += C) {
+        const int n = (int)min((int64_t)C, t1 - c0);
+        __syncthreads();
+        u128 x[P];
+#pragma unroll
+        for (int r = 0; r < P; ++r)   // clamped, unconditional: no branch between the loads
+            x[r] = ld128(v + 2 * (c0 + min(r * kThreads + tid, n - 1)));
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const int i = r * kThreads + tid;
+            s_lo[i + i / P] = (uint64_t)x[r];
+            s_hi[i + i / P] = (uint64_t)(x[r] >> 64);
+        }
+        __syncthreads();
+        u128 acc = 0;
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            x[r] = tid * P + r < n ? (((u128)s_hi[run0 + r] << 64) | s_lo[run0 + r]) : (u128)0;
+            acc += x[r];
+        }
+        uint64_t lo = (uint64_t)acc, hi = (uint64_t)(acc >> 64);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t plo = __shfl_up(lo, o, 64), phi = __shfl_up(hi, o, 64);
+            if (lane >= o) {
+                const uint64_t nlo = lo + plo;
+                hi = hi + phi + (nlo < lo ? 1ull : 0ull);
+                lo = nlo;
+            }
+        }
+        if (lane == 63) { s_wlo[wv] = lo; s_whi[wv] = hi; }
+        __syncthreads();
+        u128 below = 0, chunk = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const u128 t = ((u128)s_whi[w] << 64) | s_wlo[w];
+            if (w < wv) below += t;
+            chunk += t;
+        }
+        u128 run = carry + below + ((((u128)hi << 64) | lo) - acc);
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            s_lo[run0 + r] = (uint64_t)run;
+            s_hi[run0 + r] = (uint64_t)(run >> 64);
+            run += x[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const int i = r * kThreads + tid;
+            if (i < n) st128(v + 2 * (c0 + i), ((u128)s_hi[i + i / P] << 64) | s_lo[i + i / P]);
+        }
+        carry += chunk;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kThreads) void k_sp2_tilescan(Dev d, int rgrid)
 {
-    __shared__ uint64_t s_lo[kThreads], s_hi[kThreads];
-    __shared__ uint64_t s_clo, s_chi;
     __shared__ unsigned long long s_w[kThreads / 64];
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -324,34 +393,8 @@ __global__ __launch_bounds__(kThreads) void k_sp2_tilescan(Dev d, int rgrid)
             d.bcls_stat[(int64_t)b * 8 + kBK1] += (int64_t)k1;
         }
         const int64_t t0 = d.tileA[b], t1 = d.tileA[b + 1];
-        for (int c = 0; c < 2; ++c) {
-            uint64_t *ts = d.bTile + 2 * ((int64_t)c * d.tstride);
-            if (tid == 0) { s_clo = 0; s_chi = 0; }
-            __syncthreads();
-            for (int64_t c0 = t0; c0 < t1; c0 += kThreads) {
-                const int64_t t = c0 + tid;
-                u128 v = (t < t1) ? ld128(ts + 2 * t) : (u128)0;
-                // inclusive Hillis-Steele scan in LDS
-                s_lo[tid] = (uint64_t)v;
-                s_hi[tid] = (uint64_t)(v >> 64);
-                __syncthreads();
-                for (int o = 1; o < kThreads; o <<= 1) {
-                    u128 add = 0;
-                    if (tid >= o) add = ((u128)s_hi[tid - o] << 64) | s_lo[tid - o];
-                    __syncthreads();
-                    const u128 cur = (((u128)s_hi[tid] << 64) | s_lo[tid]) + add;
-                    s_lo[tid] = (uint64_t)cur;
-                    s_hi[tid] = (uint64_t)(cur >> 64);
-                    __syncthreads();
-                }
-                const u128 carry = ((u128)s_chi << 64) | s_clo;
-                const u128 incl = (((u128)s_hi[tid] << 64) | s_lo[tid]) + carry;
-                if (t < t1) st128(ts + 2 * t, incl - v);   // exclusive
-                __syncthreads();
-                if (tid == kThreads - 1) { s_clo = (uint64_t)incl; s_chi = (uint64_t)(incl >> 64); }
-                __syncthreads();
-            }
-        }
+        for (int c = 0; c < 2; ++c)
+            scan_u128_exclusive(d.bTile + 2 * ((int64_t)c * d.tstride), t0, t1);
         if (tid == 0) {
             int64_t *st = d.bcls_stat + (int64_t)b * 8;
             st[kBNr0] = st[kBN0] - st[kBK0];
