@@ -115,13 +115,14 @@ int validate(const wbrw_config *c)
     return WBRW_OK;
 }
 
-// Plain sp1 binning adds its counts into one grid per XCD, so that the
-// atomics of an XCD's blocks stay in that XCD's L2; the scan folds the copies
+// Plain sp1 binning (and the sp2 bootstrap's per-class counting) adds its
+// counts into one grid per XCD, so that the atomics of an XCD's blocks stay
+// in that XCD's L2; the scan (sp2: the rounding pass) folds the copies
 // together.  Worth it while the extra grids (read once per annihilation) are
 // small beside the ensemble that is binned.
 bool xcd_counts(const wbrw_config *c)
 {
-    if (c->strategy == WBRW_SP2 || c->track_tangent != 0) return false;
+    if (c->strategy != WBRW_SP2 && c->track_tangent != 0) return false;
     const int64_t nh = c->dim == 1 ? (int64_t)c->nx * c->nk : (int64_t)c->nx * c->nx * (int64_t)c->nk * c->nk;
     int64_t n0 = 0;
     for (int b = 0; b < c->n_instances; ++b) n0 += c->N0[b];
@@ -221,7 +222,7 @@ Layout make_layout(const wbrw_config *c)
     }
     L.stS = take(cur, (size_t)L.tilesS * 8);
     L.cnt = take(cur, BB * Nh * 4);
-    if (xcd_counts(c)) L.cntx = take(cur, (size_t)(kXcd - 1) * BB * Nh * 4);
+    if (xcd_counts(c)) L.cntx = take(cur, (size_t)(kXcd - 1) * (sp2 ? 2 : 1) * BB * Nh * 4);
     if (tan) {
         L.occ = take(cur, BB * Nh * 4);
         L.Tcell = take(cur, 3 * BB * Nh * 8);

@@ -358,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_sums(Dev d)
         const int64_t tl = t - (int64_t)b * tiles_per;
         const int64_t cbase = (int64_t)b * d.Nh;
         uint64_t sum = 0;
-        if (d.cntx == nullptr) {
+        if (d.cntx == nullptr || d.strategy == WBRW_SP2) {
 #pragma unroll
             for (int j = 0; j < kPPT; ++j) {      // lanes take consecutive cells
                 const int64_t c = tl * kTileS + (int64_t)j * kThreads + tid;

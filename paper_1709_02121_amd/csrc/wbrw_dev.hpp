@@ -138,8 +138,9 @@ struct Dev {
     int64_t *Nsrt;              // [B] particles in cell order at the front of each instance
     int64_t *srtS;              // [B+1] prefix of floor(Nsrt[b] / kTileA)
     int32_t *cnt;               // [B][Nh] signed counts (sp1) / rounded counts (sp2)
-    int32_t *cntx;              // [kXcd - 1][B][Nh] partial sp1 counts of the blocks on the
-                                // other XCDs (cnt is copy 0); null when not used
+    int32_t *cntx;              // partial counts of the blocks on the other XCDs (copy 0
+                                // is the grid itself): sp1 [kXcd - 1][B][Nh] of cnt, sp2
+                                // [kXcd - 1][2][B][Nh] of ntil; null when not used
     int64_t *off;               // [B][Nh] exclusive prefix of |n_nu|, bit 62 = negative cell
     int32_t *occ;               // [B][Nh] occupancy (tangents)
     double *Tcell;              // [3][B][Nh] tangent sums per cell

@@ -561,6 +561,10 @@ __global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
     const int64_t ntiles = plan[B];
     const int tid = threadIdx.x;
     const int64_t plane = (int64_t)B * d.Nh;
+    // this block's XCD copy of the two class grids (blocks are dealt to the
+    // XCDs round robin; any other placement is still correct)
+    const int xc = (int)(blockIdx.x % kXcd);
+    int32_t *const tg = (d.cntx == nullptr || xc == 0) ? d.ntil : d.cntx + (int64_t)(xc - 1) * 2 * plane;
     for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
     if (tid == 0) s_nkeys = 0;
     // key = 2 cell + class (N_h < 2^30)
@@ -569,15 +573,17 @@ __global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
             const int k = s_key[j];
             if (k < 0) continue;
             const int v = s_val[j];
-            if (v != 0) atomicAdd(&d.ntil[(int64_t)(k & 1) * plane + (int64_t)fb * d.Nh + (k >> 1)], v);
+            if (v != 0) atomicAdd(&tg[(int64_t)(k & 1) * plane + (int64_t)fb * d.Nh + (k >> 1)], v);
             s_key[j] = -1;
             s_val[j] = 0;
         }
         if (tid == 0) s_nkeys = 0;
         __syncthreads();
     };
-    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-    const int64_t t0 = min((int64_t)blockIdx.x * per, ntiles), t1 = min(t0 + per, ntiles);
+    // an equal share of the binning cost (see kBinLateCost) per block
+    const int64_t W = bin_cost_before(d, plan, B);
+    const int64_t t0 = tile_at_cost(d, plan, (W * blockIdx.x + gridDim.x - 1) / gridDim.x);
+    const int64_t t1 = tile_at_cost(d, plan, (W * (blockIdx.x + 1) + gridDim.x - 1) / gridDim.x);
     int cb = -1;
     for (int64_t t = t0; t < t1; ++t) {
         __syncthreads();
@@ -619,7 +625,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
                     done = true;
                 }
             }
-            if (!done) atomicAdd(&d.ntil[(int64_t)cl[j] * plane + (int64_t)b * d.Nh + cell[j]], cp[j]);
+            if (!done) atomicAdd(&tg[(int64_t)cl[j] * plane + (int64_t)b * d.Nh + cell[j]], cp[j]);
         }
     }
     __syncthreads();
@@ -636,7 +642,22 @@ __global__ __launch_bounds__(kThreads) void k_sp2_round(Dev d)
     for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < plane;
          g += (int64_t)gridDim.x * kThreads) {
         const int64_t b = g / d.Nh, nu = g - b * d.Nh;
-        const int32_t n0 = d.ntil[g], n1 = d.ntil[plane + g];
+        int32_t n0 = d.ntil[g], n1 = d.ntil[plane + g];
+        if (d.cntx) {   // fold the XCD copies of the class counts and clear them
+            int32_t p0[kXcd - 1], p1[kXcd - 1];
+#pragma unroll
+            for (int x = 0; x < kXcd - 1; ++x) {
+                p0[x] = d.cntx[(int64_t)x * 2 * plane + g];
+                p1[x] = d.cntx[(int64_t)x * 2 * plane + plane + g];
+            }
+#pragma unroll
+            for (int x = 0; x < kXcd - 1; ++x) {
+                n0 += p0[x];
+                n1 += p1[x];
+                if (p0[x]) d.cntx[(int64_t)x * 2 * plane + g] = 0;
+                if (p1[x]) d.cntx[(int64_t)x * 2 * plane + plane + g] = 0;
+            }
+        }
         if (n0 == 0 && n1 == 0) continue;
         d.ntil[g] = 0;
         d.ntil[plane + g] = 0;
