@@ -437,6 +437,11 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
         const int64_t li0 = (t - plan[b]) * kTileA + tid;
+        // the tile's base prefixes are needed only at the end: loaded first,
+        // their latency hides behind the scans
+        u128 tb[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) tb[c] = ld128(d.bTile + 2 * ((int64_t)c * d.tstride + t));
         uint64_t r[kPPT];
         int8_t cl[kPPT];
 #pragma unroll
@@ -487,9 +492,6 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
             }
         }
         __syncthreads();
-        u128 tb[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) tb[c] = ld128(d.bTile + 2 * ((int64_t)c * d.tstride + t));
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const int64_t li = li0 + (int64_t)j * kThreads;
