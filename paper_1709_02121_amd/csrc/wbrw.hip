@@ -33,7 +33,7 @@ struct Layout {
     size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
     size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, tileA = 0, Nsrt = 0, srtS = 0, tileB = 0, tileR = 0,
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
-           tcA = 0, tcAg = 0, supA = 0, supAg = 0, spart = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, off = 0,
+           tcA = 0, tcAg = 0, supA = 0, supAg = 0, spart = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, occx = 0, Tcellx = 0, off = 0,
            occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
            bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0, xitab = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
@@ -122,7 +122,7 @@ int validate(const wbrw_config *c)
 // small beside the ensemble that is binned.
 bool xcd_counts(const wbrw_config *c)
 {
-    if (c->strategy != WBRW_SP2 && c->track_tangent != 0) return false;
+    if (c->strategy == WBRW_SP2 && c->track_tangent != 0) return false;
     const int64_t nh = c->dim == 1 ? (int64_t)c->nx * c->nk : (int64_t)c->nx * c->nx * (int64_t)c->nk * c->nk;
     int64_t n0 = 0;
     for (int b = 0; b < c->n_instances; ++b) n0 += c->N0[b];
@@ -226,6 +226,10 @@ Layout make_layout(const wbrw_config *c)
     if (tan) {
         L.occ = take(cur, BB * Nh * 4);
         L.Tcell = take(cur, 3 * BB * Nh * 8);
+        if (L.cntx && !sp2) {
+            L.occx = take(cur, (size_t)(kXcd - 1) * BB * Nh * 4);
+            L.Tcellx = take(cur, (size_t)(kXcd - 1) * 3 * BB * Nh * 8);
+        }
         L.dTacc = take(cur, 3 * BB * MB * 8);
     }
     if (sp2) {
@@ -488,6 +492,7 @@ int enqueue_annihilate_dim(wbrw_t h)
         stage_begin(h, WBRW_STAGE_BIN);
         hipLaunchKernelGGL((k_bin<DIM, false, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
         hipLaunchKernelGGL((k_bin<DIM, false, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 1);
+        if (d.occx) hipLaunchKernelGGL(k_fold_tangents, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d);
         stage_end(h);
         stage_begin(h, WBRW_STAGE_SCAN);
         enqueue_scan(h->grid[G_SCAN], s, d, 0);
@@ -729,6 +734,8 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.off = at<int64_t>(w, L.off);
     d.occ = h->tangent ? at<int32_t>(w, L.occ) : nullptr;
     d.Tcell = h->tangent ? at<double>(w, L.Tcell) : nullptr;
+    d.occx = L.occx ? at<int32_t>(w, L.occx) : nullptr;
+    d.Tcellx = L.Tcellx ? at<double>(w, L.Tcellx) : nullptr;
     d.dTacc = h->tangent ? at<double>(w, L.dTacc) : nullptr;
     d.dacc = at<int64_t>(w, L.dacc);
     if (h->strategy == WBRW_SP2) {

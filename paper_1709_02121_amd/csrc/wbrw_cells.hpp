@@ -217,8 +217,11 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     // plain sp1: this block's XCD copy of the count grid (blocks are dealt
     // to the XCDs round robin; any other placement is still correct)
     const int xc = (int)(blockIdx.x % kXcd);
-    int32_t *const cg = (TAN || d.cntx == nullptr || xc == 0) ? d.cnt
-                        : d.cntx + (int64_t)(xc - 1) * d.Nh * B;
+    const int64_t ncell = d.Nh * (int64_t)B;
+    const bool own = d.cntx == nullptr || xc == 0 || (TAN && d.occx == nullptr);
+    int32_t *const cg = own ? d.cnt : d.cntx + (int64_t)(xc - 1) * ncell;
+    int32_t *const og = own ? d.occ : d.occx + (int64_t)(xc - 1) * ncell;
+    double *const tg = own ? d.Tcell : d.Tcellx + (int64_t)(xc - 1) * 3 * ncell;
     if (!TAN)
         for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
     if (tid == 0) { s_esc = 0; s_nkeys = 0; }
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 bool commit;
                 if (!ghost && !SP2) {   // sp2's cell counts come from the bootstrap
                     const int ns = run_sum<int>(nu, nu >= 0 ? s : 0, commit);
-                    if (commit && ns != 0) atomicAdd(&d.cnt[cbase + nu], ns);
+                    if (commit && ns != 0) atomicAdd(&cg[cbase + nu], ns);
                 }
                 const bool in = nu >= 0;
                 const int64_t ds = ghost ? d.gcap_total : d.cap_total;
@@ -322,11 +325,10 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 const double t1 = run_sum<double>(nu, in ? E.D[ds + i] : 0.0, commit);
                 const double t2 = run_sum<double>(nu, in ? E.D[2 * ds + i] : 0.0, commit);
                 if (commit) {
-                    const int64_t nc = d.Nh * (int64_t)B;
-                    atomicAdd(&d.occ[cbase + nu], no);
-                    atomicAdd(&d.Tcell[cbase + nu], t0);
-                    atomicAdd(&d.Tcell[nc + cbase + nu], t1);
-                    atomicAdd(&d.Tcell[2 * nc + cbase + nu], t2);
+                    atomicAdd(&og[cbase + nu], no);
+                    atomicAdd(&tg[cbase + nu], t0);
+                    atomicAdd(&tg[ncell + cbase + nu], t1);
+                    atomicAdd(&tg[2 * ncell + cbase + nu], t2);
                 }
             }
         }
@@ -400,6 +402,39 @@ __global__ __launch_bounds__(kThreads) void k_scan_sums(Dev d)
             d.stS[t] = tot;
         }
         __syncthreads();
+    }
+}
+
+// sp1 with tangents: the XCD copies of the occupancy and tangent sums are
+// added into occ and Tcell (in copy order) and cleared.
+__global__ __launch_bounds__(kThreads) void k_fold_tangents(Dev d)
+{
+    const int64_t nc = d.Nh * (int64_t)d.B;
+    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < nc; g += (int64_t)gridDim.x * kThreads) {
+        int32_t po[kXcd - 1];
+#pragma unroll
+        for (int x = 0; x < kXcd - 1; ++x) po[x] = d.occx[(int64_t)x * nc + g];
+        int32_t o = d.occ[g];
+        double tv[3] = {d.Tcell[g], d.Tcell[nc + g], d.Tcell[2 * nc + g]};
+        bool any = false;
+        for (int x = 0; x < kXcd - 1; ++x) {
+            if (po[x] == 0) continue;   // a copy that saw no particle here holds no sums
+            const int64_t tx = (int64_t)x * 3 * nc + g;
+            o += po[x];
+            d.occx[(int64_t)x * nc + g] = 0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                tv[q] += d.Tcellx[tx + q * nc];
+                d.Tcellx[tx + q * nc] = 0.0;
+            }
+            any = true;
+        }
+        if (any) {
+            d.occ[g] = o;
+            d.Tcell[g] = tv[0];
+            d.Tcell[nc + g] = tv[1];
+            d.Tcell[2 * nc + g] = tv[2];
+        }
     }
 }
 
