@@ -238,7 +238,7 @@ Layout make_layout(const wbrw_config *c)
         L.tileD = take(cur, 2 * (BB + 1) * 8);
         L.bscan_tiles = take(cur, (BB + 1) * 8);
     }
-    L.dacc = take(cur, BB * MB * 8);
+    L.dacc = take(cur, kXcd * BB * MB * 8);   // one accumulator per XCD
     L.vjp = take(cur, BB * 3 * 8);
     L.zero_end = (cur + kAlign - 1) / kAlign * kAlign;
     L.total = L.zero_end;

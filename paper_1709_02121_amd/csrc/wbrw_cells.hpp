@@ -659,6 +659,8 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
     const double *X = (axis == 1) ? E.x1 : E.x0;
     const int64_t ds = ghost ? d.gcap_total : d.cap_total;
     const int tid = threadIdx.x, lane = tid & 63;
+    // this block's XCD copy of the accumulator (atomics stay in its L2)
+    int64_t *const dx = d.dacc + (int64_t)(blockIdx.x % kXcd) * B * d.max_bins;
     const int width = TAN ? 3 * nbins : nbins;
     const bool priv = width <= kLds;
     if (priv)
@@ -675,7 +677,7 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
                 const int c = j / nbins, bin = j - c * nbins;
                 atomicAdd(d.dTacc + (int64_t)fb * 3 * d.max_bins + (int64_t)c * d.max_bins + bin, f);
             } else {
-                atomicAdd((unsigned long long *)&d.dacc[(int64_t)fb * d.max_bins + j], (unsigned long long)v);
+                atomicAdd((unsigned long long *)&dx[(int64_t)fb * d.max_bins + j], (unsigned long long)v);
             }
         }
         __syncthreads();
@@ -724,7 +726,7 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
                     atomicAdd(&acc[2 * d.max_bins + bin], t2);
                 }
             } else {
-                uint64_t *acc = priv ? s_raw : (uint64_t *)d.dacc + (int64_t)b * d.max_bins;
+                uint64_t *acc = priv ? s_raw : (uint64_t *)dx + (int64_t)b * d.max_bins;
                 if (SP2) {
                     int64_t v = bin >= 0 ? (int64_t)(wv[j] * 4294967296.0) : 0;
                     v = run_sum<int64_t>(bin, v, commit);
@@ -778,11 +780,16 @@ __global__ __launch_bounds__(kThreads) void k_density_out(Dev d, int nbins, doub
             out[g] = *acc / denom;
             *acc = 0.0;
         } else {
-            int64_t *acc = d.dacc + b * d.max_bins + j;
-            double v = (double)*acc;
+            // the XCD copies, summed in copy order (exact integers) and cleared
+            int64_t sum = 0;
+            for (int x = 0; x < kXcd; ++x) {
+                int64_t *acc = d.dacc + ((int64_t)x * B + b) * d.max_bins + j;
+                sum += *acc;
+                *acc = 0;
+            }
+            double v = (double)sum;
             if (SP2) v = v * 0x1p-32;
             out[g] = v / denom;
-            *acc = 0;
         }
     }
 }

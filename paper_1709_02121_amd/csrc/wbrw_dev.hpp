@@ -147,7 +147,8 @@ struct Dev {
     int32_t *occx;              // sp1 with tangents: [kXcd - 1][B][Nh] XCD copies of occ,
     double *Tcellx;             // and [kXcd - 1][3][B][Nh] of Tcell (see cntx); else null
     int32_t *ntil;              // [2][B][Nh] sp2 bootstrap counts per class
-    int64_t *dacc;              // [B][max_bins] density accumulator
+    int64_t *dacc;              // [kXcd][B][max_bins] density accumulator, one per XCD
+                                // (a block flushes into copy blockIdx mod kXcd)
     double *dTacc;              // [B][3][max_bins] tangent density accumulator
     int32_t max_bins;
     // sp2 bootstrap scratch
