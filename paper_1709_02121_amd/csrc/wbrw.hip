@@ -122,7 +122,6 @@ int validate(const wbrw_config *c)
 // small beside the ensemble that is binned.
 bool xcd_counts(const wbrw_config *c)
 {
-    if (c->strategy == WBRW_SP2 && c->track_tangent != 0) return false;
     const int64_t nh = c->dim == 1 ? (int64_t)c->nx * c->nk : (int64_t)c->nx * c->nx * (int64_t)c->nk * c->nk;
     int64_t n0 = 0;
     for (int b = 0; b < c->n_instances; ++b) n0 += c->N0[b];
@@ -226,7 +225,7 @@ Layout make_layout(const wbrw_config *c)
     if (tan) {
         L.occ = take(cur, BB * Nh * 4);
         L.Tcell = take(cur, 3 * BB * Nh * 8);
-        if (L.cntx && !sp2) {
+        if (L.cntx) {
             L.occx = take(cur, (size_t)(kXcd - 1) * BB * Nh * 4);
             L.Tcellx = take(cur, (size_t)(kXcd - 1) * 3 * BB * Nh * 8);
         }
@@ -465,6 +464,7 @@ int enqueue_annihilate_dim(wbrw_t h)
             stage_begin(h, WBRW_STAGE_BIN);
             hipLaunchKernelGGL((k_bin<DIM, true, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
             hipLaunchKernelGGL((k_bin<DIM, true, true>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 1);
+            if (d.occx) hipLaunchKernelGGL(k_fold_tangents, dim3(h->grid[G_SCAN]), dim3(kThreads), 0, s, d);
             stage_end(h);
         }
         stage_begin(h, WBRW_STAGE_BOOTSTRAP);

@@ -405,8 +405,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_sums(Dev d)
     }
 }
 
-// sp1 with tangents: the XCD copies of the occupancy and tangent sums are
-// added into occ and Tcell (in copy order) and cleared.
+// With tangents: the XCD copies of the occupancy and tangent sums are added
+// into occ and Tcell (in copy order) and cleared.
 __global__ __launch_bounds__(kThreads) void k_fold_tangents(Dev d)
 {
     const int64_t nc = d.Nh * (int64_t)d.B;

@@ -144,7 +144,7 @@ struct Dev {
     int64_t *off;               // [B][Nh] exclusive prefix of |n_nu|, bit 62 = negative cell
     int32_t *occ;               // [B][Nh] occupancy (tangents)
     double *Tcell;              // [3][B][Nh] tangent sums per cell
-    int32_t *occx;              // sp1 with tangents: [kXcd - 1][B][Nh] XCD copies of occ,
+    int32_t *occx;              // with tangents: [kXcd - 1][B][Nh] XCD copies of occ,
     double *Tcellx;             // and [kXcd - 1][3][B][Nh] of Tcell (see cntx); else null
     int32_t *ntil;              // [2][B][Nh] sp2 bootstrap counts per class
     int64_t *dacc;              // [kXcd][B][max_bins] density accumulator, one per XCD
