@@ -1367,25 +1367,53 @@ __global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost)
         const int64_t base = ghost ? P.gbase : P.base;
         const int64_t cap = ghost ? P.gcap : P.cap;
         const int64_t n = (int64_t)tc[t], src = ts[t];
-        const int64_t dst = Ncur[b] + (int64_t)block_range_sum(TileRange(tc, sup, plan[b], t), s_w);
-        for (int64_t r = threadIdx.x; r < n; r += kThreads) {
-            if (src + r >= cap) break;                 // never staged (flagged by k_family)
-            if (dst + r >= cap) { err |= kErrCapacity; break; }
-            const int64_t i = base + src + r, o = base + dst + r;
-            E.x0[o] = S.x0[i];
-            E.k0[o] = S.k0[i];
+        // a record staged past the capacity was never written (k_family
+        // flagged it); one whose place is past the capacity is an overflow
+        struct Rec { double x0, x1, k0, k1, w, D[3]; uint64_t id; int8_t sg; };
+        auto load = [&](int64_t r) {
+            Rec q;
+            const int64_t i = base + src + r;
+            q.x0 = S.x0[i];
+            q.k0 = S.k0[i];
+            q.x1 = DIM == 2 ? S.x1[i] : 0.0;
+            q.k1 = DIM == 2 ? S.k1[i] : 0.0;
+            q.w = SP2 ? S.w[i] : 0.0;
+            q.sg = SP2 ? (int8_t)0 : S.sg[i];
+            q.id = S.id[i];
+            for (int c = 0; c < 3; ++c) q.D[c] = TAN ? S.D[c * dstride + i] : 0.0;
+            return q;
+        };
+        auto store = [&](int64_t r, const Rec &q, int64_t dst) {
+            if (dst + r >= cap) { err |= kErrCapacity; return; }
+            const int64_t o = base + dst + r;
+            E.x0[o] = q.x0;
+            E.k0[o] = q.k0;
             if (DIM == 2) {
-                E.x1[o] = S.x1[i];
-                E.k1[o] = S.k1[i];
+                E.x1[o] = q.x1;
+                E.k1[o] = q.k1;
             }
-            if (SP2) E.w[o] = S.w[i]; else E.sg[o] = S.sg[i];
-            E.id[o] = S.id[i];
-            if (TAN) {
-                E.D[o] = S.D[i];
-                E.D[dstride + o] = S.D[dstride + i];
-                E.D[2 * dstride + o] = S.D[2 * dstride + i];
-            }
+            if (SP2) E.w[o] = q.w; else E.sg[o] = q.sg;
+            E.id[o] = q.id;
+            if (TAN)
+                for (int c = 0; c < 3; ++c) E.D[c * dstride + o] = q.D[c];
+        };
+        // the first records of the tile are loaded before the tile's place
+        // is summed, so that the two overlap
+        constexpr int kPre = 4;
+        Rec pre[kPre];
+#pragma unroll
+        for (int h = 0; h < kPre; ++h) {
+            const int64_t r = threadIdx.x + (int64_t)h * kThreads;
+            if (r < n && src + r < cap) pre[h] = load(r);
         }
+        const int64_t dst = Ncur[b] + (int64_t)block_range_sum(TileRange(tc, sup, plan[b], t), s_w);
+#pragma unroll
+        for (int h = 0; h < kPre; ++h) {
+            const int64_t r = threadIdx.x + (int64_t)h * kThreads;
+            if (r < n && src + r < cap) store(r, pre[h], dst);
+        }
+        for (int64_t r = threadIdx.x + (int64_t)kPre * kThreads; r < n && src + r < cap; r += kThreads)
+            store(r, load(r), dst);
     }
     if (err) atomicOr(&ctl->err, err);
 }
