@@ -150,11 +150,12 @@ __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost, int sgrid
         const int64_t tl = t - plan[b];
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
-        const uint64_t rel = wave_range_sum(TileRange(tc, sup, plan[b], t));
         // ballot q = j * 4 + w holds particle slot j of the streaming
-        // kernel's wavefront w; exclusive scan of their popcounts in q order
+        // kernel's wavefront w (loaded before the offset sum, to overlap it);
+        // exclusive scan of their popcounts in q order
         const uint64_t *em = emask + t * (kPPT * 4);
         const uint64_t mine = lane < kPPT * 4 ? em[lane] : 0ull;
+        const uint64_t rel = wave_range_sum(TileRange(tc, sup, plan[b], t));
         const uint32_t c = (uint32_t)__popcll(mine);
         uint32_t inc = c;
 #pragma unroll
