@@ -368,28 +368,33 @@ __global__ __launch_bounds__(kThreads) void k_scan_sums(Dev d)
                 sum += (uint64_t)(v < 0 ? -v : v);
             }
         } else {
-            // fold the XCD copies of the sp1 counts into cnt and clear them
+            // fold the XCD copies of the sp1 counts into cnt and clear them;
+            // every cell's loads are issued before any is used
             const int64_t nc = d.Nh * B;
-#pragma unroll 2
+            int32_t v[kPPT], part[kPPT][kXcd - 1];
+#pragma unroll
+            for (int j = 0; j < kPPT; ++j) {
+                const int64_t c = min(tl * kTileS + (int64_t)j * kThreads + tid, d.Nh - 1);
+                v[j] = d.cnt[cbase + c];
+#pragma unroll
+                for (int x = 0; x < kXcd - 1; ++x) part[j][x] = d.cntx[(int64_t)x * nc + cbase + c];
+            }
+#pragma unroll
             for (int j = 0; j < kPPT; ++j) {
                 const int64_t c = tl * kTileS + (int64_t)j * kThreads + tid;
                 if (c >= d.Nh) continue;
                 const int64_t g = cbase + c;
-                int32_t part[kXcd - 1];
-#pragma unroll
-                for (int x = 0; x < kXcd - 1; ++x) part[x] = d.cntx[(int64_t)x * nc + g];
-                int32_t v = d.cnt[g];
                 bool moved = false;
 #pragma unroll
                 for (int x = 0; x < kXcd - 1; ++x) {
-                    v += part[x];
-                    if (part[x] != 0) {
+                    v[j] += part[j][x];
+                    if (part[j][x] != 0) {
                         d.cntx[(int64_t)x * nc + g] = 0;
                         moved = true;
                     }
                 }
-                if (moved) d.cnt[g] = v;
-                sum += (uint64_t)(v < 0 ? -v : v);
+                if (moved) d.cnt[g] = v[j];
+                sum += (uint64_t)(v[j] < 0 ? -v[j] : v[j]);
             }
         }
 #pragma unroll
