@@ -105,6 +105,8 @@ def lib():
                                           C.c_uint32, vp]
         L.orc_round_cell64.restype = C.c_int64
         L.orc_round_cell64.argtypes = [C.c_uint64] * 4 + [C.c_uint32] * 3 + [C.c_uint64]
+        L.orc_keep_cells.argtypes = [vp, C.c_int]
+        L.orc_get_cells.argtypes = [vp, C.c_int, vp, vp, vp]
         L.orc_probe_jump.argtypes = [vp, C.c_int, C.c_int, vp, C.c_uint64, C.c_uint32,
                                      vp, vp, vp]
         _lib = L
@@ -218,6 +220,8 @@ class OracleSim:
             c.init_hist = hist.ctypes.data_as(C.POINTER(C.c_double))
         self._c = c
         self.h = lib().orc_create(C.byref(c))
+        if not self.h:
+            raise ValueError("oracle refused the configuration (pair probability above 1)")
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -289,6 +293,18 @@ class OracleSim:
         st = Stats()
         lib().orc_get_stats(self.h, b, C.byref(st))
         return st.as_dict()
+
+    def keep_cells(self, on=True):
+        """Test hook: keep each later sp2 annihilation's per-cell arrays."""
+        lib().orc_keep_cells(self.h, int(on))
+
+    def cells(self, b=0):
+        """(n~+, n~-, n_nu) of the last sp2 annihilation kept by keep_cells."""
+        g = self.cfg["grid"]
+        nc = (int(g["nx"]) * int(g["nk"])) ** int(self.cfg["dim"])
+        out = [np.zeros(nc, dtype=np.int64) for _ in range(3)]
+        lib().orc_get_cells(self.h, b, *(_ptr(a) for a in out))
+        return tuple(out)
 
     def gamma0(self, b=0):
         return lib().orc_get_gamma0(self.h, b)

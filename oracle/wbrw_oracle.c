@@ -343,6 +343,8 @@ typedef struct {
     uint32_t step;          /* number of completed steps */
     double vfac;            /* hbar / mass */
     int ghost_pass;         /* stepping the ghost ensemble (sp1 branching rule) */
+    int keep_cells;         /* test hook: keep the last sp2 annihilation's cell arrays */
+    int64_t *kept[3];       /* [B][N_h] each: n~+, n~-, rounded signed count n_nu */
 } orc_sim;
 
 /* ------------------------------------------------------------------------ */
@@ -446,6 +448,7 @@ static void init_instance(orc_sim *S, int b)
 }
 
 static void init_from_histogram(orc_sim *S, int b);
+void orc_destroy(orc_sim *S);
 
 orc_sim *orc_create(const orc_config *cfg)
 {
@@ -464,6 +467,25 @@ orc_sim *orc_create(const orc_config *cfg)
     S->I = (inst_t *)calloc((size_t)cfg->B, sizeof(inst_t));
     for (int b = 0; b < cfg->B; b++) {
         setup_instance(S, b);
+        /* The sp1 box reads xi_m |sin| / (2 gamma0) as a probability and the
+         * wp box uses it as a weight factor; both need it <= 1 (Remark 3,
+         * gamma0 >= xi/2).  A configuration that breaks this is refused. */
+        const inst_t *I = &S->I[b];
+        int bad = !(I->gamma0 > 0.0);
+        for (int m = 0; m < cfg->M; m++) {
+            if (!(I->c[m] <= 1.0)) bad = 1;
+            if (cfg->time_dependent && cfg->comp_kind[m] == KIND_GAUSS) {
+                double xmax = (2.0 * (fabs(I->H[m]) * (fabs(cfg->mod_a[m]) + fabs(cfg->mod_b[m])))) / cfg->hbar;
+                if (xmax > 2.0 * I->gamma0 * (1.0 + 1e-12)) bad = 1;
+            }
+        }
+        if (bad) {
+            S->cfg.B = b + 1;
+            orc_destroy(S);
+            return NULL;
+        }
+    }
+    for (int b = 0; b < cfg->B; b++) {
         if (cfg->init_kind == 1) init_from_histogram(S, b);
         else init_instance(S, b);
     }
@@ -479,6 +501,7 @@ void orc_destroy(orc_sim *S)
         for (int m = 0; m < ORC_MAXM; m++) free(S->I[b].xi_tab[m]);
     }
     for (int m = 0; m < ORC_MAXM; m++) free(S->cum[m]);
+    for (int c = 0; c < 3; c++) free(S->kept[c]);
     free(S->I);
     free(S);
 }
@@ -1142,6 +1165,14 @@ static void annihilate_sp2(orc_sim *S, inst_t *I)
         int64_t m = orc_round_cell(an, den, S->cfg.seed, I->key_inst, S->step, (uint64_t)nu);
         cnt[nu] = num < 0 ? -m : m;
     }
+    if (S->keep_cells) {   /* test hook: the bootstrap counts and the rounded cell values */
+        int64_t off = (int64_t)(I - S->I) * nc;
+        for (int64_t nu = 0; nu < nc; nu++) {
+            S->kept[0][off + nu] = ntil[0][nu];
+            S->kept[1][off + nu] = ntil[1][nu];
+            S->kept[2][off + nu] = cnt[nu];
+        }
+    }
     /* tangents: the cell sums of Eq. boostrap_histogram's expectation,
      * sum of w_i, are differentiated directly: T_nu = sum of D_i over the
      * particles and ghosts in the cell, as in sp1 */
@@ -1298,6 +1329,28 @@ void orc_get_stats(const orc_sim *S, int b, orc_stats *out)
     }
     st.step = S->step;
     *out = st;
+}
+
+/* Test hook: keep, from now on, each sp2 annihilation's per-cell bootstrap
+ * counts n~+_nu, n~-_nu and rounded signed cell counts n_nu, readable with
+ * orc_get_cells ([N_h] int64 each for instance b). */
+void orc_keep_cells(orc_sim *S, int on)
+{
+    S->keep_cells = on;
+    if (on && !S->kept[0]) {
+        size_t n = (size_t)S->cfg.B * (size_t)n_cells(S);
+        for (int c = 0; c < 3; c++) S->kept[c] = (int64_t *)calloc(n, sizeof(int64_t));
+    }
+}
+
+void orc_get_cells(const orc_sim *S, int b, int64_t *nplus, int64_t *nminus, int64_t *cnt)
+{
+    int64_t nc = n_cells(S);
+    for (int64_t nu = 0; nu < nc; nu++) {
+        nplus[nu] = S->kept[0] ? S->kept[0][(int64_t)b * nc + nu] : 0;
+        nminus[nu] = S->kept[1] ? S->kept[1][(int64_t)b * nc + nu] : 0;
+        cnt[nu] = S->kept[2] ? S->kept[2][(int64_t)b * nc + nu] : 0;
+    }
 }
 
 uint32_t orc_get_step(const orc_sim *S) { return S->step; }

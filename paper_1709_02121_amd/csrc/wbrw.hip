@@ -6,6 +6,7 @@
 // allocates device memory and never synchronises except where the ABI says so.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -107,6 +108,40 @@ int validate(const wbrw_config *c)
     }
     for (int b = 0; b < c->n_instances; ++b) {
         if (c->N0[b] < 0 || c->capacity[b] < c->N0[b] || c->capacity[b] >= (1ll << 31)) return WBRW_EINVAL;
+    }
+    // The pair probability xi_m |sin| / (2 gamma0) of the sp1 box (and the wp
+    // weight factor) must stay <= 1 (Remark 3: gamma0 >= xi_m / 2).  The
+    // normalisers and gamma0 are computed exactly as derive() does.
+    {
+        double xi_t[kMaxM] = {};
+        for (int m = 0; m < c->n_components; ++m) {
+            const wbrw_component &q = c->comp[m];
+            if (q.kind != WBRW_KERNEL_TABLE) continue;
+            double cum = 0.0;
+            for (int j = 0; j < q.table_n; ++j) cum = cum + q.table[j];
+            const double dq = (q.q_hi - q.q_lo) / (double)q.table_n;
+            xi_t[m] = ((2.0 * cum) * dq) / (0x1.921fb54442d18p+1 * c->hbar);
+        }
+        for (int b = 0; b < c->n_instances; ++b) {
+            double g = 0.0, xi[kMaxM] = {};
+            for (int m = 0; m < c->n_components; ++m) {
+                const wbrw_component &q = c->comp[m];
+                if (q.kind == WBRW_KERNEL_GAUSSIAN) {
+                    xi[m] = (2.0 * std::fabs(q.H[b])) / c->hbar;
+                    if (q.modulated) {
+                        const double xmax = (2.0 * (std::fabs(q.H[b]) * (std::fabs(q.mod_a) + std::fabs(q.mod_b)))) / c->hbar;
+                        if (xmax > g) g = xmax;
+                    }
+                } else {
+                    xi[m] = xi_t[m];
+                }
+                if (xi[m] > g) g = xi[m];
+            }
+            const double g0 = (c->gamma0 > 0.0) ? c->gamma0 : c->gamma_scale * (g / 2.0);
+            if (!(g0 > 0.0) || !std::isfinite(g0)) return WBRW_EINVAL;
+            for (int m = 0; m < c->n_components; ++m)
+                if (!(xi[m] / (2.0 * g0) <= 1.0)) return WBRW_EINVAL;
+        }
     }
     const int64_t nh = c->dim == 1 ? (int64_t)c->nx * c->nk
                                    : (int64_t)c->nx * c->nx * (int64_t)c->nk * c->nk;
@@ -1076,10 +1111,16 @@ int wbrw_restore(wbrw_t h, const void *src, size_t bytes)
     int rc = copy_fields(h, 0, (char *)p, N, false, 0u, cur);
     if (!rc && h->tangent) rc = copy_fields(h, 1, (char *)p, NG, false, 0u, cur);
     if (rc) return rc;
+    // The look-back status words of k_ghosts carry the annihilation count as
+    // their epoch, and words written by this handle before the restore stay
+    // in the workspace: the count continues past every epoch the handle has
+    // used (never rewound to the snapshot's), so no stale word can match.
+    Ctl now;
+    HIPCHK(hipMemcpy(&now, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
     Ctl c;
     std::memset(&c, 0, sizeof(c));
     c.step = hd.ctl.step;
-    c.ann_seq = hd.ctl.ann_seq;
+    c.ann_seq = std::max(now.ann_seq, hd.ctl.ann_seq) + 1u;
     std::vector<int64_t> plan, gplan;
     plan_host(plan, N.data(), h->B, kTileA);
     plan_host(gplan, NG.data(), h->B, kTileA);

@@ -98,6 +98,38 @@ def test_invalid_configs_rejected(lib):
         assert e.value.code == P.EINVAL
 
 
+def _pair_probability_above_one():
+    """Configurations whose pair probability xi |sin| / (2 gamma0) can pass 1."""
+    out = []
+    c = W.gaussian_barrier_small(gamma0=0.2); out.append(("given gamma0 below xi/2", c))   # H = 0.3
+    c = W.gaussian_barrier_small(gamma_scale=0.9); out.append(("gamma_scale below 1", c))
+    c = W.gaussian_barrier_small(gamma0=0.45); c = W.with_theta(c, H=0.5)
+    out.append(("differentiation gamma0 with a higher barrier", c))
+    c = W.helium_soft_coulomb(gamma0=1.5); out.append(("table kernel, given gamma0 below xi/2", c))
+    c = W.helium_soft_coulomb(gamma_scale=0.75); out.append(("table kernel, gamma_scale below 1", c))
+    return out
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_pair_probability_above_one_rejected(lib, oracle_mod, case):
+    """Remark 3 needs gamma0 >= xi_m / 2 for every component, static ones
+    included: both the library and the oracle refuse a configuration that
+    breaks it (the sp1 acceptance would silently cap at 1)."""
+    what, cfg = _pair_probability_above_one()[case]
+    with pytest.raises(P.WBRWError) as e:
+        P.wbrw_workspace_size(cfg)
+    assert e.value.code == P.EINVAL, what
+    with pytest.raises(ValueError):
+        oracle_mod.OracleSim(cfg)
+
+
+def test_pair_probability_at_the_bound_accepted(lib, oracle_mod):
+    for cfg in (W.gaussian_barrier_small(gamma0=0.3), W.gaussian_barrier_small(gamma_scale=1.0),
+                W.helium_soft_coulomb(N0=np.array([10])), W.gaussian_barrier_small(gamma0=0.45)):
+        assert P.wbrw_workspace_size(cfg) > 0
+        oracle_mod.OracleSim(cfg)
+
+
 def test_histogram_bytes_per_cell_match_paper():
     """Sec. 5.4: 382 MB (sp1) and 763 MB (sp2) for N_h = 100^4 integer
     histograms: 4 and 8 bytes per cell.  The workspace grows by exactly that

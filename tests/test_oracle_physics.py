@@ -286,3 +286,68 @@ def test_signed_histogram_sampling_cat_state(oracle_mod):
     d = s.density()[0]
     c = -60 + 0.25 + 0.5 * np.arange(240)
     assert np.abs(d - np.interp(c, x, rhoT)).sum() * 0.5 < 0.04
+
+
+# ---- the 4D soft-Coulomb model (Example 1: helium-like, three components) --
+
+def _soft_coulomb_forces(x1, x2):
+    """-grad V of V = -2/sqrt(x1^2+1) - 2/sqrt(x2^2+1) + 1/sqrt((x1-x2)^2+1),
+    split by component: nucleus on electron 1 (along k1), nucleus on electron 2
+    (along k2), and the electron pair, whose force is f (1, -1) with
+    f = r / (r^2+1)^(3/2), r = x1 - x2 (repulsive)."""
+    f1 = -2.0 * x1 / (x1 * x1 + 1.0) ** 1.5
+    f2 = -2.0 * x2 / (x2 * x2 + 1.0) ** 1.5
+    r = x1 - x2
+    fee = r / (r * r + 1.0) ** 1.5
+    return f1, f2, fee
+
+
+@pytest.mark.parametrize("pos", [(1.0, -1.5), (-0.6, 2.2)])
+def test_helium_per_component_kick_rate_equals_force(oracle_mod, pos):
+    """Each table component's signed kick rate along its own direction equals
+    its force: gamma0 E[accepted * 2 sigma q] = -dV_m/d(r_m).  This pins the
+    sign of each transform (nucleus attractive, electron pair repulsive) and the
+    phase argument of each component (x1, x2 and x1 - x2)."""
+    x1, x2 = pos
+    s = oracle_mod.OracleSim(W.helium_soft_coulomb(N0=np.array([10])))
+    g0 = s.gamma0()
+    expect = _soft_coulomb_forces(x1, x2)
+    ids = np.arange(300_000, dtype=np.uint64)
+    for m in range(3):
+        acc, kick, _ = s.probe_jump(0, m, [x1, x2], ids)
+        per = acc * 2.0 * kick
+        rate = g0 * per.mean()
+        se = g0 * per.std() / np.sqrt(len(ids))
+        assert abs(rate - expect[m]) < 4.5 * se + 2e-3, (m, rate, expect[m], se)
+
+
+@pytest.mark.parametrize("pos", [(1.0, -1.5), (-0.6, 2.2)])
+def test_helium_walk_momentum_rate_equals_total_force(oracle_mod, pos):
+    """Whole 4D walk, kick directions included: N static parents at (x1, x2)
+    with k = 0, one short step T.  The signed momentum of the ensemble grows
+    as N T F(x) (Ehrenfest; exact in expectation up to O(T^2) from the
+    offspring's drift), with F the total force: (f1 + f_ee, f2 - f_ee).  A
+    kick of the electron pair along (1, 1) or (-1, 1), or a component acting
+    on the wrong axis, moves one of the two components by more than 0.2."""
+    x1, x2 = pos
+    N, T = 1_000_000, 0.02
+    cfg = W.helium_soft_coulomb(N0=np.array([1]), dt=T)
+    # a k-box wide enough that no offspring is removed
+    cfg["grid"] = {"x_lo": -50.0, "x_hi": 50.0, "nx": 10, "k_lo": -40.0, "k_hi": 40.0, "nk": 10}
+    s = oracle_mod.OracleSim(cfg)
+    s.set_particles(0, np.array([[x1] * N, [x2] * N]), np.zeros((2, N)),
+                    sign=np.ones(N, dtype=np.int8))
+    s.step(1)
+    st = s.stats()
+    assert st["killed"] == 0 and st["pairs"] > 0
+    p = s.particles()
+    sg = p["sign"].astype(np.float64)
+    M = (p["k"] * sg).sum(axis=1)            # signed momentum (parents keep k = 0)
+    f1, f2, fee = _soft_coulomb_forces(x1, x2)
+    expect = np.array([f1 + fee, f2 - fee])
+    # variance from the pairs: sum over the offspring of k^2 (each pair adds
+    # +-(k_a - k_b) with independent kicks)
+    var = (p["k"] ** 2 * (sg != 0)).sum(axis=1)
+    se = np.sqrt(var) / (N * T)
+    got = M / (N * T)
+    assert np.all(np.abs(got - expect) < 4.5 * se + 0.01), (got, expect, se)
