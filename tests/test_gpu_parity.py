@@ -318,6 +318,35 @@ def test_snapshot_restore_continues_exactly(P, O):
     compare(b, r, "restore vs oracle")
 
 
+def test_restore_into_used_handle(P, O):
+    """A snapshot restored into a handle that has already run annihilations of
+    another trajectory continues exactly as the oracle does.  Ghost placement
+    and ghost tangents depend on the look-back of the next annihilation, which
+    must not accept the status words the handle wrote before the restore
+    (they carry the epochs the snapshot's count would reuse)."""
+    cfg = W.gaussian_barrier_small(N0=np.array([3000]), gamma0=0.45, track_tangent=1)
+    a = P.Simulation(cfg)
+    a.run(12, 10)
+    snap_a = a.snapshot()
+    c = P.Simulation(dict(cfg, seed=5))   # another trajectory to the same step
+    c.run(12, 10)
+    snap_c = c.snapshot()
+    b = P.Simulation(cfg)
+    b.restore(snap_c)
+    b.run(18, 10)                 # annihilations at steps 20 and 30 of that trajectory
+    b.restore(snap_a)
+    b.run(18, 10)                 # the same steps again, from a's state
+    r = O.OracleSim(cfg)
+    r.run(30, 10)
+    say(f"restore into used handle: n={r.count()} ghosts={r.count(ghost=True)}")
+    compare(b, r, "restored into a used handle")
+    assert b.count(ghost=True) == r.count(ghost=True)
+    gg, gr = b.particles(ghost=True), r.particles(ghost=True)
+    assert_same_ensemble(gg, gr, what="ghosts after restore into a used handle")
+    _close(gg["D"], gr["D"], "ghost tangents after restore into a used handle")
+    _close(b.particles()["D"], r.particles()["D"], "tangents after restore into a used handle")
+
+
 def test_autotune_keeps_results(P, O):
     """The autotuner's steps are real steps; any grid it picks gives the same bits."""
     cfg = W.batched_barriers(B=4, N0=np.array([3000, 100, 25000, 7000], dtype=np.int64))
