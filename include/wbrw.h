@@ -205,6 +205,19 @@ int wbrw_run(wbrw_t h, int32_t nsteps, int32_t annihilate_every, int32_t use_gra
  * doubles, caller-owned.  nbins <= max_density_bins.  No synchronisation. */
 int wbrw_density(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, double *d_out);
 
+/* Density readout that allocates nothing, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same result as wbrw_density, and nbins may exceed
+ * max_density_bins: the per-XCD accumulators live in a library-owned device
+ * array of 4 MiB (kXcd * n_instances * nbins int64 words, so
+ * 8 * n_instances * nbins <= 524288, else WBRW_EINVAL) instead of the
+ * workspace.  Each GPU holds one such array for the life of the process and
+ * every call on that GPU shares it: the call clears it first, and calls that
+ * overlap on one GPU (other streams or handles) race.  d_out: device,
+ * caller-owned, B*nbins doubles.  No allocation, no synchronisation. */
+int wbrw_density_noalloc(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi,
+                         double *d_out);
+
 /* Tangent density (track_tangent only): d_out[(b*3 + c) * nbins + j] =
  * sum over real particles and ghosts in bin j of D_c / (N0_b dx), an unbiased
  * estimate of the derivative of the density with respect to

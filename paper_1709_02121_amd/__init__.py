@@ -102,6 +102,7 @@ def lib():
         L.wbrw_run.argtypes = [vp, i32, i32, i32]
         L.wbrw_density.argtypes = [vp, i32, i32, C.c_double, C.c_double, vp]
         L.wbrw_density_tangent.argtypes = [vp, i32, i32, C.c_double, C.c_double, vp]
+        L.wbrw_density_noalloc.argtypes = [vp, i32, i32, C.c_double, C.c_double, vp]
         L.wbrw_stats.argtypes = [vp, i32, C.POINTER(Stats)]
         L.wbrw_count.argtypes = [vp, i32, i32, C.POINTER(C.c_int64)]
         L.wbrw_export.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp]
@@ -119,7 +120,7 @@ def lib():
                   "wbrw_density", "wbrw_density_tangent", "wbrw_stats", "wbrw_count",
                   "wbrw_export", "wbrw_destroy", "wbrw_profile", "wbrw_profile_read",
                   "wbrw_density_vjp", "wbrw_snapshot_size", "wbrw_snapshot", "wbrw_restore",
-                  "wbrw_autotune"):
+                  "wbrw_autotune", "wbrw_density_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -264,6 +265,19 @@ class Simulation:
                 out = self.torch.empty((self.B, nbins), dtype=self.torch.float64, device=self.device)
         _check(lib().wbrw_density(self.h, axis, nbins, lo, hi, C.c_void_p(out.data_ptr())),
                "wbrw_density")
+        self._order_for_caller()
+        return out
+
+    def density_noalloc(self, out, axis=0, nbins=None, lo=None, hi=None):
+        """wbrw_density_noalloc into the caller's tensor `out` (B x nbins float64
+        on the device): the library allocates nothing for it."""
+        d = self.cfg["density"]
+        nbins = d["nbins"] if nbins is None else nbins
+        lo = d["lo"] if lo is None else lo
+        hi = d["hi"] if hi is None else hi
+        assert out.dtype == self.torch.float64 and out.numel() == self.B * nbins and out.is_contiguous()
+        _check(lib().wbrw_density_noalloc(self.h, axis, nbins, lo, hi, C.c_void_p(out.data_ptr())),
+               "wbrw_density_noalloc")
         self._order_for_caller()
         return out
 

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -281,8 +282,43 @@ Layout make_layout(const wbrw_config *c)
 
 }  // namespace
 
+// Device scratch of wbrw_density_noalloc: its per-XCD density accumulators
+// (kXcd x B x nbins int64), for callers that cannot allocate.  Every GPU the
+// library runs on holds one copy until the process ends; all calls on that
+// GPU share it.  The host-side name is only a stand-in for the symbol: device
+// code gets the address that hipGetSymbolAddress returns for each GPU.
+constexpr int64_t kNoAllocWords = int64_t(1) << 19;   // 4 MiB
+static __device__ __align__(256) int64_t scratch[kNoAllocWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int64_t *g_scratch[kMaxDevices] = {};
+
+// The scratch array's address on the current device, looked up once per
+// device (the device must be current).
+int scratch_on_current_device(int dev, int64_t **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return WBRW_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            std::fprintf(stderr, "wbrw: hipGetSymbolAddress(scratch) failed: %s\n", hipGetErrorString(e));
+            return WBRW_EHIP;
+        }
+        g_scratch[dev] = (int64_t *)p;
+    }
+    *out = g_scratch[dev];
+    return WBRW_OK;
+}
+}  // namespace
+
 struct wbrw_handle {
     int B = 0, dim = 0, M = 0, strategy = 0, tangent = 0;
+    int device = 0;
+    int64_t *scratch_ptr = nullptr;   // this device's copy of `scratch`
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     Layout L;
@@ -637,6 +673,11 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         delete h;
         return WBRW_EHIP;
     }
+    h->device = dev;
+    {
+        const int rc = scratch_on_current_device(dev, &h->scratch_ptr);
+        if (rc) { delete h; return rc; }
+    }
 
     Dev &d = h->d;
     d.B = h->B;
@@ -926,6 +967,40 @@ int wbrw_density(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, do
     const Dev &d = h->d;
     hipStream_t s = h->stream;
     const bool sp2 = h->strategy == WBRW_SP2;
+    const int outb = std::max(1, std::min(h->cus * 4, (int)ceil_div((int64_t)h->B * nbins, kThreads)));
+    stage_begin(h, WBRW_STAGE_DENSITY);
+    if (h->dim == 1) {
+        if (sp2) hipLaunchKernelGGL((k_density_bin<1, true, false>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+        else hipLaunchKernelGGL((k_density_bin<1, false, false>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+    } else {
+        if (sp2) hipLaunchKernelGGL((k_density_bin<2, true, false>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+        else hipLaunchKernelGGL((k_density_bin<2, false, false>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+    }
+    if (sp2) hipLaunchKernelGGL((k_density_out<true, false>), dim3(outb), dim3(kThreads), 0, s, d, nbins, dxb, d_out);
+    else hipLaunchKernelGGL((k_density_out<false, false>), dim3(outb), dim3(kThreads), 0, s, d, nbins, dxb, d_out);
+    stage_end(h);
+    return launch_check();
+}
+
+int wbrw_density_noalloc(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, double *d_out)
+{
+    if (!h || !d_out || nbins < 1 || !(hi > lo)) return WBRW_EINVAL;
+    if (axis < 0 || axis >= h->dim) return WBRW_EINVAL;
+    const int64_t words = (int64_t)kXcd * h->B * nbins;
+    if (words > kNoAllocWords) return WBRW_EINVAL;
+    if (!h->scratch_ptr) return WBRW_ESTATE;
+    const double dxb = (hi - lo) / (double)nbins;
+    // the same kernels as wbrw_density, with the accumulators ([kXcd][B][nbins])
+    // in this device's scratch instead of the workspace
+    Dev d = h->d;
+    d.dacc = h->scratch_ptr;
+    d.max_bins = nbins;
+    hipStream_t s = h->stream;
+    const bool sp2 = h->strategy == WBRW_SP2;
+    // the accumulators start at zero (the readout clears what it reads, but a
+    // call that failed part way, or the first call, may find anything)
+    const int fb = std::max(1, std::min(h->cus * 4, (int)ceil_div(words, kThreads)));
+    hipLaunchKernelGGL(k_fill64, dim3(fb), dim3(kThreads), 0, s, (uint64_t *)h->scratch_ptr, words, 0ull);
     const int outb = std::max(1, std::min(h->cus * 4, (int)ceil_div((int64_t)h->B * nbins, kThreads)));
     stage_begin(h, WBRW_STAGE_DENSITY);
     if (h->dim == 1) {
