@@ -28,7 +28,11 @@
  *
  * Determinism: for a given configuration and seed, results are bit-identical
  * across runs and independent of launch shapes and of how many instances share
- * a handle (instance b is keyed by instance_offset + b).
+ * a handle (instance b is keyed by instance_offset + b).  Every sum over
+ * particles is an exact integer sum: signs and sp2 weights in 2^-32 units,
+ * tangents in 32.32 fixed point (each component D enters as trunc(D 2^32),
+ * and a sum Q reads as (double)floor(Q / 2^32) + (Q mod 2^32) 2^-32), so no
+ * result depends on the order in which the GPU adds them.
  */
 #ifndef WBRW_H
 #define WBRW_H
@@ -48,7 +52,9 @@ enum wbrw_status {
     WBRW_ECAPACITY = -2,  /* an instance outgrew its particle capacity */
     WBRW_EHIP = -3,       /* a HIP runtime call failed */
     WBRW_ESTATE = -4,     /* call not valid in this state (e.g. sticky device error) */
-    WBRW_EDEPTH = -5      /* a family tree within one step exceeded the depth limit */
+    WBRW_EDEPTH = -5,     /* a family tree within one step exceeded the depth limit */
+    WBRW_ERANGE = -6      /* a non-finite position met at annihilation, or a tangent
+                             component outside the fixed-point range |D| < 2^31 */
 };
 
 enum wbrw_strategy {
@@ -219,7 +225,8 @@ int wbrw_density_noalloc(wbrw_t h, int32_t axis, int32_t nbins, double lo, doubl
                          double *d_out);
 
 /* Tangent density (track_tangent only): d_out[(b*3 + c) * nbins + j] =
- * sum over real particles and ghosts in bin j of D_c / (N0_b dx), an unbiased
+ * sum over real particles and ghosts in bin j of D_c / (N0_b dx) (the sum in
+ * 32.32 fixed point, see Determinism), an unbiased
  * estimate of the derivative of the density with respect to
  * theta = (H, w, x0) (likelihood-ratio scores; with track_tangent 2 the x0
  * part comes from derivative ghost pairs).  d_out: device, caller-owned.
@@ -228,10 +235,12 @@ int wbrw_density_tangent(wbrw_t h, int32_t axis, int32_t nbins, double lo, doubl
                          double *d_out);
 
 /* Backward pass of the density (track_tangent only): grad_out[b*3 + c] =
- * sum_j g[b*nbins + j] d rho_bj / d theta_c, accumulated directly from the
- * per-particle tangents of real particles and ghosts in bin
- * j, theta = (H, w, x0).  g, grad_out: device, caller-owned.  Same binning as
- * wbrw_density.  No synchronisation. */
+ * sum_j g[b*nbins + j] d rho_bj / d theta_c, theta = (H, w, x0): the
+ * per-particle tangents of real particles and ghosts are summed per bin j in
+ * fixed point (as wbrw_density_tangent), then contracted with g over the bins
+ * in ascending order and divided by N0_b dx.  nbins <= max_density_bins.
+ * g, grad_out: device, caller-owned.  Same binning as wbrw_density.  No
+ * synchronisation. */
 int wbrw_density_vjp(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi,
                      const double *g, double *grad_out);
 
@@ -245,7 +254,8 @@ int wbrw_snapshot(wbrw_t h, void *dst, size_t bytes);
 int wbrw_restore(wbrw_t h, const void *src, size_t bytes);
 
 /* Synchronises the stream, then writes instance b's statistics.  Returns a
- * sticky device error (WBRW_ECAPACITY, WBRW_EDEPTH) if one was raised. */
+ * sticky device error (WBRW_ECAPACITY, WBRW_EDEPTH, WBRW_ERANGE) if one was
+ * raised. */
 int wbrw_stats(wbrw_t h, int32_t b, wbrw_stats_t *out);
 
 /* Synchronises and writes the particle count of instance b (ghost != 0: ghosts). */

@@ -61,7 +61,7 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "n", "n_plus", "n_minus", "n_ghost", "net", "escaped", "killed", "pairs", "events",
         "event_cap_hits", "max_depth", "S_plus", "S_minus", "N_plus", "N_minus")] + [
-        ("gamma0", C.c_double), ("step", C.c_int64)]
+        ("gamma0", C.c_double), ("step", C.c_int64), ("range_errors", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -84,6 +84,7 @@ def lib():
         L.orc_annihilate.argtypes = [vp]
         L.orc_density.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp]
         L.orc_density_tangent.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp]
+        L.orc_density_vjp.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp, vp]
         L.orc_count.restype = C.c_int64
         L.orc_count.argtypes = [vp, C.c_int, C.c_int]
         L.orc_get.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp]
@@ -266,6 +267,17 @@ class OracleSim:
         hi = d["hi"] if hi is None else hi
         out = np.zeros((self.B, 3, nbins))
         lib().orc_density_tangent(self.h, axis, nbins, lo, hi, _ptr(out))
+        return out
+
+    def density_vjp(self, g, axis=0, nbins=None, lo=None, hi=None):
+        """sum_j g[b, j] d rho[b, j] / d theta for every instance, shape (B, 3)."""
+        d = self.cfg["density"]
+        nbins = d["nbins"] if nbins is None else nbins
+        lo = d["lo"] if lo is None else lo
+        hi = d["hi"] if hi is None else hi
+        gg = np.ascontiguousarray(np.broadcast_to(np.asarray(g, dtype=np.float64), (self.B, nbins)))
+        out = np.zeros((self.B, 3))
+        lib().orc_density_vjp(self.h, axis, nbins, lo, hi, _ptr(gg), _ptr(out))
         return out
 
     def count(self, b=0, ghost=False):

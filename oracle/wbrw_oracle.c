@@ -102,6 +102,7 @@ typedef struct {
     int64_t S_plus, S_minus, N_plus, N_minus; /* last sp2 bootstrap */
     double gamma0;
     int64_t step;
+    int64_t range_errors; /* tangent components outside the fixed-point range of fx_add */
 } orc_stats;
 
 /* ------------------------------------------------------------------------ */
@@ -993,6 +994,28 @@ static void init_from_histogram(orc_sim *S, int b)
     free(cnt);
 }
 
+/* Sums of tangents over the particles of a cell or a density bin (the
+ * differentiation form; the paper defines no such sums): each component D of
+ * a particle enters as the integer trunc(D 2^32) (32.32 fixed point, which
+ * needs |D| < 2^31), the integer sums are exact, so no summation order is
+ * singled out, and a sum Q has the value (double)floor(Q / 2^32) +
+ * (double)(Q mod 2^32) 2^-32.  A component outside the range, or not a
+ * number, adds nothing and is counted in range_errors. */
+static void fx_add(inst_t *I, i128 *Q, const double *D)
+{
+    for (int c = 0; c < 3; c++) {
+        if (!(fabs(D[c]) < 2147483648.0)) { I->st.range_errors++; continue; }
+        Q[c] += (i128)(int64_t)(D[c] * 4294967296.0);
+    }
+}
+
+static double fx_value(i128 Q)
+{
+    i128 h = Q >> 32;                                  /* floor(Q / 2^32) */
+    uint64_t lo = (uint64_t)(Q - h * ((i128)1 << 32)); /* Q mod 2^32 */
+    return (double)(int64_t)h + (double)lo * 0x1p-32;
+}
+
 /* sp1 annihilation: Eq. signed_histogram, n_nu = n_nu^+ - n_nu^- exactly,
  * then Alg. 3 without its rounding step (m is already an integer). */
 static void annihilate_sp1(orc_sim *S, inst_t *I)
@@ -1001,7 +1024,7 @@ static void annihilate_sp1(orc_sim *S, inst_t *I)
     int64_t nc = n_cells(S);
     int64_t *cnt = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
     int64_t *occ = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
-    double *T = C->track_tangent ? (double *)calloc((size_t)nc * 3, sizeof(double)) : NULL;
+    i128 *Q = C->track_tangent ? (i128 *)calloc((size_t)nc * 3, sizeof(i128)) : NULL;
     for (int64_t i = 0; i < I->real.n; i++) {
         double x[2] = { I->real.x[0][i], I->real.x[1][i] };
         double k[2] = { I->real.k[0][i], I->real.k[1][i] };
@@ -1009,20 +1032,23 @@ static void annihilate_sp1(orc_sim *S, inst_t *I)
         if (nu < 0) { I->st.escaped += I->real.sgn[i]; continue; }
         cnt[nu] += I->real.sgn[i];
         occ[nu] += 1;
-        if (T) for (int c = 0; c < 3; c++) T[3 * nu + c] += I->real.D[3 * i + c];
+        if (Q) fx_add(I, Q + 3 * nu, I->real.D + 3 * i);
     }
-    if (T) {
+    double *T = NULL;
+    if (Q) {
         for (int64_t i = 0; i < I->ghost.n; i++) {
             double x[2] = { I->ghost.x[0][i], I->ghost.x[1][i] };
             double k[2] = { I->ghost.k[0][i], I->ghost.k[1][i] };
             int64_t nu = cell_of(S, x, k);
             if (nu < 0) continue;
             occ[nu] += 1;
-            for (int c = 0; c < 3; c++) T[3 * nu + c] += I->ghost.D[3 * i + c];
+            fx_add(I, Q + 3 * nu, I->ghost.D + 3 * i);
         }
+        T = (double *)malloc((size_t)nc * 3 * sizeof(double));
+        for (int64_t j = 0; j < 3 * nc; j++) T[j] = fx_value(Q[j]);
     }
     regenerate(S, I, cnt, occ, T);
-    free(cnt); free(occ); free(T);
+    free(cnt); free(occ); free(Q); free(T);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1180,11 +1206,11 @@ static void annihilate_sp2(orc_sim *S, inst_t *I)
     double *T = NULL;
     if (S->cfg.track_tangent) {
         occ = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
-        T = (double *)calloc((size_t)nc * 3, sizeof(double));
+        i128 *Q = (i128 *)calloc((size_t)nc * 3, sizeof(i128));
         for (int64_t i = 0; i < n; i++) {
             if (cell[i] < 0) continue;
             occ[cell[i]] += 1;
-            for (int c = 0; c < 3; c++) T[3 * cell[i] + c] += I->real.D[3 * i + c];
+            fx_add(I, Q + 3 * cell[i], I->real.D + 3 * i);
         }
         for (int64_t i = 0; i < I->ghost.n; i++) {
             double x[2] = { I->ghost.x[0][i], I->ghost.x[1][i] };
@@ -1192,8 +1218,11 @@ static void annihilate_sp2(orc_sim *S, inst_t *I)
             int64_t nu = cell_of(S, x, k);
             if (nu < 0) continue;
             occ[nu] += 1;
-            for (int c = 0; c < 3; c++) T[3 * nu + c] += I->ghost.D[3 * i + c];
+            fx_add(I, Q + 3 * nu, I->ghost.D + 3 * i);
         }
+        T = (double *)malloc((size_t)nc * 3 * sizeof(double));
+        for (int64_t j = 0; j < 3 * nc; j++) T[j] = fx_value(Q[j]);
+        free(Q);
     }
     regenerate(S, I, cnt, occ, T);
     for (int c = 0; c < 2; c++) { free(A[c]); free(idx[c]); free(ntil[c]); }
@@ -1245,28 +1274,57 @@ void orc_density(orc_sim *S, int axis, int nbins, double lo, double hi, double *
     free(acc);
 }
 
-/* Tangent density J[b][c][j] = sum_{i in j} D_i[c] / (N_alpha dx_b), real
- * particles then ghosts, in array order. */
+/* Bin sums of the tangents of instance b's real particles and ghosts in
+ * fixed point (fx_add): T[c * nbins + j] = value of sum_{i in bin j} D_i[c]. */
+static void tangent_bins(orc_sim *S, int b, int axis, int nbins, double lo, double dxb, double *T)
+{
+    inst_t *I = &S->I[b];
+    i128 *Q = (i128 *)calloc((size_t)nbins * 3, sizeof(i128));
+    ens_t *E2[2] = { &I->real, &I->ghost };
+    for (int e = 0; e < 2; e++) {
+        ens_t *E = E2[e];
+        for (int64_t i = 0; i < E->n; i++) {
+            double q = (E->x[axis][i] - lo) / dxb;
+            if (!(q >= 0.0 && q < (double)nbins)) continue;
+            i128 acc[3] = { 0, 0, 0 };
+            fx_add(I, acc, E->D + 3 * i);
+            for (int c = 0; c < 3; c++) Q[(int64_t)c * nbins + (int)q] += acc[c];
+        }
+    }
+    for (int64_t j = 0; j < 3 * (int64_t)nbins; j++) T[j] = fx_value(Q[j]);
+    free(Q);
+}
+
+/* Tangent density J[b][c][j] = sum_{i in j} D_i[c] / (N_alpha dx_b), the bin
+ * sums taken over real particles and ghosts in fixed point (fx_add). */
 void orc_density_tangent(orc_sim *S, int axis, int nbins, double lo, double hi, double *out)
 {
     double dxb = (hi - lo) / (double)nbins;
     for (int b = 0; b < S->cfg.B; b++) {
-        inst_t *I = &S->I[b];
         double *o = out + (int64_t)b * 3 * nbins;
-        for (int j = 0; j < 3 * nbins; j++) o[j] = 0.0;
-        ens_t *E2[2] = { &I->real, &I->ghost };
-        for (int e = 0; e < 2; e++) {
-            ens_t *E = E2[e];
-            for (int64_t i = 0; i < E->n; i++) {
-                double q = (E->x[axis][i] - lo) / dxb;
-                if (!(q >= 0.0 && q < (double)nbins)) continue;
-                int j = (int)q;
-                for (int c = 0; c < 3; c++) o[c * nbins + j] += E->D[3 * i + c];
-            }
-        }
-        double denom = (double)I->N0 * dxb;
+        tangent_bins(S, b, axis, nbins, lo, dxb, o);
+        double denom = (double)S->I[b].N0 * dxb;
         for (int j = 0; j < 3 * nbins; j++) o[j] = o[j] / denom;
     }
+}
+
+/* Backward pass of the density: out[b * 3 + c] = (sum_j g[b * nbins + j]
+ * T[c][j]) / (N_alpha dx_b), with the fixed-point bin sums T of
+ * tangent_bins and the contraction taken over the bins in ascending order. */
+void orc_density_vjp(orc_sim *S, int axis, int nbins, double lo, double hi, const double *g, double *out)
+{
+    double dxb = (hi - lo) / (double)nbins;
+    double *T = (double *)malloc((size_t)nbins * 3 * sizeof(double));
+    for (int b = 0; b < S->cfg.B; b++) {
+        tangent_bins(S, b, axis, nbins, lo, dxb, T);
+        double denom = (double)S->I[b].N0 * dxb;
+        for (int c = 0; c < 3; c++) {
+            double acc = 0.0;
+            for (int j = 0; j < nbins; j++) acc = acc + g[(int64_t)b * nbins + j] * T[(int64_t)c * nbins + j];
+            out[b * 3 + c] = acc / denom;
+        }
+    }
+    free(T);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -21,7 +21,7 @@ SRC_DIR = os.path.join(HERE, "csrc")
 HEADER = os.path.join(ROOT, "include", "wbrw.h")
 MAXM = 4
 
-OK, EINVAL, ECAPACITY, EHIP, ESTATE, EDEPTH = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ECAPACITY, EHIP, ESTATE, EDEPTH, ERANGE = 0, -1, -2, -3, -4, -5, -6
 SP1, SP2 = 0, 1
 KERNEL = {"gauss": 0, "table": 1}
 STRATEGY = {"sp1": SP1, "sp2": SP2}

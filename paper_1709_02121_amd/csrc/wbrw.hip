@@ -35,9 +35,9 @@ struct Layout {
     size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
     size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, tileA = 0, Nsrt = 0, srtS = 0, tileB = 0, tileR = 0,
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
-           tcA = 0, tcAg = 0, supA = 0, supAg = 0, spart = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, occx = 0, Tcellx = 0, off = 0,
-           occ = 0, Tcell = 0, ntil = 0, dacc = 0, dTacc = 0, bA = 0, bcopies = 0, bcls = 0,
-           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, vjp = 0, hist = 0, xitab = 0;
+           tcA = 0, tcAg = 0, supA = 0, supAg = 0, spart = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, occx = 0, Tqx = 0, off = 0,
+           occ = 0, Tq = 0, ntil = 0, dacc = 0, dTq = 0, bA = 0, bcopies = 0, bcls = 0,
+           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, hist = 0, xitab = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
     int64_t tilesA = 0, tilesAg = 0, tilesB = 0, tilesBg = 0, tilesS = 0, tilesP = 0;
 };
@@ -260,12 +260,12 @@ Layout make_layout(const wbrw_config *c)
     if (xcd_counts(c)) L.cntx = take(cur, (size_t)(kXcd - 1) * (sp2 ? 2 : 1) * BB * Nh * 4);
     if (tan) {
         L.occ = take(cur, BB * Nh * 4);
-        L.Tcell = take(cur, 3 * BB * Nh * 8);
+        L.Tq = take(cur, 6 * BB * Nh * 8);
         if (L.cntx) {
             L.occx = take(cur, (size_t)(kXcd - 1) * BB * Nh * 4);
-            L.Tcellx = take(cur, (size_t)(kXcd - 1) * 3 * BB * Nh * 8);
+            L.Tqx = take(cur, (size_t)(kXcd - 1) * 6 * BB * Nh * 8);
         }
-        L.dTacc = take(cur, 3 * BB * MB * 8);
+        L.dTq = take(cur, 6 * BB * MB * 8);
     }
     if (sp2) {
         L.ntil = take(cur, 2 * BB * Nh * 4);
@@ -274,7 +274,6 @@ Layout make_layout(const wbrw_config *c)
         L.bscan_tiles = take(cur, (BB + 1) * 8);
     }
     L.dacc = take(cur, kXcd * BB * MB * 8);   // one accumulator per XCD
-    L.vjp = take(cur, BB * 3 * 8);
     L.zero_end = (cur + kAlign - 1) / kAlign * kAlign;
     L.total = L.zero_end;
     return L;
@@ -631,6 +630,7 @@ const char *wbrw_strerror(int code)
     case WBRW_EHIP: return "HIP runtime error";
     case WBRW_ESTATE: return "invalid state";
     case WBRW_EDEPTH: return "family tree deeper than the per-step limit";
+    case WBRW_ERANGE: return "a non-finite position, or a tangent outside the fixed-point range";
     default: return "unknown error";
     }
 }
@@ -809,10 +809,10 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.cntx = L.cntx ? at<int32_t>(w, L.cntx) : nullptr;
     d.off = at<int64_t>(w, L.off);
     d.occ = h->tangent ? at<int32_t>(w, L.occ) : nullptr;
-    d.Tcell = h->tangent ? at<double>(w, L.Tcell) : nullptr;
+    d.Tq = h->tangent ? at<int64_t>(w, L.Tq) : nullptr;
     d.occx = L.occx ? at<int32_t>(w, L.occx) : nullptr;
-    d.Tcellx = L.Tcellx ? at<double>(w, L.Tcellx) : nullptr;
-    d.dTacc = h->tangent ? at<double>(w, L.dTacc) : nullptr;
+    d.Tqx = L.Tqx ? at<int64_t>(w, L.Tqx) : nullptr;
+    d.dTq = h->tangent ? at<int64_t>(w, L.dTq) : nullptr;
     d.dacc = at<int64_t>(w, L.dacc);
     if (h->strategy == WBRW_SP2) {
         d.ntil = at<int32_t>(w, L.ntil);
@@ -1037,11 +1037,14 @@ int wbrw_density_vjp(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi
     const double dxb = (hi - lo) / (double)nbins;
     const Dev &d = h->d;
     hipStream_t s = h->stream;
-    double *acc = at<double>(h->ws, h->L.vjp);
+    if (nbins > h->d.max_bins) return WBRW_EINVAL;
+    // the tangent bin sums (fixed point, real particles and ghosts), then the
+    // contraction with g in bin order
     stage_begin(h, WBRW_STAGE_DENSITY);
-    hipLaunchKernelGGL(k_vjp, dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, nbins, lo, dxb, g, acc);
-    hipLaunchKernelGGL(k_vjp, dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 1, nbins, lo, dxb, g, acc);
-    hipLaunchKernelGGL(k_vjp_out, dim3(1), dim3(kThreads), 0, s, d, dxb, acc, grad_out);
+    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 1, axis, nbins, lo, dxb);
+    const int ob = std::max(1, (int)ceil_div((int64_t)h->B * 3, kThreads));
+    hipLaunchKernelGGL(k_vjp_out, dim3(ob), dim3(kThreads), 0, s, d, nbins, dxb, g, grad_out);
     stage_end(h);
     return launch_check();
 }
@@ -1133,7 +1136,7 @@ int wbrw_snapshot(wbrw_t h, void *dst, size_t bytes)
     int rc = snap_counts(h, N, NG, c, total);
     if (rc) return rc;
     if (bytes < total) return WBRW_EINVAL;
-    if (c.err) return (c.err & kErrCapacity) ? WBRW_ECAPACITY : WBRW_EDEPTH;
+    if (c.err) return (c.err & kErrCapacity) ? WBRW_ECAPACITY : (c.err & kErrDepth) ? WBRW_EDEPTH : WBRW_ERANGE;
     SnapHeader hd;
     std::memset(&hd, 0, sizeof(hd));
     hd.magic = 0x5742525753534e50ull;
@@ -1243,6 +1246,7 @@ int wbrw_stats(wbrw_t h, int32_t b, wbrw_stats_t *out)
     out->gamma0 = h->ip[b].gamma0;
     if (c.err & kErrCapacity) return WBRW_ECAPACITY;
     if (c.err & kErrDepth) return WBRW_EDEPTH;
+    if (c.err & kErrRange) return WBRW_ERANGE;
     return WBRW_OK;
 }
 

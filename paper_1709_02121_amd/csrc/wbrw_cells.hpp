@@ -221,7 +221,8 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     const bool own = d.cntx == nullptr || xc == 0 || (TAN && d.occx == nullptr);
     int32_t *const cg = own ? d.cnt : d.cntx + (int64_t)(xc - 1) * ncell;
     int32_t *const og = own ? d.occ : d.occx + (int64_t)(xc - 1) * ncell;
-    double *const tg = own ? d.Tcell : d.Tcellx + (int64_t)(xc - 1) * 3 * ncell;
+    int64_t *const tg = own ? d.Tq : d.Tqx + (int64_t)(xc - 1) * 6 * ncell;
+    uint32_t err = 0;
     if (!TAN)
         for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
     if (tid == 0) { s_esc = 0; s_nkeys = 0; }
@@ -291,7 +292,10 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
             const int64_t i = base + (live ? li : 0);
             const int64_t nu = live ? cell_index<DIM>(d, xa[j], xb[j], ka[j], kb[j]) : -1;
             const int s = live ? sv[j] : 0;
-            if (live && nu < 0) esc += s;
+            if (live && nu < 0) {
+                esc += s;
+                if (!(isfinite(xa[j]) && isfinite(xb[j]) && isfinite(ka[j]) && isfinite(kb[j]))) err |= kErrRange;
+            }
             if (!TAN) {
                 if (nu < 0 || s == 0) continue;
                 const int key = (int)nu;
@@ -321,21 +325,26 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 const bool in = nu >= 0;
                 const int64_t ds = ghost ? d.gcap_total : d.cap_total;
                 const int no = run_sum<int>(nu, in ? 1 : 0, commit);
-                const double t0 = run_sum<double>(nu, in ? E.D[i] : 0.0, commit);
-                const double t1 = run_sum<double>(nu, in ? E.D[ds + i] : 0.0, commit);
-                const double t2 = run_sum<double>(nu, in ? E.D[2 * ds + i] : 0.0, commit);
-                if (commit) {
-                    atomicAdd(&og[cbase + nu], no);
-                    atomicAdd(&tg[cbase + nu], t0);
-                    atomicAdd(&tg[ncell + cbase + nu], t1);
-                    atomicAdd(&tg[2 * ncell + cbase + nu], t2);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    int64_t hi = 0;
+                    uint64_t lo = 0;
+                    if (in && !fx_split(E.D[c * ds + i], hi, lo)) err |= kErrRange;
+                    hi = run_sum<int64_t>(nu, hi, commit);
+                    lo = run_sum<uint64_t>(nu, lo, commit);
+                    if (commit) {
+                        if (hi) atomicAdd((unsigned long long *)&tg[(2 * c) * ncell + cbase + nu], (unsigned long long)hi);
+                        if (lo) atomicAdd((unsigned long long *)&tg[(2 * c + 1) * ncell + cbase + nu], (unsigned long long)lo);
+                    }
                 }
+                if (commit) atomicAdd(&og[cbase + nu], no);
             }
         }
         if (esc) atomicAdd((unsigned long long *)&s_esc, (unsigned long long)esc);
     }
     __syncthreads();
     if (cb >= 0) flush(cb);
+    if (err) atomicOr(&ctl->err, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -420,25 +429,26 @@ __global__ __launch_bounds__(kThreads) void k_fold_tangents(Dev d)
 #pragma unroll
         for (int x = 0; x < kXcd - 1; ++x) po[x] = d.occx[(int64_t)x * nc + g];
         int32_t o = d.occ[g];
-        double tv[3] = {d.Tcell[g], d.Tcell[nc + g], d.Tcell[2 * nc + g]};
+        int64_t tv[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) tv[q] = d.Tq[q * nc + g];
         bool any = false;
         for (int x = 0; x < kXcd - 1; ++x) {
             if (po[x] == 0) continue;   // a copy that saw no particle here holds no sums
-            const int64_t tx = (int64_t)x * 3 * nc + g;
+            const int64_t tx = (int64_t)x * 6 * nc + g;
             o += po[x];
             d.occx[(int64_t)x * nc + g] = 0;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                tv[q] += d.Tcellx[tx + q * nc];
-                d.Tcellx[tx + q * nc] = 0.0;
+            for (int q = 0; q < 6; ++q) {   // exact integer sums: any order
+                tv[q] += d.Tqx[tx + q * nc];
+                d.Tqx[tx + q * nc] = 0;
             }
             any = true;
         }
         if (any) {
             d.occ[g] = o;
-            d.Tcell[g] = tv[0];
-            d.Tcell[nc + g] = tv[1];
-            d.Tcell[2 * nc + g] = tv[2];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) d.Tq[q * nc + g] = tv[q];
         }
     }
 }
@@ -613,9 +623,10 @@ __global__ __launch_bounds__(kThreads) void k_regen(Dev d)
                 const int64_t nxt = (nu + 1 < d.Nh) ? (off[nu + 1] & kOffMask) : nout;
                 const double an = (double)(nxt - (onu & kOffMask));
                 const int64_t nc = d.Nh * (int64_t)B;
-                O.D[i] = d.Tcell[cbase + nu] / an;
-                O.D[d.cap_total + i] = d.Tcell[nc + cbase + nu] / an;
-                O.D[2 * d.cap_total + i] = d.Tcell[2 * nc + cbase + nu] / an;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    O.D[c * d.cap_total + i] = fx_value(d.Tq[(2 * c) * nc + cbase + nu],
+                                                        (uint64_t)d.Tq[(2 * c + 1) * nc + cbase + nu]) / an;
             }
         }
     }
@@ -654,7 +665,6 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
     // order.  Histograms wider than the LDS array go straight to HBM.
     constexpr int kLds = 4096;
     __shared__ uint64_t s_raw[kLds];
-    double *s_d = reinterpret_cast<double *>(s_raw);
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
@@ -666,8 +676,11 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
     const int tid = threadIdx.x, lane = tid & 63;
     // this block's XCD copy of the accumulator (atomics stay in its L2)
     int64_t *const dx = d.dacc + (int64_t)(blockIdx.x % kXcd) * B * d.max_bins;
-    const int width = TAN ? 3 * nbins : nbins;
+    // tangents: six fixed-point words per bin (high and low word of each
+    // component, see fx_split), exact in any order
+    const int width = TAN ? 6 * nbins : nbins;
     const bool priv = width <= kLds;
+    uint32_t err = 0;
     if (priv)
         for (int j = tid; j < width; j += kThreads) s_raw[j] = 0ull;
     int cb = -1;
@@ -676,11 +689,11 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
         for (int j = tid; j < width; j += kThreads) {
             const uint64_t v = s_raw[j];
             if (v == 0ull) continue;
-            const double f = s_d[j];
             s_raw[j] = 0ull;
             if (TAN) {
-                const int c = j / nbins, bin = j - c * nbins;
-                atomicAdd(d.dTacc + (int64_t)fb * 3 * d.max_bins + (int64_t)c * d.max_bins + bin, f);
+                const int w = j / nbins, bin = j - w * nbins;
+                atomicAdd((unsigned long long *)(d.dTq + (int64_t)fb * 6 * d.max_bins + (int64_t)w * d.max_bins + bin),
+                          (unsigned long long)v);
             } else {
                 atomicAdd((unsigned long long *)&dx[(int64_t)fb * d.max_bins + j], (unsigned long long)v);
             }
@@ -716,19 +729,22 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
             bool commit;
             if (TAN) {
                 const bool in = bin >= 0;
-                const double t0 = run_sum<double>(bin, in ? E.D[i] : 0.0, commit);
-                const double t1 = run_sum<double>(bin, in ? E.D[ds + i] : 0.0, commit);
-                const double t2 = run_sum<double>(bin, in ? E.D[2 * ds + i] : 0.0, commit);
-                if (!commit) continue;
-                if (priv) {
-                    atomicAdd(&s_d[bin], t0);
-                    atomicAdd(&s_d[nbins + bin], t1);
-                    atomicAdd(&s_d[2 * nbins + bin], t2);
-                } else {
-                    double *acc = d.dTacc + (int64_t)b * 3 * d.max_bins;
-                    atomicAdd(&acc[bin], t0);
-                    atomicAdd(&acc[d.max_bins + bin], t1);
-                    atomicAdd(&acc[2 * d.max_bins + bin], t2);
+                int64_t *acc = d.dTq + (int64_t)b * 6 * d.max_bins;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    int64_t hi = 0;
+                    uint64_t lo = 0;
+                    if (in && !fx_split(E.D[c * ds + i], hi, lo)) err |= kErrRange;
+                    hi = run_sum<int64_t>(bin, hi, commit);
+                    lo = run_sum<uint64_t>(bin, lo, commit);
+                    if (!commit) continue;
+                    if (priv) {
+                        if (hi) atomicAdd((unsigned long long *)&s_raw[(2 * c) * nbins + bin], (unsigned long long)hi);
+                        if (lo) atomicAdd((unsigned long long *)&s_raw[(2 * c + 1) * nbins + bin], (unsigned long long)lo);
+                    } else {
+                        if (hi) atomicAdd((unsigned long long *)&acc[(int64_t)(2 * c) * d.max_bins + bin], (unsigned long long)hi);
+                        if (lo) atomicAdd((unsigned long long *)&acc[(int64_t)(2 * c + 1) * d.max_bins + bin], (unsigned long long)lo);
+                    }
                 }
             } else {
                 uint64_t *acc = priv ? s_raw : (uint64_t *)dx + (int64_t)b * d.max_bins;
@@ -765,6 +781,7 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
         }
     }
     if (priv && cb >= 0) flush(cb);
+    if (err) atomicOr(&ctl->err, err);
 }
 
 // out[b][j] = acc / (N0_b dxb); the accumulator is cleared.
@@ -781,9 +798,10 @@ __global__ __launch_bounds__(kThreads) void k_density_out(Dev d, int nbins, doub
         const int64_t c = r / nbins, j = r - c * nbins;
         const double denom = (double)d.ip[b].N0 * dxb;
         if (TAN) {
-            double *acc = d.dTacc + b * 3 * d.max_bins + c * d.max_bins + j;
-            out[g] = *acc / denom;
-            *acc = 0.0;
+            int64_t *acc = d.dTq + b * 6 * d.max_bins + (2 * c) * d.max_bins + j;
+            out[g] = fx_value(acc[0], (uint64_t)acc[d.max_bins]) / denom;
+            acc[0] = 0;
+            acc[d.max_bins] = 0;
         } else {
             // the XCD copies, summed in copy order (exact integers) and cleared
             int64_t sum = 0;
@@ -799,77 +817,28 @@ __global__ __launch_bounds__(kThreads) void k_density_out(Dev d, int nbins, doub
     }
 }
 
-// Vector-Jacobian product of the density: grad[b][c] += sum over particles
-// (real, then ghosts in a second launch) of D_c g[b][bin(x)], divided by
-// N0_b dxb in k_vjp_out.  This is the backward pass of the differentiation
-// form: the likelihood-ratio scores are already accumulated per particle.
-__global__ __launch_bounds__(kThreads) void k_vjp(Dev d, int ghost, int nbins, double lo, double dxb,
-                                                  const double *g, double *acc)
+// Vector-Jacobian product of the density, after k_density_bin<.., true> has
+// summed the tangents of real particles and ghosts per bin:
+// grad[b][c] = (sum over bins j in ascending order of g[b][j] T_c[j]) /
+// (N0_b dxb), T_c[j] the fixed-point bin sum; one thread per (instance,
+// component), which also clears its sums.  This is the backward pass of the
+// differentiation form: the likelihood-ratio scores are already carried per
+// particle.
+__global__ __launch_bounds__(kThreads) void k_vjp_out(Dev d, int nbins, double dxb, const double *g, double *out)
 {
-    __shared__ double s_sum[3][kThreads / 64];
-    Ctl *ctl = d.ctl;
-    const int B = d.B;
-    const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
-    const int64_t ntiles = plan[B];
-    const int64_t *Ncur = ghost ? d.NG : d.N;
-    const Ens E = pick_set(d, ghost, ghost ? ctl->gcur : ctl->cur);
-    const int64_t ds = ghost ? d.gcap_total : d.cap_total;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        __syncthreads();
-        const int b = segment_of(plan, B, t);
-        const InstParam &P = d.ip[b];
-        const int64_t base = ghost ? P.gbase : P.base;
-        const int64_t n = Ncur[b];
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        const int64_t li0 = (t - plan[b]) * kTileA + tid;
-        double xv[kPPT], d0[kPPT], d1[kPPT], d2[kPPT], gv[kPPT];
-#pragma unroll
-        for (int j = 0; j < kPPT; ++j) {      // loads first: kPPT in flight per thread
-            const int64_t li = li0 + (int64_t)j * kThreads;
-            const int64_t i = base + (li < n ? li : 0);
-            xv[j] = E.x0[i];
-            d0[j] = E.D[i];
-            d1[j] = E.D[ds + i];
-            d2[j] = E.D[2 * ds + i];
+    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < (int64_t)d.B * 3;
+         q += (int64_t)gridDim.x * kThreads) {
+        const int64_t b = q / 3, c = q - b * 3;
+        int64_t *hi = d.dTq + b * 6 * d.max_bins + (2 * c) * d.max_bins;
+        int64_t *lo = hi + d.max_bins;
+        const double *gb = g + b * nbins;
+        double acc = 0.0;
+        for (int j = 0; j < nbins; ++j) {
+            acc = acc + gb[j] * fx_value(hi[j], (uint64_t)lo[j]);
+            hi[j] = 0;
+            lo[j] = 0;
         }
-#pragma unroll
-        for (int j = 0; j < kPPT; ++j) {      // then the bins' cotangents
-            const double q = (xv[j] - lo) / dxb;
-            const bool in = li0 + (int64_t)j * kThreads < n && q >= 0.0 && q < (double)nbins;
-            gv[j] = in ? g[(int64_t)b * nbins + (int64_t)q] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < kPPT; ++j) {      // accumulated in slot order
-            const double q = (xv[j] - lo) / dxb;
-            if (li0 + (int64_t)j * kThreads >= n || !(q >= 0.0 && q < (double)nbins)) continue;
-            a0 += d0[j] * gv[j];
-            a1 += d1[j] * gv[j];
-            a2 += d2[j] * gv[j];
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            a0 += __shfl_down(a0, o, 64);
-            a1 += __shfl_down(a1, o, 64);
-            a2 += __shfl_down(a2, o, 64);
-        }
-        if (lane == 0) { s_sum[0][wv] = a0; s_sum[1][wv] = a1; s_sum[2][wv] = a2; }
-        __syncthreads();
-        if (tid < 3) {
-            double v = 0.0;
-            for (int q = 0; q < kThreads / 64; ++q) v += s_sum[tid][q];
-            atomicAdd(&acc[(int64_t)b * 3 + tid], v);
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_vjp_out(Dev d, double dxb, double *acc, double *out)
-{
-    for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < (int64_t)d.B * 3;
-         g += (int64_t)gridDim.x * kThreads) {
-        const double denom = (double)d.ip[g / 3].N0 * dxb;
-        out[g] = acc[g] / denom;
-        acc[g] = 0.0;
+        out[q] = acc / ((double)d.ip[b].N0 * dxb);
     }
 }
 

@@ -36,7 +36,7 @@ constexpr int kMaxGrid = 8192;          // blocks of a persistent launch (per-bl
 // use the tangent kernel, hence kTileB.
 constexpr int fam_tile(int dim, bool tangent) { return (dim == 1 && !tangent) ? 2 * kThreads : kTileB; }
 
-enum : uint32_t { kErrCapacity = 1u, kErrDepth = 2u };
+enum : uint32_t { kErrCapacity = 1u, kErrDepth = 2u, kErrRange = 4u };
 
 // tally slots per instance
 enum : int {
@@ -143,13 +143,14 @@ struct Dev {
                                 // [kXcd - 1][2][B][Nh] of ntil; null when not used
     int64_t *off;               // [B][Nh] exclusive prefix of |n_nu|, bit 62 = negative cell
     int32_t *occ;               // [B][Nh] occupancy (tangents)
-    double *Tcell;              // [3][B][Nh] tangent sums per cell
+    int64_t *Tq;                // [6][B][Nh] tangent sums per cell in 32.32 fixed point
+                                // (see fx_split): plane 2c high words, 2c + 1 low words
     int32_t *occx;              // with tangents: [kXcd - 1][B][Nh] XCD copies of occ,
-    double *Tcellx;             // and [kXcd - 1][3][B][Nh] of Tcell (see cntx); else null
+    int64_t *Tqx;               // and [kXcd - 1][6][B][Nh] of Tq (see cntx); else null
     int32_t *ntil;              // [2][B][Nh] sp2 bootstrap counts per class
     int64_t *dacc;              // [kXcd][B][max_bins] density accumulator, one per XCD
                                 // (a block flushes into copy blockIdx mod kXcd)
-    double *dTacc;              // [B][3][max_bins] tangent density accumulator
+    int64_t *dTq;               // [B][6][max_bins] tangent density sums (fixed point, as Tq)
     int32_t max_bins;
     // sp2 bootstrap scratch
     uint64_t *bA;               // [cap_total] quantised weight
@@ -458,6 +459,34 @@ __device__ __forceinline__ void block_plan(int64_t *plan, const int64_t *cnt, in
 // instance b is kBinLateCost tileA[b] - (kBinLateCost - kBinSortedCost)
 // srtS[b]; it needs N[b] >= Nsrt[b], which holds because steps only append.
 constexpr int64_t kBinSortedCost = 1, kBinLateCost = 3;
+
+// Tangent sums over cells and bins are exact integer sums in 32.32 fixed
+// point, so that no summation order is singled out: a component D enters as
+// q = trunc(D 2^32), which needs |D| < 2^31 (else, or for a NaN, it adds
+// nothing and false is returned), split as hi = floor(q / 2^32) and
+// lo = q mod 2^32.  Over at most 2^31 particles the high words sum to less
+// than 2^62 and the low words to less than 2^63, so two 64-bit sums per
+// component are exact without carries.
+__device__ __forceinline__ bool fx_split(double D, int64_t &hi, uint64_t &lo)
+{
+    if (!(fabs(D) < 2147483648.0)) {
+        hi = 0;
+        lo = 0;
+        return false;
+    }
+    const int64_t q = (int64_t)(D * 4294967296.0);
+    hi = q >> 32;
+    lo = (uint64_t)q & 0xFFFFFFFFull;
+    return true;
+}
+
+// value of the sum with high-word sum hs and low-word sum ls:
+// (double)floor(Q / 2^32) + (double)(Q mod 2^32) 2^-32, Q = hs 2^32 + ls
+__device__ __forceinline__ double fx_value(int64_t hs, uint64_t ls)
+{
+    const int64_t h = hs + (int64_t)(ls >> 32);
+    return (double)h + (double)(ls & 0xFFFFFFFFull) * 0x1p-32;
+}
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 {

@@ -787,17 +787,17 @@ __global__ __launch_bounds__(kThreads) void k_ghosts(Dev d)
                     G.k0[o] = k[0];
                     G.sg[o] = 0;
                     G.id[o] = id;
-                    G.D[o] = d.Tcell[cbase + c];
-                    G.D[d.gcap_total + o] = d.Tcell[nc + cbase + c];
-                    G.D[2 * d.gcap_total + o] = d.Tcell[2 * nc + cbase + c];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        G.D[q * d.gcap_total + o] = fx_value(d.Tq[(2 * q) * nc + cbase + c],
+                                                             (uint64_t)d.Tq[(2 * q + 1) * nc + cbase + c]);
                 }
                 gi++;
             }
             d.cnt[cbase + c] = 0;
             d.occ[cbase + c] = 0;
-            d.Tcell[cbase + c] = 0.0;
-            d.Tcell[nc + cbase + c] = 0.0;
-            d.Tcell[2 * nc + cbase + c] = 0.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) d.Tq[q * nc + cbase + c] = 0;
         }
         __syncthreads();
     }

@@ -230,20 +230,27 @@ def test_sp2_batched_and_wide(P, O):
     compare(g, r, "sp2 batched", B=3)
 
 
-def _close(a, b, what, rtol=1e-9):
-    scale = max(np.max(np.abs(b)), 1e-300) if np.size(b) else 1.0
-    err = np.max(np.abs(a - b)) if np.size(b) else 0.0
-    assert err <= rtol * scale, f"{what}: max abs err {err:.3e} vs scale {scale:.3e}"
+def _exact(a, b, what):
+    """Tangents and their readouts: bit-identical.  Every sum of tangents is an
+    exact 32.32 fixed-point integer sum on both sides, so the GPU's order of
+    addition cannot show."""
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    if np.array_equal(a, b):
+        return
+    bad = np.flatnonzero(a.ravel() != b.ravel())
+    rel = np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
+    raise AssertionError(f"{what}: {len(bad)} elements differ, first at {bad[:5]} (max rel {rel:.3e})")
 
 
 @pytest.mark.parametrize("strategy,mode", [("sp1", 1), ("sp1", 2), ("sp2", 1)])
 def test_tangent_parity(P, O, strategy, mode):
     """Tangents (sp1 mode 1: likelihood-ratio scores; sp1 mode 2: x0 by
     derivative ghost pairs, which ride in the real ensemble with sign 0 until
-    the next annihilation; sp2: pathwise weight tangents): the real ensemble
-    stays bit-exact, ghosts (integer creation rule) match exactly in count,
-    position and id, and the tangents (order-dependent floating sums per cell)
-    agree to 1e-9 relative."""
+    the next annihilation; sp2: pathwise weight tangents): the real ensemble,
+    the ghosts (count, position, id) and every tangent are bit-exact, before
+    and after annihilations (cell sums of tangents are exact fixed-point
+    sums), and so is the tangent density."""
     cfg = W.gaussian_barrier_small(N0=np.array([5000]), gamma0=0.45, track_tangent=mode,
                                    strategy=strategy)
     g, r = P.Simulation(cfg), O.OracleSim(cfg)
@@ -251,7 +258,7 @@ def test_tangent_parity(P, O, strategy, mode):
     r.step(3)
     say(f"tangent mode {mode}: 3 steps n={r.count()}")
     compare(g, r, f"tangent mode {mode} before annihilation")
-    _close(g.particles()["D"], r.particles()["D"], "real tangents before annihilation")
+    _exact(g.particles()["D"], r.particles()["D"], "real tangents before annihilation")
     g.step(7)
     r.step(7)
     for ep in range(3):
@@ -263,22 +270,22 @@ def test_tangent_parity(P, O, strategy, mode):
         say(f"tangent mode {mode}: epoch {ep} n={r.count()} ghosts={r.count(ghost=True)}")
         compare(g, r, f"tangent real {ep}")
         pg, pr = g.particles(), r.particles()
-        _close(pg["D"], pr["D"], f"real tangents {ep}")
+        _exact(pg["D"], pr["D"], f"real tangents {ep}")
         assert g.count(ghost=True) == r.count(ghost=True)
         gg, gr = g.particles(ghost=True), r.particles(ghost=True)
         assert_same_ensemble(gg, gr, what=f"ghosts {ep}")
-        _close(gg["D"], gr["D"], f"ghost tangents {ep}")
+        _exact(gg["D"], gr["D"], f"ghost tangents {ep}")
     g.step(5)
     r.step(5)
     compare(g, r, "tangent mid-epoch")
-    _close(g.particles(ghost=True)["D"], r.particles(ghost=True)["D"], "ghost tangents mid-epoch")
-    _close(g.density_tangent().cpu().numpy(), r.density_tangent(), "tangent density")
+    _exact(g.particles(ghost=True)["D"], r.particles(ghost=True)["D"], "ghost tangents mid-epoch")
+    _exact(g.density_tangent().cpu().numpy(), r.density_tangent(), "tangent density")
 
 
 def test_density_vjp_and_autograd_match_oracle(P, O):
-    """Backward kernel: g . d rho / d theta from the per-particle tangents equals
-    the oracle's tangent density contracted with g (1e-9 relative); the
-    torch.autograd.Function returns the same gradient."""
+    """Backward kernel: g . d rho / d theta from the per-particle tangents
+    (fixed-point bin sums, contracted with g in bin order) equals the oracle's
+    bit for bit; the torch.autograd.Function returns the same gradient."""
     import torch
     from paper_1709_02121_amd import autograd as A
     cfg = W.gaussian_barrier_small(N0=np.array([4000]), gamma0=0.45, track_tangent=1)
@@ -287,16 +294,19 @@ def test_density_vjp_and_autograd_match_oracle(P, O):
     g = 0.5 * (1 + np.tanh(x / 2.0))
     r = O.OracleSim(cfg)
     r.run(30, 10)
-    ref = r.density_tangent()[0] @ g
+    ref = r.density_vjp(g)[0]
+    # and the contraction is the tangent density's, to rounding
+    J = r.density_tangent()[0]
+    assert np.all(np.abs(ref - J @ g) <= 1e-12 * (np.abs(J) @ np.abs(g)))
     sim = P.Simulation(cfg)
     sim.run(30, 10)
     got = sim.density_vjp(torch.tensor(g)).cpu().numpy()[0]
-    _close(got, ref, "vjp")
+    _exact(got, ref, "vjp")
     theta = torch.tensor([0.3, 1.0, 0.0], dtype=torch.float64, requires_grad=True)
     rho = A.density(theta, cfg, steps=30, annihilate_every=10, snapshot_every=10)
     assert np.array_equal(rho.detach().cpu().numpy(), r.density()[0])
     (rho * torch.tensor(g, device=rho.device)).sum().backward()
-    _close(theta.grad.numpy(), ref, "autograd")
+    _exact(theta.grad.numpy(), ref, "autograd")
 
 
 def test_snapshot_restore_continues_exactly(P, O):
@@ -311,8 +321,7 @@ def test_snapshot_restore_continues_exactly(P, O):
     for ghost in (False, True):
         pa, pb = a.particles(ghost=ghost), b.particles(ghost=ghost)
         assert_same_ensemble(pa, pb, what=f"restore ghost={ghost}")
-        # tangents are summed per cell with floating atomics: equal to rounding
-        _close(pa["D"], pb["D"], f"restore tangents ghost={ghost}")
+        _exact(pa["D"], pb["D"], f"restore tangents ghost={ghost}")
     r = O.OracleSim(cfg)
     r.run(30, 10)
     compare(b, r, "restore vs oracle")
@@ -343,8 +352,8 @@ def test_restore_into_used_handle(P, O):
     assert b.count(ghost=True) == r.count(ghost=True)
     gg, gr = b.particles(ghost=True), r.particles(ghost=True)
     assert_same_ensemble(gg, gr, what="ghosts after restore into a used handle")
-    _close(gg["D"], gr["D"], "ghost tangents after restore into a used handle")
-    _close(b.particles()["D"], r.particles()["D"], "tangents after restore into a used handle")
+    _exact(gg["D"], gr["D"], "ghost tangents after restore into a used handle")
+    _exact(b.particles()["D"], r.particles()["D"], "tangents after restore into a used handle")
 
 
 def test_autotune_keeps_results(P, O):

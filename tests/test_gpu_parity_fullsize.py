@@ -58,10 +58,15 @@ def stats_equal(g, r, what, b=0, rb=None):
         assert sg[k] == so[k], (what, b, k, sg[k], so[k])
 
 
-def close(a, b, what, rtol=1e-9):
-    scale = max(np.max(np.abs(b)), 1e-300) if np.size(b) else 1.0
-    err = np.max(np.abs(a - b)) if np.size(b) else 0.0
-    assert err <= rtol * scale, f"{what}: max abs err {err:.3e} vs scale {scale:.3e}"
+def exact(a, b, what):
+    """Tangents: bit-identical (cell and bin sums are exact fixed-point sums)."""
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    if np.array_equal(a, b):
+        return
+    bad = np.flatnonzero(a.ravel() != b.ravel())
+    rel = np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
+    raise AssertionError(f"{what}: {len(bad)} elements differ, first at {bad[:5]} (max rel {rel:.3e})")
 
 
 def epoch_parity(P, O, cfg, steps, what, tangents=False):
@@ -77,19 +82,26 @@ def epoch_parity(P, O, cfg, steps, what, tangents=False):
     pg, pr = g.particles(), r.particles()
     same(pg, pr, f"{what} steps")
     if tangents:
-        close(pg["D"], pr["D"], f"{what} tangents")
+        exact(pg["D"], pr["D"], f"{what} tangents")
     del pg, pr
     g.annihilate()
     r.annihilate()
     say(f"{what}: annihilated n={r.count()}")
     stats_equal(g, r, f"{what} annihilation")
-    same(g.particles(), r.particles(), f"{what} annihilation")
+    pg, pr = g.particles(), r.particles()
+    same(pg, pr, f"{what} annihilation")
     if tangents:
+        exact(pg["D"], pr["D"], f"{what} tangents after annihilation")
+        del pg, pr
         assert g.count(ghost=True) == r.count(ghost=True)
         gg, gr = g.particles(ghost=True), r.particles(ghost=True)
         same(gg, gr, f"{what} ghosts")
-        close(gg["D"], gr["D"], f"{what} ghost tangents")
-        close(g.density_tangent().cpu().numpy(), r.density_tangent(), f"{what} tangent density")
+        exact(gg["D"], gr["D"], f"{what} ghost tangents")
+        exact(g.density_tangent().cpu().numpy(), r.density_tangent(), f"{what} tangent density")
+        gv = np.cos(np.linspace(0.0, 3.0, cfg["density"]["nbins"]))
+        exact(g.density_vjp(__import__("torch").tensor(gv)).cpu().numpy(), r.density_vjp(gv), f"{what} vjp")
+    else:
+        del pg, pr
     assert np.array_equal(g.density().cpu().numpy(), r.density())
     say(f"{what}: done")
 

@@ -116,3 +116,46 @@ def test_sp2_tangent_mean_equals_sp1(oracle_mod):
     se = np.sqrt(a.var(0, ddof=1) / R + b.var(0, ddof=1) / R)
     assert np.all(np.abs(a.mean(0) - b.mean(0)) < 4.5 * se), (a.mean(0), b.mean(0), se)
     assert np.all(np.abs(b.mean(0)) > 10 * b.std(0, ddof=1) / np.sqrt(R))
+
+
+def test_tangent_sums_are_exact_fixed_point_sums(oracle_mod):
+    """Cell and bin sums of tangents are exact sums of trunc(D 2^32) (32.32
+    fixed point), read back as floor(Q / 2^32) + (Q mod 2^32) 2^-32: checked
+    here with Python integers on the oracle's own per-particle tangents, for
+    the tangent density and the backward contraction, and against the
+    floating sums within the truncation bound n 2^-32 per bin."""
+    from fractions import Fraction
+    import math
+    cfg = W.gaussian_barrier_small(N0=np.array([3000]), gamma0=0.45, track_tangent=1, seed=3)
+    s = oracle_mod.OracleSim(cfg)
+    s.run(25, 10)
+    assert s.stats()["range_errors"] == 0
+    nb, lo, hi = 60, -30.0, 30.0
+    dx = (hi - lo) / nb
+    parts = [s.particles(), s.particles(ghost=True)]
+    Q = np.zeros((3, nb), dtype=object)
+    Q[:] = 0
+    fl = np.zeros((3, nb))
+    cnt = np.zeros(nb, dtype=np.int64)
+    for p in parts:
+        q = (p["x"][0] - lo) / dx
+        for i in np.flatnonzero((q >= 0) & (q < nb)):
+            j = int(q[i])
+            cnt[j] += 1
+            for c in range(3):
+                D = float(p["D"][i, c])
+                Q[c, j] += math.trunc(Fraction(D) * 2**32)
+                fl[c, j] += D
+    val = np.array([[float(Q[c, j] // 2**32) + float(Q[c, j] % 2**32) * 2.0**-32 for j in range(nb)]
+                    for c in range(3)])
+    denom = 3000 * dx
+    J = s.density_tangent(nbins=nb, lo=lo, hi=hi)[0]
+    assert np.array_equal(J, val / denom)
+    assert np.all(np.abs(val - fl) <= cnt * 2.0**-32 + 1e-12 * np.abs(fl) + 1e-300)
+    g = np.sin(np.arange(nb) * 0.3)
+    got = s.density_vjp(g, nbins=nb, lo=lo, hi=hi)[0]
+    for c in range(3):
+        acc = 0.0
+        for j in range(nb):
+            acc = acc + g[j] * val[c, j]
+        assert got[c] == acc / denom
