@@ -10,16 +10,22 @@ free flight, jumps and offspring families); every 10th step is followed by the
 annihilation and the density readout, which are inside the timed region.
 value = sum over timed steps of the particles held at the start of the step,
 divided by the wall time.  Inputs are resident on the GPU before timing starts.
-The timed region carries no instrumentation; the same number of steps is then
-run again with HIP events around every stage (on the launch stream), and the
-per-kernel durations of the roofline entry come from that second pass.
+
+Roofline: the whole step (its five launches) against HBM, with the survey's
+model of 34 algorithmic bytes per particle-step (read x, k, id; write x; the
+offspring records and the parents' signs), timed by HIP events around every
+step on the launch stream inside the timed region.  The same steps are then
+run again with events around every kernel, for the per-kernel split
+(`kernels`, with the dominant kernel named).
 
 Printed: one JSON line on stdout (everything else goes to stderr).
 """
 import argparse
 import hashlib
 import json
+import multiprocessing as mp
 import os
+import platform
 import sys
 import time
 
@@ -30,6 +36,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 ANN_EVERY = 10
+STEP_MODEL_BYTES = 34   # algorithmic bytes per particle-step of the 1D sp1 step
+STEP_KERNELS = (("stream", "k_stream"), ("events", "k_events"), ("family", "k_family"),
+                ("place", "k_place_records"), ("close", "k_close_family"))
+TRAFFIC_SOURCES = ("wbrw_stream.hpp", "wbrw_step.hpp", "wbrw_math.hpp", "wbrw_dev.hpp")
 
 
 def log(*a):
@@ -43,13 +53,20 @@ def stream_bytes_per_particle_step(dim):
 
 
 def run_form(P, torch, cfg, steps, warmup, every=ANN_EVERY, use_graph=False, density=True,
-             autotune=False):
+             autotune=False, adjoint=None):
     """Runs warmup (and the autotuner), then `steps` timed steps; returns a dict
-    of measurements."""
+    of measurements.  adjoint: {"snapshot_every": S} times the differentiation
+    form: forward steps with a checkpoint every S steps, then the density and
+    its backward pass (the vector-Jacobian kernel) inside the timed region."""
     s = torch.cuda.Stream()
     sim = P.Simulation(cfg, stream=s)
     done = 0
     tuned = None
+    snap_every = (adjoint or {}).get("snapshot_every", 0)
+    nbins = cfg["density"]["nbins"]
+    g = torch.linspace(-1.0, 1.0, nbins, dtype=torch.float64, device="cuda").reshape(1, nbins)
+    g = g.expand(sim.B, nbins).contiguous()
+    held = {}
 
     def advance(n):
         nonlocal done
@@ -58,8 +75,10 @@ def run_form(P, torch, cfg, steps, warmup, every=ANN_EVERY, use_graph=False, den
             done += 1
             if every and done % every == 0:
                 sim.annihilate()
-                if density:
+                if density and not adjoint:
                     sim.density()
+            if snap_every and done % snap_every == 0:
+                held["snap"] = sim.snapshot()      # the latest checkpoint is kept
 
     advance(warmup)
     if autotune:
@@ -70,46 +89,38 @@ def run_form(P, torch, cfg, steps, warmup, every=ANN_EVERY, use_graph=False, den
             advance(1)
     s.synchronize()
 
-    def timed(n):
+    def timed(n, marks):
         ps0 = sum(sim.stats(b)["particle_steps"] for b in range(sim.B))
+        if marks:
+            sim.profile(True, steps_only=(marks == "steps"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if use_graph:
             sim.run(n, every, use_graph=True)
         else:
             advance(n)
+        if adjoint:
+            sim.density()
+            held["grad"] = sim.density_vjp(g)
         s.synchronize()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return wall, sum(sim.stats(b)["particle_steps"] for b in range(sim.B)) - ps0
+        prof = sim.profile_read() if marks else None
+        if marks:
+            sim.profile(False)
+        return wall, sum(sim.stats(b)["particle_steps"] for b in range(sim.B)) - ps0, prof
 
-    # the timed region: exactly `steps` steps with no instrumentation
-    wall, ps = timed(steps)
-    # the same number of steps again with HIP events around every stage on
-    # the launch stream, for the per-kernel durations
-    sim.profile(True)
-    _, ps_prof = timed(steps)
-    prof = sim.profile_read()
-    sim.profile(False)
+    # the timed region: exactly `steps` steps, with two HIP events per step
+    # (none inside a graph replay)
+    wall, ps, step_prof = timed(steps, None if use_graph else "steps")
+    # the same number of steps again with HIP events around every kernel
+    _, ps_prof, prof = timed(steps, "all")
     stats = [sim.stats(b) for b in range(sim.B)]
     out = {"wall_s": wall, "particle_steps": int(ps), "rate": ps / wall,
-           "prof_particle_steps": int(ps_prof),
-           "n_end": int(sum(st["n"] for st in stats)), "profile": prof, "sim": sim,
-           "tuned": tuned}
+           "prof_particle_steps": int(ps_prof), "steps": steps,
+           "n_end": int(sum(st["n"] for st in stats)), "profile": prof, "step_profile": step_prof,
+           "sim": sim, "tuned": tuned}
     return out
-
-
-def roofline_of(res, dim):
-    ms, launches = res["profile"]["stream"]
-    if launches == 0 or ms <= 0:
-        return None
-    bytes_total = stream_bytes_per_particle_step(dim) * res["prof_particle_steps"]
-    achieved = bytes_total / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": "k_stream",
-            "avg_launch_us": round(ms * 1e3 / launches, 3),
-            "bytes_per_launch": int(bytes_total / launches),
-            "bytes_per_particle_step": stream_bytes_per_particle_step(dim)}
 
 
 def copy_rate(torch):
@@ -136,44 +147,156 @@ def copy_rate(torch):
     return best
 
 
-def measured_traffic(dim, bytes_per_launch):
-    """HBM bytes per launch from the committed counter summary of k_stream,
-    only if that summary was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_stream_traffic.json")
+def measured_traffic():
+    """Per-kernel HBM bytes per particle-step of the step from the committed
+    counter summary, only if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "step_traffic_gaussian_barrier_1e7.json")
     if not os.path.exists(path):
         return None
     info = json.load(open(path))
     h = hashlib.sha256()
-    for f in ("wbrw_stream.hpp", "wbrw_math.hpp", "wbrw_dev.hpp"):
+    for f in TRAFFIC_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_1709_02121_amd", "csrc", f), "rb").read())
     if info.get("source_sha256") != h.hexdigest():
         return None
-    per = info.get("hbm_bytes_per_particle_step")
-    if per is None:
+    return info.get("hbm_bytes_per_particle_step")
+
+
+def step_roofline(res):
+    """Roofline of the whole step: STEP_MODEL_BYTES per particle-step over the
+    mean step time of the timed region (HIP events around each step), with
+    the per-kernel split of the profiled pass."""
+    sp = res["step_profile"]
+    if not sp or sp["step"][1] == 0:
         return None
-    return int(per * bytes_per_launch / stream_bytes_per_particle_step(dim))
+    step_ms, nsteps = sp["step"]
+    ps_step = res["particle_steps"] / nsteps
+    avg_step_s = step_ms * 1e-3 / nsteps
+    bytes_step = STEP_MODEL_BYTES * ps_step
+    achieved = bytes_step / avg_step_s / 1e9
+    prof = res["profile"]
+    kern = {}
+    total = sum(prof[st][0] for st, _ in STEP_KERNELS)
+    for st, name in STEP_KERNELS:
+        ms, n = prof[st]
+        if n == 0:
+            continue
+        kern[name] = {"avg_launch_us": round(ms * 1e3 / n, 2), "share": round(ms / total, 4)}
+    ms_s, n_s = prof["stream"]
+    if n_s:
+        b = stream_bytes_per_particle_step(1) * res["prof_particle_steps"] / n_s
+        a = b / (ms_s * 1e-3 / n_s) / 1e9
+        kern["k_stream"].update({"bytes_per_launch": int(b), "bytes_per_particle_step":
+                                 stream_bytes_per_particle_step(1), "achieved": round(a, 1),
+                                 "frac": round(a / HBM_PEAK_GBS, 4)})
+    dominant = max(kern, key=lambda k: kern[k]["avg_launch_us"])
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+           "scope": "whole step: k_stream, k_events, k_family, k_place_records, k_close_family",
+           "kernel": dominant, "dominant_kernel": dominant,
+           "avg_step_us": round(avg_step_s * 1e6, 2), "steps_timed": nsteps,
+           "particle_steps_per_step": int(ps_step), "bytes_per_particle_step": STEP_MODEL_BYTES,
+           "bytes_per_step": int(bytes_step), "kernels": kern}
+    per = measured_traffic()
+    if per:
+        out["traffic"] = int(sum(per.values()) * ps_step)
+        out["traffic_per_kernel"] = {k: int(v * ps_step) for k, v in per.items()}
+    return out
 
 
-def cpu_baseline():
-    """The FP64 oracle on one host core: the headline workload's physics and
-    grid with 1e6 initial particles for 100 steps (annihilation every 10)."""
+def _oracle_leg(args):
+    """One host process: the oracle on one share of the CPU-baseline sample."""
+    n0, steps, offset = args
     import workloads as W
     from oracle import oracle as O
-    O.build()
-    cfg = W.scaled(W.gaussian_barrier_large("sp1"), N0=1_000_000)
+    cfg = W.scaled(W.gaussian_barrier_large("sp1"), N0=n0, instance_offset=offset)
     sim = O.OracleSim(cfg)
     ps = 0
     t0 = time.perf_counter()
-    for s in range(100):
+    for s in range(steps):
         ps += sim.count()
         sim.step(1)
         if (s + 1) % ANN_EVERY == 0:
             sim.annihilate()
             sim.density()
-    wall = time.perf_counter() - t0
-    return {"value": round(ps / wall, 1), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "Gaussian barrier, 2000x512 grid, 1e6 initial particles, 100 steps with "
-                      "annihilation + density every 10 (%.3g particle-steps in %.1f s)" % (ps, wall)}
+    return ps, time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline():
+    """The FP64 oracle on the host: one core over the headline workload's
+    physics and grid with 1e6 initial particles for 100 steps (annihilation
+    and density every 10); then every core of the box's share at once, each
+    process running its own instance (own random keys) of 1e6 / P particles,
+    the same per-particle work."""
+    from oracle import oracle as O
+    O.build()
+    ps, wall = _oracle_leg((1_000_000, 100, 0))
+    out = {"value": round(ps / wall, 1), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "sample": "Gaussian barrier, 2000x512 grid, 1e6 initial particles, 100 steps with "
+                     "annihilation + density every 10 (%.3g particle-steps in %.1f s)" % (ps, wall),
+           "cpu": cpu_model()}
+    P = max(1, min(16, os.cpu_count() or 1))
+    if P > 1:
+        ctx = mp.get_context("spawn")
+        t0 = time.perf_counter()
+        with ctx.Pool(P) as pool:
+            legs = pool.map(_oracle_leg, [(1_000_000 // P, 100, p) for p in range(P)])
+        wall_all = time.perf_counter() - t0
+        ps_all = sum(l[0] for l in legs)
+        out["all_cores"] = {"value": round(ps_all / wall_all, 1), "cores": P,
+                            "sample": f"{P} processes, each 1e6/{P} particles of the same workload "
+                                      f"(own instance key), 100 steps; {ps_all:.3g} particle-steps "
+                                      f"in {wall_all:.1f} s of wall time"}
+    return out
+
+
+def run_forms(P, torch, W, args):
+    """The batched, differentiation, sp2 and 4D forms (--forms selects)."""
+    forms = {}
+    snap = {"snapshot_every": 50}
+    for name, maker, steps, warm, extra in (
+            ("sp2", lambda: W.gaussian_barrier_large("sp2"), 50, 10, {}),
+            ("batched_256", lambda: W.batched_barriers(), 100, 10,
+             {"use_graph": True, "autotune": True}),
+            ("fwd_adjoint", lambda: W.differentiation(), 50, 10, {"adjoint": snap}),
+            ("fwd_adjoint_x0_deriv_pairs", lambda: W.differentiation(track_tangent=2), 50, 10,
+             {"adjoint": snap}),
+            ("fwd_adjoint_sp2", lambda: W.differentiation(strategy="sp2"), 50, 10, {"adjoint": snap}),
+            ("helium_4d", lambda: W.helium_soft_coulomb(), 10, 0, {})):
+        if args.forms != "all" and name not in args.forms.split(","):
+            continue
+        try:
+            torch.cuda.empty_cache()
+            r = run_form(P, torch, maker(), steps, warm, **extra)
+            r.pop("sim")
+            forms[name] = {"value": round(r["rate"], 1), "steps": steps,
+                           "particle_steps": r["particle_steps"], "n_end": r["n_end"]}
+            if extra.get("adjoint"):
+                forms[name]["timed"] = ("forward steps (annihilation every 10, a checkpoint every "
+                                        "50 steps), then the density and its backward pass")
+            if r["tuned"]:
+                forms[name]["autotuned"] = r["tuned"]
+            if name == "helium_4d":
+                ms, n = r["profile"]["stream"]
+                if n:
+                    a = stream_bytes_per_particle_step(2) * r["prof_particle_steps"] / (ms * 1e-3) / 1e9
+                    forms[name]["stream_frac_hbm"] = round(a / HBM_PEAK_GBS, 4)
+            log(f"{name}: {r['rate']:.4g} particle-steps/s")
+        except Exception as e:   # report, never hide, a form that failed
+            forms[name] = {"error": str(e)[:300]}
+            log(f"{name}: FAILED {e}")
+
+    return forms
 
 
 def main():
@@ -187,12 +310,21 @@ def main():
                     help="comma-separated forms to run besides the main line (default: all)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first copy 1 GiB device to device (a reference for HBM byte counters)")
+    ap.add_argument("--no-main", action="store_true",
+                    help="skip the headline workload (to profile the forms alone); value is then null")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "path is a design (histogram merge over RCCL) that this build does not run.",
               file=sys.stderr)
         sys.exit(2)
+
+    # the host baseline first: its worker processes start before this process
+    # has touched the GPU
+    cpu = None if args.no_cpu else cpu_baseline()
+    if cpu:
+        log(f"cpu baseline: {cpu['value']:.4g} particle-steps/s on 1 core ({cpu['cpu']})"
+            + (f"; {cpu['all_cores']['value']:.4g} on {cpu['all_cores']['cores']}" if "all_cores" in cpu else ""))
 
     import torch
 
@@ -215,52 +347,30 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read + 1 GiB written")
         del a, b
+    if args.no_main:
+        forms = run_forms(P, torch, W, args)
+        print(json.dumps({"metric": "forms only (profiling run)", "value": None, "forms": forms}), flush=True)
+        return
     cfg = W.gaussian_barrier_large("sp1")
     main_res = run_form(P, torch, cfg, args.steps, args.warmup)
-    roof = roofline_of(main_res, 1)
+    roof = step_roofline(main_res)
     if roof is not None:
-        roof["traffic"] = measured_traffic(1, roof["bytes_per_launch"])
         cr = copy_rate(torch)
         roof["attainable"] = {"what": "plain 1 GiB device copy, read + write, same GPU",
                               "GBps": round(cr, 1), "frac": round(roof["achieved"] / cr, 4)}
-    step_ms = main_res["profile"]["stream"][0] + main_res["profile"]["family"][0]
     log(f"sp1 1e7: {main_res['rate']:.4g} particle-steps/s, n_end={main_res['n_end']}, "
         f"profile={ {k: (round(v[0], 3), v[1]) for k, v in main_res['profile'].items()} }")
+    if roof:
+        log(f"step: {roof['avg_step_us']} us, {roof['achieved']} GB/s ({roof['frac']} of peak), "
+            f"dominant {roof['dominant_kernel']}")
     main_res.pop("sim")
 
+    step_ms = sum(main_res["profile"][st][0] for st, _ in STEP_KERNELS)
     forms = {"plain_sp1": {"value": round(main_res["rate"], 1),
                            "step_kernels_only": round(main_res["prof_particle_steps"] / (step_ms * 1e-3), 1)
                            if step_ms > 0 else None}}
     if not args.no_forms:
-        for name, maker, steps, warm in (
-                ("sp2", lambda: W.gaussian_barrier_large("sp2"), 50, 10),
-                ("batched_256", lambda: W.batched_barriers(), 100, 10),
-                ("fwd_adjoint", lambda: W.differentiation(), 50, 10),
-                ("fwd_adjoint_x0_deriv_pairs", lambda: W.differentiation(track_tangent=2), 50, 10),
-                ("fwd_adjoint_sp2", lambda: W.differentiation(strategy="sp2"), 50, 10),
-                ("helium_4d", lambda: W.helium_soft_coulomb(), 10, 0)):
-            if args.forms != "all" and name not in args.forms.split(","):
-                continue
-            try:
-                torch.cuda.empty_cache()
-                batched = name == "batched_256"
-                r = run_form(P, torch, maker(), steps, warm, use_graph=batched, autotune=batched)
-                r.pop("sim")
-                forms[name] = {"value": round(r["rate"], 1), "steps": steps,
-                               "particle_steps": r["particle_steps"], "n_end": r["n_end"]}
-                if r["tuned"]:
-                    forms[name]["autotuned_grid"] = r["tuned"]
-                if name == "helium_4d":
-                    rf = roofline_of(r, 2)
-                    forms[name]["stream_frac_hbm"] = rf["frac"] if rf else None
-                log(f"{name}: {r['rate']:.4g} particle-steps/s")
-            except Exception as e:   # report, never hide, a form that failed
-                forms[name] = {"error": str(e)[:300]}
-                log(f"{name}: FAILED {e}")
-
-    cpu = None if args.no_cpu else cpu_baseline()
-    if cpu:
-        log(f"cpu baseline: {cpu['value']:.4g} particle-steps/s on {cpu['cores']} core")
+        forms.update(run_forms(P, torch, W, args))
 
     line = {
         "metric": "particle-steps/s at 1 GPU (plain vs batched vs fwd+adjoint) and % HBM roofline",

@@ -162,7 +162,11 @@ enum wbrw_stage {
     WBRW_STAGE_BOOTSTRAP = 5, /* sp2 bootstrap filter */
     WBRW_STAGE_DENSITY = 6,   /* density readout */
     WBRW_STAGE_GHOST = 7,     /* tangent ghosts and ghost steps */
-    WBRW_STAGE_COUNT = 8
+    WBRW_STAGE_EVENTS = 8,    /* step: ordered event list */
+    WBRW_STAGE_PLACE = 9,     /* step: record placement */
+    WBRW_STAGE_CLOSE = 10,    /* step: one-block bookkeeping */
+    WBRW_STAGE_STEP = 11,     /* a whole step, all of its launches (brackets the others) */
+    WBRW_STAGE_COUNT = 12
 };
 
 typedef struct wbrw_handle *wbrw_t;
@@ -280,8 +284,10 @@ int wbrw_export(wbrw_t h, int32_t b, int32_t ghost, int64_t n, double *x, double
 int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen);
 
 /* Per-stage timing with hip events recorded on the handle's stream around
- * every kernel of a stage (enable != 0 starts a fresh measurement; enable == 0
- * stops recording).  Not used inside graph capture. */
+ * every kernel of a stage and around every whole step (enable == 1 starts a
+ * fresh measurement; enable == 2 the same with whole steps marked only, two
+ * events per step; enable == 0 stops recording).  Not used inside graph
+ * capture. */
 int wbrw_profile(wbrw_t h, int32_t enable);
 
 /* Synchronises, then writes for each stage s < WBRW_STAGE_COUNT the summed

@@ -377,10 +377,14 @@ class Simulation:
     def synchronize(self):
         self.stream.synchronize()
 
-    STAGES = ("stream", "family", "bin", "scan", "regen", "bootstrap", "density", "ghost")
+    STAGES = ("stream", "family", "bin", "scan", "regen", "bootstrap", "density", "ghost",
+              "events", "place", "close", "step")
 
-    def profile(self, enable=True):
-        _check(lib().wbrw_profile(self.h, int(bool(enable))), "wbrw_profile")
+    def profile(self, enable=True, steps_only=False):
+        """Start (enable) or stop HIP-event timing on the handle's stream: every
+        stage and whole step, or whole steps only (two events per step)."""
+        mode = 0 if not enable else (2 if steps_only else 1)
+        _check(lib().wbrw_profile(self.h, mode), "wbrw_profile")
 
     def profile_read(self):
         """{stage: (total ms, launches)} of the kernels timed since profile(True)."""

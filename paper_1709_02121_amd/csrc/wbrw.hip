@@ -329,11 +329,12 @@ struct wbrw_handle {
     int graph_every = -1;
     int sticky = WBRW_OK;
     int64_t host_step = 0;   // steps enqueued so far (mirror of the device counter)
-    bool prof = false;
+    int prof = 0;   // 1: every stage and step marked; 2: whole steps only
     struct Mark { int stage; hipEvent_t a, b; };
     std::vector<Mark> marks;
     int open_stage = -1;
     hipEvent_t open_ev = nullptr;
+    hipEvent_t step_ev = nullptr;    // start of the step being enqueued (WBRW_STAGE_STEP)
 };
 
 namespace {
@@ -444,7 +445,7 @@ int launch_check()
 // per-stage profiling marks (no-ops unless wbrw_profile enabled them)
 void stage_begin(wbrw_t h, int stage)
 {
-    if (!h->prof) return;
+    if (h->prof != 1) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     (void)hipEventRecord(e, h->stream);
@@ -454,13 +455,33 @@ void stage_begin(wbrw_t h, int stage)
 
 void stage_end(wbrw_t h)
 {
-    if (!h->prof || h->open_stage < 0) return;
+    if (h->prof != 1 || h->open_stage < 0) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     (void)hipEventRecord(e, h->stream);
     h->marks.push_back({h->open_stage, h->open_ev, e});
     h->open_stage = -1;
     h->open_ev = nullptr;
+}
+
+// the outer mark of a whole step (the stage marks above nest inside it)
+void step_begin(wbrw_t h)
+{
+    if (!h->prof) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, h->stream);
+    h->step_ev = e;
+}
+
+void step_end(wbrw_t h)
+{
+    if (!h->prof || !h->step_ev) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, h->stream);
+    h->marks.push_back({WBRW_STAGE_STEP, h->step_ev, e});
+    h->step_ev = nullptr;
 }
 
 // Ordered scan of |n_nu| (see k_scan_sums): tile sums, their one-block scan
@@ -483,7 +504,9 @@ void enqueue_step_dim(wbrw_t h)
     stage_begin(h, WBRW_STAGE_STREAM);
     hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
+    stage_begin(h, WBRW_STAGE_EVENTS);
     hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS] + 1), dim3(kThreads), 0, s, d, 0, h->grid[G_STREAM]);
+    stage_end(h);
     stage_begin(h, WBRW_STAGE_FAMILY);
     if (h->strategy == WBRW_SP2 && tan)
         hipLaunchKernelGGL((k_family<DIM, true, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
@@ -494,6 +517,7 @@ void enqueue_step_dim(wbrw_t h)
     else
         hipLaunchKernelGGL((k_family<DIM, false, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
+    stage_begin(h, WBRW_STAGE_PLACE);
     if (h->strategy == WBRW_SP2 && tan)
         hipLaunchKernelGGL((k_place_records<DIM, true, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
     else if (h->strategy == WBRW_SP2)
@@ -502,7 +526,10 @@ void enqueue_step_dim(wbrw_t h)
         hipLaunchKernelGGL((k_place_records<DIM, false, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
     else
         hipLaunchKernelGGL((k_place_records<DIM, false, false>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
+    stage_end(h);
+    stage_begin(h, WBRW_STAGE_CLOSE);
     hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 0, tan ? 0 : 1, h->grid[G_FAMILY]);
+    stage_end(h);
     if (tan) {
         // ghosts (weight 0) branch by the sp1 rule in either strategy
         stage_begin(h, WBRW_STAGE_GHOST);
@@ -517,7 +544,9 @@ void enqueue_step_dim(wbrw_t h)
 
 int enqueue_step(wbrw_t h)
 {
+    step_begin(h);
     if (h->dim == 1) enqueue_step_dim<1>(h); else enqueue_step_dim<2>(h);
+    step_end(h);
     h->host_step += 1;
     return launch_check();
 }
@@ -929,8 +958,8 @@ int wbrw_run(wbrw_t h, int32_t nsteps, int32_t every, int32_t use_graph)
         if (h->graph_every != every) {
             if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
             hipGraph_t g;
-            const bool prof = h->prof;
-            h->prof = false;
+            const int prof = h->prof;
+            h->prof = 0;
             const int64_t hs = h->host_step;
             HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
             int rc = WBRW_OK;
@@ -1311,7 +1340,7 @@ int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen)
     for (int per : {1, 2, 3, 4, 6, 8, 12, 16})
         if (per <= std::max(occ_s, occ_f)) cand.push_back(per);
     if (cand.empty()) cand.push_back(1);
-    const bool prof = h->prof;
+    const int prof = h->prof;
     const std::vector<wbrw_handle::Mark> saved = h->marks;
     h->marks.clear();
     double best_s = 1e300, best_f = 1e300;
@@ -1329,12 +1358,12 @@ int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen)
                 HIPCHK(hipMemcpy(tal, h->d.tally + (int64_t)b * kTalCount, sizeof(tal), hipMemcpyDeviceToHost));
                 before += tal[kTalPSteps];
             }
-            h->prof = true;
+            h->prof = 1;
             for (int i = 0; i < steps_per_candidate; ++i) {
                 const int rc = enqueue_step(h);
                 if (rc) { h->prof = prof; return rc; }
             }
-            h->prof = false;
+            h->prof = 0;
             HIPCHK(hipStreamSynchronize(h->stream));
             for (int b = 0; b < h->B; ++b) {
                 HIPCHK(hipMemcpy(tal, h->d.tally + (int64_t)b * kTalCount, sizeof(tal), hipMemcpyDeviceToHost));
@@ -1384,7 +1413,7 @@ int wbrw_profile(wbrw_t h, int32_t enable)
         HIPCHK(hipStreamSynchronize(h->stream));
         drop_marks(h);
     }
-    h->prof = enable != 0;
+    h->prof = enable == 2 ? 2 : (enable != 0 ? 1 : 0);
     return WBRW_OK;
 }
 
