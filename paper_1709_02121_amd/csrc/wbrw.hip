@@ -32,7 +32,7 @@ struct Layout {
     size_t zero_begin = 0, zero_end = 0;   // region cleared at init
     // offsets
     size_t ens[2][8] = {}, gens[2][8] = {};
-    size_t ip = 0, tab[kMaxM] = {}, ctl = 0;
+    size_t ip = 0, tab[kMaxM] = {}, guide[kMaxM] = {}, ctl = 0;
     size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, tileA = 0, Nsrt = 0, srtS = 0, tileB = 0, tileR = 0,
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
            tcA = 0, tcAg = 0, supA = 0, supAg = 0, spart = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, occx = 0, Tqx = 0, off = 0,
@@ -51,6 +51,28 @@ size_t take(size_t &cursor, size_t bytes)
 }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// buckets of a table's guide: the least power of two >= n
+int32_t guide_buckets(int32_t n)
+{
+    int32_t k = 1;
+    while (k < n) k <<= 1;
+    return k;
+}
+
+// guide[i] = the last j < n with cum[j] <= t_i, t_i = (i / kg) cum[n] rounded
+// as the sampler rounds u1 cum[n] (kg a power of two, so i / kg is exact and
+// u1 >= i / kg gives u1 cum[n] >= t_i); cum is non-decreasing
+void build_guide(const std::vector<double> &cum, int32_t n, int32_t kg, std::vector<int32_t> &guide)
+{
+    guide.assign((size_t)kg + 1, 0);
+    int32_t j = 0;
+    for (int32_t i = 0; i <= kg; ++i) {
+        const double t = ((double)i / (double)kg) * cum[n];
+        while (j + 1 < n && cum[j + 1] <= t) ++j;
+        guide[i] = j;
+    }
+}
 
 int validate(const wbrw_config *c)
 {
@@ -207,7 +229,10 @@ Layout make_layout(const wbrw_config *c)
     if (tan) L.gev_idx = take(cur, G * 4);
     L.ip = take(cur, BB * sizeof(InstParam));
     for (int m = 0; m < c->n_components; ++m)
-        if (c->comp[m].kind == WBRW_KERNEL_TABLE) L.tab[m] = take(cur, ((size_t)c->comp[m].table_n + 1) * 8);
+        if (c->comp[m].kind == WBRW_KERNEL_TABLE) {
+            L.tab[m] = take(cur, ((size_t)c->comp[m].table_n + 1) * 8);
+            L.guide[m] = take(cur, ((size_t)guide_buckets(c->comp[m].table_n) + 1) * 4);
+        }
     L.off = take(cur, BB * Nh * 8);
     if (c->init_hist) L.hist = take(cur, BB * Nh * 8);
     bool alg4 = false;
@@ -750,6 +775,8 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         // xi_m = (2/(pi hbar)) sum_j |F[V](2 q_j)| dq
         xi_tab[m] = ((2.0 * cm[q.table_n]) * dq) / (0x1.921fb54442d18p+1 * cfg->hbar);
         d.tab[m].cum = at<double>(w, L.tab[m]);
+        d.tab[m].guide = at<int32_t>(w, L.guide[m]);
+        d.tab[m].kg = guide_buckets(q.table_n);
         d.tab[m].n = q.table_n;
         d.tab[m].q_lo = q.q_lo;
         d.tab[m].dq = dq;
@@ -881,10 +908,14 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     if (L.xitab &&
         hipMemcpyAsync((void *)d.xi_tab, xitabs.data(), 8 * xitabs.size(), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(WBRW_EHIP);
-    for (int m = 0; m < h->M; ++m)
-        if (cfg->comp[m].kind == WBRW_KERNEL_TABLE &&
-            hipMemcpyAsync((void *)d.tab[m].cum, cums[m].data(), 8 * cums[m].size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    std::vector<std::vector<int32_t>> guides(kMaxM);
+    for (int m = 0; m < h->M; ++m) {
+        if (cfg->comp[m].kind != WBRW_KERNEL_TABLE) continue;
+        build_guide(cums[m], cfg->comp[m].table_n, d.tab[m].kg, guides[m]);
+        if (hipMemcpyAsync((void *)d.tab[m].cum, cums[m].data(), 8 * cums[m].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync((void *)d.tab[m].guide, guides[m].data(), 4 * guides[m].size(), hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(WBRW_EHIP);
+    }
     if (cfg->init_hist) {
         // Alg. 3 from the caller's signed histogram: rounding, scan, placement
         double *hd = at<double>(w, L.hist);

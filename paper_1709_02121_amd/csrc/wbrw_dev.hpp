@@ -69,9 +69,11 @@ struct InstParam {
 };
 
 struct Table {
-    const double *cum;  // n + 1 cumulative sums of |F[V](2q_j)|
+    const double *cum;    // n + 1 cumulative sums of |F[V](2q_j)|
+    const int32_t *guide; // kg + 1 entries: guide[i] = the last bin j < n with
+                          // cum[j] <= (i / kg) cum[n] (as the sampler rounds it)
     int32_t n;
-    int32_t pad;
+    int32_t kg;           // guide buckets, a power of two >= n
     double q_lo, dq;
 };
 
