@@ -150,6 +150,8 @@ typedef struct wbrw_stats {
     int64_t N_plus, N_minus;  /* sp2: last bootstrap's class sizes */
     int64_t particle_steps;   /* sum over steps of the particles held at the start of the step */
     double gamma0;            /* the instance's auxiliary rate */
+    int64_t annihilations;    /* annihilations so far */
+    int64_t triggered;        /* of those, run by wbrw_run_adaptive for the threshold alone */
 } wbrw_stats_t;
 
 /* Stages timed by the per-stage profiler. */
@@ -207,6 +209,20 @@ int wbrw_annihilate(wbrw_t h);
  * annihilate_every steps + annihilation are captured once into a hipGraph and
  * replayed.  No synchronisation. */
 int wbrw_run(wbrw_t h, int32_t nsteps, int32_t annihilate_every, int32_t use_graph);
+
+/* Steps with resampling at the scheduled instants and whenever the particle
+ * number is about to exceed a threshold (Sec. 5): after each of the nsteps
+ * steps the ensemble is annihilated (as wbrw_annihilate) if the step count
+ * is a multiple of annihilate_every (0 = no schedule) or if it holds more
+ * than `limit` particles (0 = no threshold).  The decision is taken on the
+ * device by the step's last kernel, and every annihilation kernel enqueued
+ * after the step reads it, so a run needs no host round trip; with
+ * use_graph != 0 (and a non-NULL stream) one step with its conditional
+ * annihilation is captured once into a hipGraph and replayed.  A threshold
+ * needs n_instances == 1 (instances must not resample each other);
+ * track_tangent must be 0.  WBRW_EINVAL otherwise.  No synchronisation. */
+int wbrw_run_adaptive(wbrw_t h, int32_t nsteps, int32_t annihilate_every, int64_t limit,
+                      int32_t use_graph);
 
 /* Position density (Eq. estimator with an indicator observable):
  * d_out[b * nbins + j] = sum_{particles of instance b in bin j} w / (N0_b dx),

@@ -61,7 +61,8 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "n", "n_plus", "n_minus", "n_ghost", "net", "escaped", "killed", "pairs", "events",
         "event_cap_hits", "max_depth", "S_plus", "S_minus", "N_plus", "N_minus")] + [
-        ("gamma0", C.c_double), ("step", C.c_int64), ("range_errors", C.c_int64)]
+        ("gamma0", C.c_double), ("step", C.c_int64), ("range_errors", C.c_int64),
+        ("annihilations", C.c_int64), ("triggered", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -82,6 +83,7 @@ def lib():
         L.orc_destroy.argtypes = [vp]
         L.orc_step.argtypes = [vp, C.c_int]
         L.orc_annihilate.argtypes = [vp]
+        L.orc_run_adaptive.argtypes = [vp, C.c_int, C.c_int, C.c_int64]
         L.orc_density.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp]
         L.orc_density_tangent.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp]
         L.orc_density_vjp.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp, vp]
@@ -250,6 +252,12 @@ class OracleSim:
             self.step(1)
             if annihilate_every and (self.step_count % annihilate_every == 0):
                 self.annihilate()
+
+    def run_adaptive(self, steps, annihilate_every, limit):
+        """Steps, each followed by an annihilation if the step count is a
+        multiple of annihilate_every or an instance holds more than `limit`
+        particles (0 turns either rule off)."""
+        lib().orc_run_adaptive(self.h, int(steps), int(annihilate_every), int(limit))
 
     def density(self, axis=0, nbins=None, lo=None, hi=None):
         d = self.cfg["density"]

@@ -103,6 +103,8 @@ typedef struct {
     double gamma0;
     int64_t step;
     int64_t range_errors; /* tangent components outside the fixed-point range of fx_add */
+    int64_t annihilations, triggered; /* orc_run_adaptive: annihilations, and those the
+                                         threshold alone called for */
 } orc_stats;
 
 /* ------------------------------------------------------------------------ */
@@ -1237,6 +1239,28 @@ void orc_annihilate(orc_sim *S)
     for (int b = 0; b < S->cfg.B; b++) {
         if (S->cfg.strategy == STRAT_SP2) annihilate_sp2(S, &S->I[b]);
         else annihilate_sp1(S, &S->I[b]);
+    }
+}
+
+/* Steps with resampling at the scheduled instants and whenever the particle
+ * number is about to exceed a threshold (Sec. 5, the resampling instants):
+ * after each step, the ensemble is annihilated if the number of steps done
+ * is a multiple of `every` (every > 0), or if some instance holds more than
+ * `limit` particles (limit > 0). */
+void orc_run_adaptive(orc_sim *S, int nsteps, int every, int64_t limit)
+{
+    for (int s = 0; s < nsteps; s++) {
+        orc_step(S, 1);
+        int sched = every > 0 && S->step % (uint32_t)every == 0;
+        int over = 0;
+        for (int b = 0; b < S->cfg.B; b++)
+            if (limit > 0 && S->I[b].real.n > limit) over = 1;
+        if (!sched && !over) continue;
+        orc_annihilate(S);
+        for (int b = 0; b < S->cfg.B; b++) {
+            S->I[b].st.annihilations++;
+            if (!sched) S->I[b].st.triggered++;
+        }
     }
 }
 

@@ -78,7 +78,7 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "n", "n_ghost", "events", "pairs", "killed", "escaped", "max_depth", "event_cap_hits",
         "step", "S_plus", "S_minus", "N_plus", "N_minus", "particle_steps")] + [
-        ("gamma0", C.c_double)]
+        ("gamma0", C.c_double), ("annihilations", C.c_int64), ("triggered", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -100,6 +100,7 @@ def lib():
         L.wbrw_step.argtypes = [vp, i32]
         L.wbrw_annihilate.argtypes = [vp]
         L.wbrw_run.argtypes = [vp, i32, i32, i32]
+        L.wbrw_run_adaptive.argtypes = [vp, i32, i32, i64, i32]
         L.wbrw_density.argtypes = [vp, i32, i32, C.c_double, C.c_double, vp]
         L.wbrw_density_tangent.argtypes = [vp, i32, i32, C.c_double, C.c_double, vp]
         L.wbrw_density_noalloc.argtypes = [vp, i32, i32, C.c_double, C.c_double, vp]
@@ -120,7 +121,7 @@ def lib():
                   "wbrw_density", "wbrw_density_tangent", "wbrw_stats", "wbrw_count",
                   "wbrw_export", "wbrw_destroy", "wbrw_profile", "wbrw_profile_read",
                   "wbrw_density_vjp", "wbrw_snapshot_size", "wbrw_snapshot", "wbrw_restore",
-                  "wbrw_autotune", "wbrw_density_noalloc"):
+                  "wbrw_autotune", "wbrw_density_noalloc", "wbrw_run_adaptive"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -254,6 +255,13 @@ class Simulation:
     def run(self, steps, annihilate_every, use_graph=False):
         _check(lib().wbrw_run(self.h, int(steps), int(annihilate_every), int(bool(use_graph))),
                "wbrw_run")
+
+    def run_adaptive(self, steps, annihilate_every, limit, use_graph=False):
+        """Steps, each followed by an annihilation if the step count is a
+        multiple of annihilate_every or the instance holds more than `limit`
+        particles (decided on the device)."""
+        _check(lib().wbrw_run_adaptive(self.h, int(steps), int(annihilate_every), int(limit),
+                                       int(bool(use_graph))), "wbrw_run_adaptive")
 
     def density(self, axis=0, nbins=None, lo=None, hi=None, out=None):
         d = self.cfg["density"]

@@ -352,6 +352,9 @@ struct wbrw_handle {
     int grid[16] = {};
     hipGraphExec_t gexec = nullptr;
     int graph_every = -1;
+    hipGraphExec_t gexec_ad = nullptr;        // one step + conditional annihilation
+    int ad_every = -1;
+    int64_t ad_limit = -1;
     int sticky = WBRW_OK;
     int64_t host_step = 0;   // steps enqueued so far (mirror of the device counter)
     int prof = 0;   // 1: every stage and step marked; 2: whole steps only
@@ -1019,6 +1022,54 @@ int wbrw_run(wbrw_t h, int32_t nsteps, int32_t every, int32_t use_graph)
     return wbrw_step(h, left - epochs * every);
 }
 
+int wbrw_run_adaptive(wbrw_t h, int32_t nsteps, int32_t every, int64_t limit, int32_t use_graph)
+{
+    if (!h || nsteps < 0 || every < 0 || limit < 0) return WBRW_EINVAL;
+    // the threshold is one instance's; tangents would need the ghost pass
+    // conditioned too
+    if (h->tangent || (limit > 0 && h->B != 1)) return WBRW_EINVAL;
+    Dev &d = h->d;
+    const int32_t c0 = d.cond_ann, e0 = d.ann_every;
+    const int64_t l0 = d.ann_limit;
+    d.cond_ann = 1;
+    d.ann_every = every;
+    d.ann_limit = limit;
+    auto restore = [&]() { d.cond_ann = c0; d.ann_every = e0; d.ann_limit = l0; };
+    int rc = WBRW_OK;
+    if (use_graph && h->stream != nullptr && nsteps > 0) {
+        if (!h->gexec_ad || h->ad_every != every || h->ad_limit != limit) {
+            if (h->gexec_ad) { (void)hipGraphExecDestroy(h->gexec_ad); h->gexec_ad = nullptr; }
+            hipGraph_t g;
+            const int prof = h->prof;
+            h->prof = 0;
+            const int64_t hs = h->host_step;
+            if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) { restore(); return WBRW_EHIP; }
+            rc = enqueue_step(h);
+            if (!rc) rc = enqueue_annihilate(h);
+            const hipError_t e = hipStreamEndCapture(h->stream, &g);
+            h->prof = prof;
+            h->host_step = hs;
+            if (!rc && e != hipSuccess) rc = WBRW_EHIP;
+            if (!rc && hipGraphInstantiate(&h->gexec_ad, g, nullptr, nullptr, 0) != hipSuccess) rc = WBRW_EHIP;
+            if (e == hipSuccess) (void)hipGraphDestroy(g);
+            if (rc) { restore(); return rc; }
+            h->ad_every = every;
+            h->ad_limit = limit;
+        }
+        for (int i = 0; i < nsteps && !rc; ++i) {
+            if (hipGraphLaunch(h->gexec_ad, h->stream) != hipSuccess) rc = WBRW_EHIP;
+            h->host_step += 1;
+        }
+    } else {
+        for (int i = 0; i < nsteps && !rc; ++i) {
+            rc = enqueue_step(h);
+            if (!rc) rc = enqueue_annihilate(h);
+        }
+    }
+    restore();
+    return rc;
+}
+
 int wbrw_density(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi, double *d_out)
 {
     if (!h || !d_out || nbins < 1 || nbins > h->d.max_bins || !(hi > lo)) return WBRW_EINVAL;
@@ -1304,6 +1355,8 @@ int wbrw_stats(wbrw_t h, int32_t b, wbrw_stats_t *out)
     out->step = c.step;
     out->particle_steps = tal[kTalPSteps];
     out->gamma0 = h->ip[b].gamma0;
+    out->annihilations = tal[kTalAnn];
+    out->triggered = tal[kTalTrig];
     if (c.err & kErrCapacity) return WBRW_ECAPACITY;
     if (c.err & kErrDepth) return WBRW_EDEPTH;
     if (c.err & kErrRange) return WBRW_ERANGE;
@@ -1467,6 +1520,7 @@ int wbrw_destroy(wbrw_t h)
     if (!h) return WBRW_EINVAL;
     drop_marks(h);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->gexec_ad) (void)hipGraphExecDestroy(h->gexec_ad);
     delete h;
     return WBRW_OK;
 }

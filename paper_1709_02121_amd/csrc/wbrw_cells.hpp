@@ -194,6 +194,7 @@ __device__ __forceinline__ int64_t tile_at_cost(const Dev &d, const int64_t *pla
 template <int DIM, bool SP2, bool TAN>
 __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
 {
+    if (ann_skipped(d)) return;
     // Each block takes a contiguous run of tiles.  Without tangents the
     // signs are summed per cell in an LDS hash table (open addressing on the
     // cell index, 8 probes) that lives across the block's tiles and is added
@@ -359,6 +360,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_scan_sums(Dev d)
 {
+    if (ann_skipped(d)) return;
     __shared__ uint64_t s_w[kThreads / 64];
     const int B = d.B;
     const int64_t tiles_per = (d.Nh + kTileS - 1) / kTileS;
@@ -457,6 +459,7 @@ __global__ __launch_bounds__(kThreads) void k_fold_tangents(Dev d)
 // new counts with the capacity clamp, and the regeneration-tile plan.
 __global__ __launch_bounds__(kThreads) void k_close_scan(Dev d)
 {
+    if (ann_skipped(d)) return;
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t tiles_per = (d.Nh + kTileS - 1) / kTileS;
@@ -477,6 +480,7 @@ __global__ __launch_bounds__(kThreads) void k_close_scan(Dev d)
 
 __global__ __launch_bounds__(kThreads) void k_scan(Dev d, int zero_counts)
 {
+    if (ann_skipped(d)) return;
     // Lanes take consecutive cells (coalesced): cell j * kThreads + tid of the
     // tile.  Each of the kPPT rows is scanned within the wavefront; the
     // (row, wavefront) totals are scanned in that order by one wavefront.
@@ -558,6 +562,7 @@ __device__ __forceinline__ int64_t cell_of_output(const int64_t *off, int64_t lo
 template <int DIM, bool SP2, bool TAN>
 __global__ __launch_bounds__(kThreads) void k_regen(Dev d)
 {
+    if (ann_skipped(d)) return;
     Ctl *ctl = d.ctl;
     const uint32_t step = ctl->step;
     const int B = d.B;
@@ -636,11 +641,13 @@ __global__ __launch_bounds__(kThreads) void k_regen(Dev d)
 // buffer set becomes the active one.
 __global__ __launch_bounds__(kThreads) void k_close_regen(Dev d)
 {
+    if (ann_skipped(d)) return;
     Ctl *ctl = d.ctl;
     const int B = d.B;
     for (int b = threadIdx.x; b < B; b += kThreads) {
         d.N[b] = d.Nnew[b];
         d.Nsrt[b] = d.Nnew[b];   // the regenerated ensemble is in cell order
+        d.tally[(int64_t)b * kTalCount + kTalAnn] += 1;
     }
     __syncthreads();
     block_plan(d.tileA, d.N, B, kTileA);

@@ -41,7 +41,7 @@ enum : uint32_t { kErrCapacity = 1u, kErrDepth = 2u, kErrRange = 4u };
 // tally slots per instance
 enum : int {
     kTalEvents = 0, kTalPairs, kTalKilled, kTalEscaped, kTalMaxDepth, kTalEventCap,
-    kTalSplus, kTalSminus, kTalNplus, kTalNminus, kTalPSteps, kTalCount = 16
+    kTalSplus, kTalSminus, kTalNplus, kTalNminus, kTalPSteps, kTalAnn, kTalTrig, kTalCount = 16
 };
 
 // ticket counters of the persistent passes
@@ -91,7 +91,8 @@ struct Ctl {
     uint32_t gcur;             // active ghost buffer set
     uint32_t err;              // sticky error bits
     uint32_t ann_seq;          // annihilations so far (look-back epoch of the scans)
-    uint32_t pad[3];
+    uint32_t ann_now;          // conditional annihilation: the one after this step runs
+    uint32_t pad[2];
     uint32_t ticket[kPassCount];   // zero between launches (see next_tile)
 };
 
@@ -99,6 +100,12 @@ struct Dev {
     // sizes and constants
     int32_t B, dim, M, strategy, tangent;
     int32_t tdep;               // some Gaussian height varies in time
+    // conditional annihilation (wbrw_run_adaptive): the step's closing kernel
+    // sets ctl->ann_now when the step count is a multiple of ann_every or an
+    // instance holds more than ann_limit particles, and with cond_ann set the
+    // annihilation kernels run only then
+    int32_t cond_ann, ann_every;
+    int64_t ann_limit;
     double hbar;
     int32_t nx, nk;
     uint32_t seed;
@@ -166,6 +173,13 @@ struct Dev {
     int64_t *bscan_tiles;       // [B+1] tiles per instance for the residual scan
     int64_t tstride;            // tiles per class in bTile
 };
+
+// An annihilation kernel enqueued after a step of wbrw_run_adaptive does
+// nothing unless that step's closing kernel asked for the annihilation.
+__device__ __forceinline__ bool ann_skipped(const Dev &d)
+{
+    return d.cond_ann && d.ctl->ann_now == 0u;
+}
 
 __device__ __forceinline__ Ens pick_set(const Dev &d, int ghost, uint32_t which)
 {

@@ -77,6 +77,7 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, un
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
 {
+    if (ann_skipped(d)) return;
     __shared__ unsigned long long s_w[kThreads / 64];
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -154,6 +155,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_classify(Dev d)
 // class counters (summed per instance in LDS when the instances fit).
 __global__ __launch_bounds__(kThreads) void k_sp2_close_classify(Dev d, int grid)
 {
+    if (ann_skipped(d)) return;
     constexpr int kLdsB = 512;
     __shared__ unsigned long long s_acc[5][kLdsB];
     const int B = d.B;
@@ -207,6 +209,7 @@ __device__ __forceinline__ uint64_t udiv_floor(uint64_t num, uint64_t den)
 
 __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
 {
+    if (ann_skipped(d)) return;
     __shared__ unsigned long long s_acc[4];    // tile sums (lo,hi) x 2
     __shared__ unsigned long long s_w[kThreads / 64];
     Ctl *ctl = d.ctl;
@@ -373,6 +376,7 @@ __device__ __forceinline__ void scan_u128_exclusive(uint64_t *v, int64_t t0, int
 
 __global__ __launch_bounds__(kThreads) void k_sp2_tilescan(Dev d, int rgrid)
 {
+    if (ann_skipped(d)) return;
     __shared__ unsigned long long s_w[kThreads / 64];
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -411,6 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_tilescan(Dev d, int rgrid)
 // After k_sp2_tilescan (one block): the draw-tile plans of both classes.
 __global__ __launch_bounds__(kThreads) void k_close_sp2_tilescan(Dev d)
 {
+    if (ann_skipped(d)) return;
     const int B = d.B;
     block_plan(d.tileD, d.Nnew, B, kTileR);
     block_plan(d.tileD + (B + 1), d.NGnew, B, kTileR);
@@ -419,6 +424,7 @@ __global__ __launch_bounds__(kThreads) void k_close_sp2_tilescan(Dev d)
 // ---- stage 4: per-particle exclusive prefixes P_0, P_1 (128-bit) -----------
 __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
 {
+    if (ann_skipped(d)) return;
     // Lanes take consecutive particles (coalesced): particle j * kThreads +
     // tid of the tile.  Per class, each of the kPPT rows is scanned within the
     // wavefront (shuffles of the 64-bit halves with carry); the (row,
@@ -511,6 +517,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
 // ---- stage 5: the N_r i.i.d. draws of each class (Alg. 2 step 2) ------------
 __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
 {
+    if (ann_skipped(d)) return;
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const uint32_t step = ctl->step;
@@ -554,6 +561,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
 // update whose probes all fail adds directly.
 __global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
 {
+    if (ann_skipped(d)) return;
     constexpr int kSlots = 4096;
     __shared__ int32_t s_key[kSlots];
     __shared__ int32_t s_val[kSlots];
@@ -637,6 +645,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_cells(Dev d)
 // ---- stage 7: exact rational cell values and the rounding step -------------
 __global__ __launch_bounds__(kThreads) void k_sp2_round(Dev d)
 {
+    if (ann_skipped(d)) return;
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const uint32_t step = ctl->step;
@@ -694,6 +703,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_round(Dev d)
 // the last bootstrap's class sizes and sums into the tallies; clear the stats
 __global__ __launch_bounds__(kThreads) void k_sp2_close(Dev d)
 {
+    if (ann_skipped(d)) return;
     for (int b = blockIdx.x * kThreads + threadIdx.x; b < d.B; b += gridDim.x * kThreads) {
         int64_t *st = d.bcls_stat + (int64_t)b * 8;
         int64_t *T = d.tally + (int64_t)b * kTalCount;

@@ -1480,6 +1480,7 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
     }
     __syncthreads();
     int64_t n_next = 0;   // instance tid's count for the next step
+    int over = 0;         // an instance of this thread holds more than ann_limit
     for (int b = tid; b < B; b += kThreads) {
         const bool mine = b == tid;
         int64_t *T = d.tally + (int64_t)b * kTalCount;
@@ -1507,6 +1508,16 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
         Ncur[b] = n;
         if (mine) n_next = n;
         evc[b] = 0;
+        if (d.ann_limit > 0 && n > d.ann_limit) over = 1;
+    }
+    // conditional annihilation after this step: scheduled, or an instance
+    // about to outgrow the threshold (the real ensemble's closing launch)
+    const int any_over = __syncthreads_or(over);
+    if (d.cond_ann && !ghost && tid == 0) {
+        const bool sched = d.ann_every > 0 && (step + 1u) % (uint32_t)d.ann_every == 0u;
+        ctl->ann_now = (sched || any_over) ? 1u : 0u;
+        if (any_over && !sched)
+            for (int b = 0; b < B; ++b) d.tally[(int64_t)b * kTalCount + kTalTrig] += 1;
     }
     {   // clear the group sums of this step's streaming and family tiles
         uint64_t *supA = ghost ? d.supAg : d.supA, *supB = ghost ? d.supBg : d.supB;

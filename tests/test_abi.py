@@ -51,7 +51,7 @@ int main(void) {
   O(wbrw_config, hbar); O(wbrw_config, comp); O(wbrw_config, N0); O(wbrw_config, ghost_capacity);
   O(wbrw_config, init_mean_x); O(wbrw_config, x_lo); O(wbrw_config, nx); O(wbrw_config, nk);
   O(wbrw_component, table); O(wbrw_component, q_lo); O(wbrw_component, center_b);
-  O(wbrw_stats_t, gamma0);
+  O(wbrw_stats_t, gamma0); O(wbrw_stats_t, triggered);
   return 0;
 }
 """
@@ -69,6 +69,7 @@ int main(void) {
     for f in ("table", "q_lo", "center_b"):
         assert vals[f] == getattr(P.Component, f).offset, f
     assert vals["gamma0"] == P.Stats.gamma0.offset
+    assert vals["triggered"] == P.Stats.triggered.offset
 
 
 @pytest.mark.parametrize("name", sorted(W.ALL))

@@ -356,6 +356,40 @@ def test_restore_into_used_handle(P, O):
     _exact(b.particles()["D"], r.particles()["D"], "tangents after restore into a used handle")
 
 
+@pytest.mark.parametrize("strategy,graph", [("sp1", False), ("sp1", True), ("sp2", False)])
+def test_threshold_triggered_annihilation_parity(P, O, strategy, graph):
+    """Sec. 5's resampling when the particle number is about to exceed a
+    threshold: the device decides after every step (no host round trip, also
+    replayed from a captured graph), and the ensemble, the tallies and the
+    number of triggered annihilations equal the oracle's."""
+    cfg = W.gaussian_barrier_small(N0=np.array([3000]), strategy=strategy)
+    limit = 3400 if strategy == "sp1" else 3600
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.run_adaptive(40, 10, limit, use_graph=graph)
+    r.run_adaptive(40, 10, limit)
+    st_g, st_r = g.stats(), r.stats()
+    say(f"threshold {strategy} graph={graph}: annihilations {st_r['annihilations']}, "
+        f"triggered {st_r['triggered']}")
+    assert 3 <= st_r["triggered"] < 40 - st_r["annihilations"] + st_r["triggered"]   # fires, not always
+    assert (st_g["annihilations"], st_g["triggered"]) == (st_r["annihilations"], st_r["triggered"])
+    compare(g, r, f"threshold {strategy}")
+    assert np.array_equal(g.density().cpu().numpy(), r.density())
+
+
+def test_threshold_triggered_annihilation_4d(P, O):
+    """The 4D model, whose growth the threshold keeps below the capacity."""
+    cfg = W.helium_soft_coulomb(N0=np.array([3000]))
+    cfg["grid"] = {"x_lo": -10.0, "x_hi": 10.0, "nx": 12, "k_lo": -4.0, "k_hi": 4.0, "nk": 12}
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    g.run_adaptive(30, 10, 9000)
+    r.run_adaptive(30, 10, 9000)
+    st = r.stats()
+    say(f"threshold 4d: annihilations {st['annihilations']}, triggered {st['triggered']}, n={r.count()}")
+    assert st["triggered"] >= 2
+    assert (g.stats()["annihilations"], g.stats()["triggered"]) == (st["annihilations"], st["triggered"])
+    compare(g, r, "threshold 4d")
+
+
 def test_autotune_keeps_results(P, O):
     """The autotuner's steps are real steps; any grid it picks gives the same bits."""
     cfg = W.batched_barriers(B=4, N0=np.array([3000, 100, 25000, 7000], dtype=np.int64))

@@ -139,3 +139,38 @@ def test_sp2_weights_are_signed_units_after_annihilation(oracle_mod):
     s.annihilate()
     w = s.particles()["w"]
     assert set(np.unique(w)) <= {-1.0, 1.0}
+
+
+def test_threshold_triggered_annihilation(oracle_mod):
+    """Sec. 5: resampling at the scheduled instants and whenever the particle
+    number is about to exceed a threshold.  The adaptive runner annihilates
+    after exactly the steps whose end count exceeds the limit (or that are
+    scheduled): the same ensemble as stepping one step at a time and
+    annihilating by hand on that rule; the threshold fires between scheduled
+    instants, never lets the count after a step exceed the limit unresolved,
+    and the signed count stays conserved."""
+    cfg = W.gaussian_barrier_small(N0=np.array([3000]))
+    limit = 3090
+    a = oracle_mod.OracleSim(cfg)
+    a.run_adaptive(40, 10, limit)
+    b = oracle_mod.OracleSim(cfg)
+    fired = []
+    for s in range(1, 41):
+        b.step(1)
+        over = b.count() > limit
+        if s % 10 == 0 or over:
+            b.annihilate()
+            if s % 10:
+                fired.append(s)
+        st = b.stats()
+        assert st["net"] + st["escaped"] + st["killed"] == 3000
+    pa, pb = a.particles(), b.particles()
+    for f in ("x", "k", "sign", "id"):
+        assert np.array_equal(pa[f], pb[f]), f
+    st = a.stats()
+    assert st["annihilations"] == 4 + len(fired) and st["triggered"] == len(fired)
+    assert len(fired) >= 3, fired          # the limit sits inside the growth of an epoch
+    # without the scheduled instants the threshold alone keeps annihilating
+    c = oracle_mod.OracleSim(cfg)
+    c.run_adaptive(40, 0, limit)
+    assert c.stats()["triggered"] == c.stats()["annihilations"] > 0
