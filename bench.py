@@ -299,6 +299,96 @@ def run_forms(P, torch, W, args):
     return forms
 
 
+def long_runs(P, torch, W):
+    """Each configuration once at its full length: the 1e7 barrier for 1000
+    steps (sp1 and sp2), the 4D model for 400 steps with resampling at the
+    scheduled instants and on a particle-count threshold (when it fires and
+    the particles left by each resampling, #_P^a), the batched form and the
+    differentiation form (forward, a checkpoint every 50 steps, backward) for
+    500 steps."""
+    out = {}
+
+    def timed(sim, fn):
+        ps0 = sum(sim.stats(b)["particle_steps"] for b in range(sim.B))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        sim.synchronize()
+        wall = time.perf_counter() - t0
+        ps = sum(sim.stats(b)["particle_steps"] for b in range(sim.B)) - ps0
+        return {"steps_run": int(sim.stats(0)["step"]), "wall_s": round(wall, 3),
+                "value": round(ps / wall, 1), "particle_steps": int(ps),
+                "n_end": int(sum(sim.stats(b)["n"] for b in range(sim.B)))}
+
+    for strat in ("sp1", "sp2"):
+        torch.cuda.empty_cache()
+        sim = P.Simulation(W.gaussian_barrier_large(strat))
+        r = timed(sim, lambda: (sim.run(1000, ANN_EVERY, use_graph=True), sim.density()))
+        st = sim.stats()
+        r.update({"escaped": int(st["escaped"]), "killed": int(st["killed"]),
+                  "annihilations": int(st["annihilations"])})
+        out[f"gaussian_barrier_1e7_{strat}_1000_steps"] = r
+        log(f"long {strat}: {r}")
+        del sim
+
+    torch.cuda.empty_cache()
+    cap, limit = 1_500_000_000, 600_000_000
+    cfg = W.helium_soft_coulomb(capacity=cap)
+    sim = P.Simulation(cfg)
+    epochs = []
+
+    def run4d():
+        last = 0
+        for s in range(cfg["steps"]):
+            sim.run_adaptive(1, ANN_EVERY, limit)
+            st = sim.stats()
+            if st["annihilations"] != last:
+                epochs.append({"step": int(st["step"]), "n_after": int(st["n"]),
+                               "trigger": (int(st["step"]) % ANN_EVERY) != 0})
+                last = st["annihilations"]
+
+    r = timed(sim, run4d)
+    st = sim.stats()
+    r.update({"capacity": cap, "threshold": limit, "annihilations": int(st["annihilations"]),
+              "triggered": int(st["triggered"]), "max_depth": int(st["max_depth"]),
+              "n_after_resampling": [e["n_after"] for e in epochs],
+              "triggered_at_steps": [e["step"] for e in epochs if e["trigger"]],
+              "mean_n_after_resampling": round(float(np.mean([e["n_after"] for e in epochs])), 1)
+              if epochs else None})
+    out["helium_4d_400_steps"] = r
+    log(f"long 4d: {r}")
+    del sim
+
+    torch.cuda.empty_cache()
+    sim = P.Simulation(W.batched_barriers())
+    out["batched_256_500_steps"] = timed(sim, lambda: sim.run(500, ANN_EVERY, use_graph=True))
+    log(f"long batched: {out['batched_256_500_steps']}")
+    del sim
+
+    torch.cuda.empty_cache()
+    cfg = W.differentiation()
+    sim = P.Simulation(cfg)
+    nb = cfg["density"]["nbins"]
+    g = torch.linspace(-1.0, 1.0, nb, dtype=torch.float64, device="cuda").reshape(1, nb)
+    held = {}
+
+    def fwd_adj():
+        for s in range(cfg["steps"]):
+            sim.step(1)
+            if (s + 1) % ANN_EVERY == 0:
+                sim.annihilate()
+            if (s + 1) % cfg["snapshot_every"] == 0:
+                held["snap"] = sim.snapshot()
+        sim.density()
+        held["grad"] = sim.density_vjp(g)
+
+    out["fwd_adjoint_500_steps"] = timed(sim, fwd_adj)
+    out["fwd_adjoint_500_steps"]["grad"] = [float(v) for v in held["grad"][0].cpu()]
+    log(f"long fwd+adjoint: {out['fwd_adjoint_500_steps']}")
+    del sim
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +400,8 @@ def main():
                     help="comma-separated forms to run besides the main line (default: all)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first copy 1 GiB device to device (a reference for HBM byte counters)")
+    ap.add_argument("--long", action="store_true",
+                    help="instead of the timed line, run every configuration once at its full length")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the headline workload (to profile the forms alone); value is then null")
     args = ap.parse_args()
@@ -347,6 +439,14 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read + 1 GiB written")
         del a, b
+    if args.long:
+        try:
+            lr = long_runs(P, torch, W)
+        except Exception as e:   # report, never hide, a run that failed
+            lr = {"error": str(e)[:300]}
+            log(f"long runs: FAILED {e}")
+        print(json.dumps({"metric": "full-length runs", "value": None, "long_runs": lr}), flush=True)
+        return
     if args.no_main:
         forms = run_forms(P, torch, W, args)
         print(json.dumps({"metric": "forms only (profiling run)", "value": None, "forms": forms}), flush=True)
