@@ -360,10 +360,13 @@ def long_runs(P, torch, W):
     del sim
 
     torch.cuda.empty_cache()
-    sim = P.Simulation(W.batched_barriers())
-    out["batched_256_500_steps"] = timed(sim, lambda: sim.run(500, ANN_EVERY, use_graph=True))
+    try:
+        sim = P.Simulation(W.batched_barriers())
+        out["batched_256_500_steps"] = timed(sim, lambda: sim.run(500, ANN_EVERY, use_graph=True))
+        del sim
+    except Exception as e:
+        out["batched_256_500_steps"] = {"error": str(e)[:300]}
     log(f"long batched: {out['batched_256_500_steps']}")
-    del sim
 
     torch.cuda.empty_cache()
     cfg = W.differentiation()

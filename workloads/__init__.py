@@ -132,7 +132,10 @@ def helium_soft_coulomb(**over):
 def batched_barriers(B=256, seed=0, **over):
     """B independent Gaussian-barrier instances: numpy default_rng(seed) draws,
     in order, H_b ~ U[0.1,0.5], w_b ~ U[0.5,2], log10 N_b ~ U[4,6]; gamma0_b = H_b
-    (gamma_scale 1); 500 steps, annihilation every 10 on a 240 x 128 grid each."""
+    (gamma_scale 1); 500 steps, annihilation every 10 on a 240 x 128 grid each.
+    Capacity 16 N_b per instance: the smallest instances (N_b near 1e4 on 30720
+    cells, fewer particles than cells) keep growing between resamplings and
+    reach 9.5 N_b within the 500 steps."""
     rng = np.random.default_rng(seed)
     H = rng.uniform(0.1, 0.5, size=B)
     w = rng.uniform(0.5, 2.0, size=B)
@@ -145,6 +148,7 @@ def batched_barriers(B=256, seed=0, **over):
                         "center": np.zeros(B)}],
         "N0": N,
         "steps": 500,
+        "capacity_factor": 16.0,
     })
     return _override(cfg, over)
 
