@@ -303,10 +303,39 @@ def test_density_vjp_and_autograd_match_oracle(P, O):
     got = sim.density_vjp(torch.tensor(g)).cpu().numpy()[0]
     _exact(got, ref, "vjp")
     theta = torch.tensor([0.3, 1.0, 0.0], dtype=torch.float64, requires_grad=True)
-    rho = A.density(theta, cfg, steps=30, annihilate_every=10, snapshot_every=10)
+    rho = A.density(theta, cfg, steps=30, annihilate_every=10)
     assert np.array_equal(rho.detach().cpu().numpy(), r.density()[0])
     (rho * torch.tensor(g, device=rho.device)).sum().backward()
     _exact(theta.grad.numpy(), ref, "autograd")
+
+
+@pytest.mark.parametrize("strategy,mode", [("sp1", 2), ("sp2", 1)])
+def test_autograd_other_tangent_modes_and_checkpoints(P, O, strategy, mode):
+    """The autograd Function in the finite-variance x0 mode (derivative ghost
+    pairs) and in sp2 (pathwise tangents): the gradient equals the oracle's
+    backward contraction bit for bit.  Its checkpoints are restart points: a
+    handle restored from the one at step 20 reaches the same density."""
+    import torch
+    from paper_1709_02121_amd import autograd as A
+    cfg = W.gaussian_barrier_small(N0=np.array([4000]), gamma0=0.45, track_tangent=mode,
+                                   strategy=strategy)
+    cfg["init"] = dict(cfg["init"], mean_x=[-4.0, 0.0])
+    x = -60 + 0.25 + 0.5 * np.arange(240)
+    g = 0.5 * (1 + np.tanh(x / 2.0))
+    r = O.OracleSim(cfg)
+    r.run(30, 10)
+    ref = r.density_vjp(g)[0]
+    theta = torch.tensor([0.3, 1.0, 0.0], dtype=torch.float64, requires_grad=True)
+    ckpt = []
+    rho = A.density(theta, cfg, steps=30, annihilate_every=10, snapshot_every=10, checkpoints=ckpt)
+    assert np.array_equal(rho.detach().cpu().numpy(), r.density()[0])
+    (rho * torch.tensor(g, device=rho.device)).sum().backward()
+    _exact(theta.grad.numpy(), ref, f"autograd {strategy} mode {mode}")
+    assert [c[0] for c in ckpt] == [10, 20, 30]
+    sim = P.Simulation(A.theta_config(cfg, [0.3, 1.0, 0.0]))
+    sim.restore(ckpt[1][1])
+    sim.run(10, 10)
+    assert np.array_equal(sim.density().cpu().numpy()[0], r.density()[0])
 
 
 def test_snapshot_restore_continues_exactly(P, O):
