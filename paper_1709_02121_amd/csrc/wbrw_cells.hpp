@@ -3,18 +3,20 @@
 // Annihilation (Sec. 4.3, Eq. signed_histogram; Alg. 3 step 3):
 //   k_bin     one pass over the particles: cell index on the uniform grid
 //             D_nu = X_nu1 x K_nu2 (escaped sign tallied), signs summed per
-//             cell in LDS per tile, then integer atomic adds into the
-//             instance's count grid: the per-cell sums n_nu^+ - n_nu^- are
-//             exact and order independent;
-//   k_scan    ordered exclusive scan of |n_nu| per instance (decoupled
-//             look-back), which is also the output layout: ascending cell,
-//             then index within the cell;
+//             cell in an LDS hash per block, then integer atomic adds into the
+//             instance's count grid (one copy per XCD): the per-cell sums
+//             n_nu^+ - n_nu^- are exact and order independent;
+//   k_scan_sums, k_close_scan, k_scan
+//             ordered exclusive scan of |n_nu| per instance in three launches
+//             (tile sums, their one-block scan, the offsets), which is also
+//             the output layout: ascending cell, then index within the cell;
 //   k_regen   one thread per output particle: the cell by binary search in the
 //             scan, position uniform in the cell, sign sgn(n_nu), lineage id
 //             (nu << 32) | j; written to the inactive buffer set, which then
 //             becomes active.
 // Density (Eq. estimator with an indicator observable): integer (sp1) or
-// 2^-32 fixed-point (sp2) atomics per bin, then one division per bin.
+// 2^-32 fixed-point (sp2) atomics per bin, then one division per bin; the
+// tangent density and the backward pass sum tangents in 32.32 fixed point.
 #pragma once
 #include "wbrw_dev.hpp"
 #include "wbrw_math.hpp"
