@@ -37,7 +37,7 @@ struct Layout {
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
            tcA = 0, tcAg = 0, supA = 0, supAg = 0, spart = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, occx = 0, Tqx = 0, off = 0,
            occ = 0, Tq = 0, ntil = 0, dacc = 0, dTq = 0, bA = 0, bcopies = 0, bcls = 0,
-           bcell = 0, bP = 0, bTile = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, hist = 0, xitab = 0;
+           bcell = 0, bP = 0, bTile = 0, bG = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, hist = 0, xitab = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
     int64_t tilesA = 0, tilesAg = 0, tilesB = 0, tilesBg = 0, tilesS = 0, tilesP = 0;
 };
@@ -245,6 +245,7 @@ Layout make_layout(const wbrw_config *c)
         L.bcell = take(cur, C * 8);
         L.bP = take(cur, 2 * C * 16);
         L.bTile = take(cur, 2 * (size_t)L.tilesP * 16);
+        L.bG = take(cur, 2 * C * 4);
     }
     // everything below starts zeroed
     L.zero_begin = (cur + kAlign - 1) / kAlign * kAlign;
@@ -379,7 +380,7 @@ namespace {
 template <typename T>
 T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off); }
 
-enum { G_STREAM = 0, G_FAMILY, G_BIN, G_SCAN, G_REGEN, G_DENS, G_SP2, G_GHOST, G_EVENTS, G_COUNT };
+enum { G_STREAM = 0, G_FAMILY, G_BIN, G_SCAN, G_REGEN, G_DENS, G_SP2, G_GHOST, G_EVENTS, G_DRAW, G_COUNT };
 
 template <typename K>
 int persistent_blocks(K kernel, int cus)
@@ -595,7 +596,7 @@ int enqueue_annihilate_dim(wbrw_t h)
             stage_end(h);
         }
         stage_begin(h, WBRW_STAGE_BOOTSTRAP);
-        int rc = enqueue_sp2_bootstrap<DIM>(d, s, h->grid[G_SP2], h->grid[G_SCAN]);
+        int rc = enqueue_sp2_bootstrap<DIM>(d, s, h->grid[G_SP2], h->grid[G_SCAN], h->grid[G_DRAW]);
         stage_end(h);
         if (rc) return rc;
         stage_begin(h, WBRW_STAGE_SCAN);
@@ -672,6 +673,7 @@ void set_grids_dim(wbrw_t h)
     h->grid[G_SP2] = persistent_blocks(k_sp2_classify<DIM>, cus);
     h->grid[G_GHOST] = persistent_blocks(k_ghosts, cus);
     h->grid[G_EVENTS] = persistent_blocks(k_events, cus);
+    h->grid[G_DRAW] = persistent_blocks(k_sp2_draw, cus);
 }
 
 }  // namespace
@@ -881,6 +883,7 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
         d.bcell = at<int64_t>(w, L.bcell);
         d.bP = at<uint64_t>(w, L.bP);
         d.bTile = at<uint64_t>(w, L.bTile);
+        d.bG = at<int32_t>(w, L.bG);
         d.bcls_stat = at<int64_t>(w, L.bcls_stat);
         d.tileD = at<int64_t>(w, L.tileD);
         d.bscan_tiles = at<int64_t>(w, L.bscan_tiles);

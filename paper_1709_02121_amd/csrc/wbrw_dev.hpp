@@ -162,12 +162,14 @@ struct Dev {
     int64_t *dTq;               // [B][6][max_bins] tangent density sums (fixed point, as Tq)
     int32_t max_bins;
     // sp2 bootstrap scratch
-    uint64_t *bA;               // [cap_total] quantised weight
+    uint64_t *bA;               // [cap_total] quantised weight, then the residual
     int32_t *bcopies;           // [cap_total] copies per particle
     int8_t *bcls;               // [cap_total] class (0 +, 1 -, -1 none)
     int64_t *bcell;             // [cap_total] cell or -1
     uint64_t *bP;               // [2][cap_total] 128-bit residual prefix (lo, hi interleaved)
     uint64_t *bTile;            // [2][tiles] 128-bit tile sums
+    int32_t *bG;                // [2][cap_total] draw guide per class, in the
+                                // instance's particle slots (sp2_guide_bits)
     int64_t *bcls_stat;         // [B][8]: N+, N-, S+, S-, sumk+, sumk-, Nr+, Nr-
     int64_t *tileD;             // [2][B+1] draw-tile plan (per class)
     int64_t *bscan_tiles;       // [B+1] tiles per instance for the residual scan

@@ -277,8 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
                 rs[c] += r;
             }
             d.bcopies[i] = (int32_t)k;
-            d.bP[2 * i] = r;           // residual, replaced by the prefix in stage 4
-            d.bP[2 * i + 1] = 0;
+            d.bA[i] = r;               // A_i is no longer needed: the residual
         }
         // block sums: 64-bit halves of the 128-bit residual sums
         for (int c = 0; c < 2; ++c) {
@@ -421,45 +420,87 @@ __global__ __launch_bounds__(kThreads) void k_close_sp2_tilescan(Dev d)
     block_plan(d.tileD + (B + 1), d.NGnew, B, kTileR);
 }
 
+// ---- draw guide ------------------------------------------------------------
+// A class with N_r draws splits the draws' 64 random bits into K = 2^bits
+// buckets by their top bits, K the largest power of two below N_r (one to
+// two draws per bucket).  Guide entry k < K
+// is the particle whose residual interval [P_i, P_i + r_i) holds the bucket's
+// least value B_k = floor(k R / K); entry K is n - 1.  A draw in bucket k has
+// B_k <= U <= B_(k+1), so its particle lies between entries k and k + 1 and
+// the search over that slice returns what the search over the whole prefix
+// does.  Since r_i < S_c, each interval spans less than K / N_r < 1
+// bucket: a particle writes at most one entry.  K + 1 <= N_r <= n entries fit
+// the instance's particle slots.
+__device__ __forceinline__ int sp2_guide_bits(int64_t Nr)
+{
+    return Nr >= 2 ? 63 - __clzll((unsigned long long)(Nr - 1)) : 0;   // K < N_r
+}
+
+__device__ __forceinline__ double u128_to_f64(u128 v)
+{
+    return (double)(uint64_t)(v >> 64) * 0x1p64 + (double)(uint64_t)v;
+}
+
+// k R for k < 2^32: two 32 x 64-bit products (R < 2^95 as S_c < 2^64 and
+// N_r < 2^31, so k R < 2^128)
+__device__ __forceinline__ u128 mul32_128(uint32_t k, u128 R)
+{
+    return (u128)k * (uint64_t)R + (((u128)k * (uint64_t)(R >> 64)) << 64);
+}
+
+// The least k in [0, K] with B_k >= P, B_k = floor(k R / 2^bits) (the value
+// scale64(k 2^(64 - bits), R) takes), B_K = R: the least k with
+// k R >= P 2^bits.  The estimate e is within one of the exact quotient
+// (K <= 2^30 as n < 2^31), so the corrections take a step or two.
+__device__ __forceinline__ uint32_t sp2_guide_first(u128 P, int bits, u128 R)
+{
+    const uint32_t K = 1u << bits;
+    const u128 Ps = P << bits;
+    const double e = u128_to_f64(P) / u128_to_f64(R) * (double)K;
+    uint32_t k = e <= 0.0 ? 0u : (e >= (double)K ? K : (uint32_t)e);
+    while (k > 0 && mul32_128(k - 1, R) >= Ps) --k;
+    while (k < K && mul32_128(k, R) < Ps) ++k;
+    return k;
+}
+
 // ---- stage 4: per-particle exclusive prefixes P_0, P_1 (128-bit) -----------
+// and the draw guides
 __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
 {
     if (ann_skipped(d)) return;
     // Lanes take consecutive particles (coalesced): particle j * kThreads +
-    // tid of the tile.  Per class, each of the kPPT rows is scanned within the
-    // wavefront (shuffles of the 64-bit halves with carry); the (row,
-    // wavefront) totals are then scanned in that order by one wavefront.
+    // tid of the tile.  One class at a time: each of the kPPT rows is scanned
+    // within the wavefront (shuffles of the 64-bit halves with carry); the
+    // (row, wavefront) totals are then scanned in that order by one
+    // wavefront.  A class without draws is skipped (nothing reads its prefix).
     constexpr int kW = kThreads / 64;
-    __shared__ uint64_t s_lo[2][kPPT * kW], s_hi[2][kPPT * kW];
-    Ctl *ctl = d.ctl;
+    __shared__ uint64_t s_lo[kPPT * kW], s_hi[kPPT * kW];
     const int B = d.B;
     const int64_t *plan = d.tileA;
     const int64_t ntiles = plan[B];
     const int64_t C = d.cap_total;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        __syncthreads();
         const int b = segment_of(plan, B, t);
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
         const int64_t li0 = (t - plan[b]) * kTileA + tid;
-        // the tile's base prefixes are needed only at the end: loaded first,
-        // their latency hides behind the scans
-        u128 tb[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) tb[c] = ld128(d.bTile + 2 * ((int64_t)c * d.tstride + t));
+        const int64_t *st = d.bcls_stat + (int64_t)b * 8;
         uint64_t r[kPPT];
         int8_t cl[kPPT];
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const int64_t li = li0 + (int64_t)j * kThreads;
             const int64_t i = P.base + (li < n ? li : 0);
-            r[j] = d.bP[2 * i];
+            r[j] = d.bA[i];                   // the residual r_i since stage 3
             cl[j] = li < n ? d.bcls[i] : (int8_t)-1;
         }
-        uint64_t elo[2][kPPT], ehi[2][kPPT];     // exclusive within (row, wavefront)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < 2; ++c) {
+            const int64_t Nr = st[kBNr0 + c];
+            __syncthreads();                  // s_lo, s_hi free again
+            if (Nr <= 0) continue;
+            const u128 tb = ld128(d.bTile + 2 * ((int64_t)c * d.tstride + t));
+            uint64_t elo[kPPT], ehi[kPPT];    // exclusive within (row, wavefront)
 #pragma unroll
             for (int j = 0; j < kPPT; ++j) {
                 const uint64_t v = cl[j] == c ? r[j] : 0ull;
@@ -473,16 +514,14 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
                         lo = nlo;
                     }
                 }
-                if (lane == 63) { s_lo[c][j * kW + wv] = lo; s_hi[c][j * kW + wv] = hi; }
-                elo[c][j] = lo - v;
-                ehi[c][j] = hi - (lo < v ? 1ull : 0ull);
+                if (lane == 63) { s_lo[j * kW + wv] = lo; s_hi[j * kW + wv] = hi; }
+                elo[j] = lo - v;
+                ehi[j] = hi - (lo < v ? 1ull : 0ull);
             }
-        __syncthreads();
-        if (wv == 0) {   // exclusive scan of the kPPT * kW totals, in place
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const uint64_t v0 = lane < kPPT * kW ? s_lo[c][lane] : 0ull;
-                const uint64_t v1 = lane < kPPT * kW ? s_hi[c][lane] : 0ull;
+            __syncthreads();
+            if (wv == 0) {   // exclusive scan of the kPPT * kW totals, in place
+                const uint64_t v0 = lane < kPPT * kW ? s_lo[lane] : 0ull;
+                const uint64_t v1 = lane < kPPT * kW ? s_hi[lane] : 0ull;
                 uint64_t lo = v0, hi = v1;
 #pragma unroll
                 for (int o = 1; o < 64; o <<= 1) {
@@ -494,27 +533,36 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
                     }
                 }
                 const uint64_t xlo = lo - v0, xhi = hi - v1 - (lo < v0 ? 1ull : 0ull);
-                if (lane < kPPT * kW) { s_lo[c][lane] = xlo; s_hi[c][lane] = xhi; }
+                if (lane < kPPT * kW) { s_lo[lane] = xlo; s_hi[lane] = xhi; }
             }
-        }
-        __syncthreads();
+            __syncthreads();
+            const int gb = sp2_guide_bits(Nr);
+            const u128 R = (u128)(uint64_t)st[kBS0 + c] * (u128)(uint64_t)Nr;
+            int32_t *G = d.bG + (int64_t)c * C + P.base;
+            uint64_t *Pc = d.bP + 2 * (int64_t)c * C;
 #pragma unroll
-        for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = li0 + (int64_t)j * kThreads;
-            if (li >= n) continue;
-            const int64_t i = P.base + li;
-            u128 pc[2];
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-                pc[c] = tb[c] + (((u128)s_hi[c][j * kW + wv] << 64) | s_lo[c][j * kW + wv]) +
-                        (((u128)ehi[c][j] << 64) | elo[c][j]);
-            st128_nt(d.bP + 2 * i, pc[0]);
-            st128_nt(d.bP + 2 * C + 2 * i, pc[1]);
+            for (int j = 0; j < kPPT; ++j) {
+                const int64_t li = li0 + (int64_t)j * kThreads;
+                if (li >= n) continue;
+                const int64_t i = P.base + li;
+                const u128 pc = tb + (((u128)s_hi[j * kW + wv] << 64) | s_lo[j * kW + wv]) +
+                                (((u128)ehi[j] << 64) | elo[j]);
+                st128_nt(Pc + 2 * i, pc);
+                if (cl[j] == c && r[j] != 0ull) {
+                    const uint32_t k = sp2_guide_first(pc, gb, R);
+                    if (k < (1u << gb) && mul32_128(k, R) < ((pc + (u128)r[j]) << gb))
+                        G[k] = (int32_t)li;
+                }
+                if (li == n - 1) G[1u << gb] = (int32_t)li;
+            }
         }
     }
 }
 
 // ---- stage 5: the N_r i.i.d. draws of each class (Alg. 2 step 2) ------------
+// One draw per thread at a time: the searches are short (the guide leaves
+// about n / N_r particles), and more searches in flight per thread measured
+// slower.
 __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
 {
     if (ann_skipped(d)) return;
@@ -525,7 +573,6 @@ __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
     const int64_t C = d.cap_total;
     const int tid = threadIdx.x;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        __syncthreads();
         const int c = t < n0 ? 0 : 1;
         const int64_t *plan = d.tileD + (int64_t)c * (B + 1);
         const int64_t tc = t - (c ? n0 : 0);
@@ -534,18 +581,20 @@ __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
         const int64_t *st = d.bcls_stat + (int64_t)b * 8;
         const int64_t Nr = st[kBNr0 + c];
         const u128 R = (u128)(uint64_t)st[kBS0 + c] * (u128)(uint64_t)Nr;
-        const int64_t n = d.N[b];
         const uint64_t *Pc = d.bP + 2 * (int64_t)c * C + 2 * P.base;
+        const int32_t *G = d.bG + (int64_t)c * C + P.base;
+        const int gb = sp2_guide_bits(Nr);
         for (int j = 0; j < kTileR / kThreads; ++j) {
             const int64_t dd = (tc - plan[b]) * kTileR + (int64_t)j * kThreads + tid;
             if (dd >= Nr) break;
             const W4 w = draw((uint64_t)dd, step, kTagBoot, 0u, (uint32_t)c, d.seed, P.key);
             const uint64_t bits = ((uint64_t)w.b << 32) | (uint64_t)w.a;
             const u128 U = scale64(bits, R);
-            int64_t lo = 0, hi = n - 1;
+            const uint64_t k = gb ? bits >> (64 - gb) : 0ull;
+            int32_t lo = G[k], hi = G[k + 1];
             while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if (ld128(Pc + 2 * mid) <= U) lo = mid; else hi = mid - 1;
+                const int32_t mid = lo + ((hi - lo + 1) >> 1);
+                if (ld128(Pc + 2 * (int64_t)mid) <= U) lo = mid; else hi = mid - 1;
             }
             atomicAdd(&d.bcopies[P.base + lo], 1);
         }
@@ -716,7 +765,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_close(Dev d)
 }
 
 template <int DIM>
-int enqueue_sp2_bootstrap(const Dev &d, hipStream_t s, int grid, int grid_scan)
+int enqueue_sp2_bootstrap(const Dev &d, hipStream_t s, int grid, int grid_scan, int grid_draw)
 {
     hipLaunchKernelGGL(k_sp2_classify<DIM>, dim3(grid), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_close_classify, dim3(1), dim3(kThreads), 0, s, d, grid);
@@ -724,7 +773,7 @@ int enqueue_sp2_bootstrap(const Dev &d, hipStream_t s, int grid, int grid_scan)
     hipLaunchKernelGGL(k_sp2_tilescan, dim3(std::min(d.B, grid_scan)), dim3(kThreads), 0, s, d, grid);
     hipLaunchKernelGGL(k_close_sp2_tilescan, dim3(1), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_prefix, dim3(grid), dim3(kThreads), 0, s, d);
-    hipLaunchKernelGGL(k_sp2_draw, dim3(grid), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sp2_draw, dim3(grid_draw), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_cells, dim3(grid), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_round, dim3(grid), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sp2_close, dim3(1), dim3(kThreads), 0, s, d);
