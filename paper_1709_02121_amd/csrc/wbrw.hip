@@ -245,7 +245,7 @@ Layout make_layout(const wbrw_config *c)
         L.bcell = take(cur, C * 8);
         L.bP = take(cur, 2 * C * 16);
         L.bTile = take(cur, 2 * (size_t)L.tilesP * 16);
-        L.bG = take(cur, 2 * C * 4);
+        L.bG = take(cur, 2 * 4 * C * 4);
     }
     // everything below starts zeroed
     L.zero_begin = (cur + kAlign - 1) / kAlign * kAlign;

@@ -168,8 +168,8 @@ struct Dev {
     int64_t *bcell;             // [cap_total] cell or -1
     uint64_t *bP;               // [2][cap_total] 128-bit residual prefix (lo, hi interleaved)
     uint64_t *bTile;            // [2][tiles] 128-bit tile sums
-    int32_t *bG;                // [2][cap_total] draw guide per class, in the
-                                // instance's particle slots (sp2_guide_bits)
+    int32_t *bG;                // [2][4 cap_total] draw guide per class, four
+                                // slots per particle slot (sp2_guide_bits)
     int64_t *bcls_stat;         // [B][8]: N+, N-, S+, S-, sumk+, sumk-, Nr+, Nr-
     int64_t *tileD;             // [2][B+1] draw-tile plan (per class)
     int64_t *bscan_tiles;       // [B+1] tiles per instance for the residual scan

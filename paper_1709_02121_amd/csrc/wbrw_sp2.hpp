@@ -422,18 +422,19 @@ __global__ __launch_bounds__(kThreads) void k_close_sp2_tilescan(Dev d)
 
 // ---- draw guide ------------------------------------------------------------
 // A class with N_r draws splits the draws' 64 random bits into K = 2^bits
-// buckets by their top bits, K the largest power of two below N_r (one to
-// two draws per bucket).  Guide entry k < K
-// is the particle whose residual interval [P_i, P_i + r_i) holds the bucket's
-// least value B_k = floor(k R / K); entry K is n - 1.  A draw in bucket k has
-// B_k <= U <= B_(k+1), so its particle lies between entries k and k + 1 and
-// the search over that slice returns what the search over the whole prefix
-// does.  Since r_i < S_c, each interval spans less than K / N_r < 1
-// bucket: a particle writes at most one entry.  K + 1 <= N_r <= n entries fit
-// the instance's particle slots.
+// buckets by their top bits, K the largest power of two below 4 N_r.  Guide
+// entry k < K is the particle whose residual interval [P_i, P_i + r_i) holds
+// the bucket's least value B_k = floor(k R / K); entry K is n - 1.  A draw in
+// bucket k has B_k <= U <= B_(k+1), so its particle lies between entries k
+// and k + 1 and the search over that slice returns what the search over the
+// whole prefix does; mostly the slice is one particle, and there is no search.
+// Since r_i < S_c, an interval spans less than K / N_r < 4 buckets, so a
+// particle writes at most four entries.  The guide of an instance's class
+// has 4 slots per particle slot: K + 1 <= 4 N_r <= 4 n entries fit.
 __device__ __forceinline__ int sp2_guide_bits(int64_t Nr)
 {
-    return Nr >= 2 ? 63 - __clzll((unsigned long long)(Nr - 1)) : 0;   // K < N_r
+    // K < 4 N_r (K <= 2^30)
+    return Nr >= 2 ? min(30, 65 - __clzll((unsigned long long)(Nr - 1))) : 0;
 }
 
 __device__ __forceinline__ double u128_to_f64(u128 v)
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
             __syncthreads();
             const int gb = sp2_guide_bits(Nr);
             const u128 R = (u128)(uint64_t)st[kBS0 + c] * (u128)(uint64_t)Nr;
-            int32_t *G = d.bG + (int64_t)c * C + P.base;
+            int32_t *G = d.bG + 4 * ((int64_t)c * C + P.base);
             uint64_t *Pc = d.bP + 2 * (int64_t)c * C;
 #pragma unroll
             for (int j = 0; j < kPPT; ++j) {
@@ -549,8 +550,8 @@ __global__ __launch_bounds__(kThreads) void k_sp2_prefix(Dev d)
                                 (((u128)ehi[j] << 64) | elo[j]);
                 st128_nt(Pc + 2 * i, pc);
                 if (cl[j] == c && r[j] != 0ull) {
-                    const uint32_t k = sp2_guide_first(pc, gb, R);
-                    if (k < (1u << gb) && mul32_128(k, R) < ((pc + (u128)r[j]) << gb))
+                    const u128 end = (pc + (u128)r[j]) << gb;
+                    for (uint32_t k = sp2_guide_first(pc, gb, R); k < (1u << gb) && mul32_128(k, R) < end; ++k)
                         G[k] = (int32_t)li;
                 }
                 if (li == n - 1) G[1u << gb] = (int32_t)li;
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void k_sp2_draw(Dev d)
         const int64_t Nr = st[kBNr0 + c];
         const u128 R = (u128)(uint64_t)st[kBS0 + c] * (u128)(uint64_t)Nr;
         const uint64_t *Pc = d.bP + 2 * (int64_t)c * C + 2 * P.base;
-        const int32_t *G = d.bG + (int64_t)c * C + P.base;
+        const int32_t *G = d.bG + 4 * ((int64_t)c * C + P.base);
         const int gb = sp2_guide_bits(Nr);
         for (int j = 0; j < kTileR / kThreads; ++j) {
             const int64_t dd = (tc - plan[b]) * kTileR + (int64_t)j * kThreads + tid;
