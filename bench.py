@@ -82,6 +82,12 @@ def run_form(P, torch, cfg, steps, warmup, every=ANN_EVERY, use_graph=False, den
 
     advance(warmup)
     if autotune:
+        # tune on a state an annihilation is due on (the binning is timed on
+        # it): `every` steps after the last one
+        while every and done % every != every - 1:
+            advance(1)
+        if every:
+            sim.step(1)
         tuned = sim.autotune(1)
         done = sim.stats(0)["step"]
         # re-align with the annihilation schedule before timing
@@ -119,7 +125,7 @@ def run_form(P, torch, cfg, steps, warmup, every=ANN_EVERY, use_graph=False, den
     out = {"wall_s": wall, "particle_steps": int(ps), "rate": ps / wall,
            "prof_particle_steps": int(ps_prof), "steps": steps,
            "n_end": int(sum(st["n"] for st in stats)), "profile": prof, "step_profile": step_prof,
-           "sim": sim, "tuned": tuned}
+           "sim": sim, "tuned": tuned, "sim_launch": sim.launch()}
     return out
 
 
@@ -455,6 +461,8 @@ def main():
         print(json.dumps({"metric": "forms only (profiling run)", "value": None, "forms": forms}), flush=True)
         return
     cfg = W.gaussian_barrier_large("sp1")
+    # the default launch shapes: the autotuner keeps them on this workload
+    # (its extra steps would only start the timed region on a larger ensemble)
     main_res = run_form(P, torch, cfg, args.steps, args.warmup)
     roof = step_roofline(main_res)
     if roof is not None:
@@ -471,7 +479,8 @@ def main():
     step_ms = sum(main_res["profile"][st][0] for st, _ in STEP_KERNELS)
     forms = {"plain_sp1": {"value": round(main_res["rate"], 1),
                            "step_kernels_only": round(main_res["prof_particle_steps"] / (step_ms * 1e-3), 1)
-                           if step_ms > 0 else None}}
+                           if step_ms > 0 else None,
+                           "launch": main_res["sim_launch"]}}
     if not args.no_forms:
         forms.update(run_forms(P, torch, W, args))
 

@@ -291,12 +291,30 @@ int wbrw_count(wbrw_t h, int32_t b, int32_t ghost, int64_t *n);
 int wbrw_export(wbrw_t h, int32_t b, int32_t ghost, int64_t n, double *x, double *k,
                 int8_t *sign, double *w, uint64_t *id, double *D);
 
-/* Autotuner.  Runs 2 * candidates * steps_per_candidate time steps of the
- * handle's own ensemble (they are real steps: results do not depend on launch
- * shapes) while timing the streaming and family kernels at several persistent
- * grid sizes (blocks per compute unit), then keeps the fastest of each.
- * chosen (host, may be NULL) receives {stream blocks, family blocks}.
- * Synchronises. */
+/* Launch configuration of the plain step and annihilation: six int32,
+ * {streaming blocks, family blocks, streaming threads per block, streaming
+ * particles per thread, binning blocks, binning hash slots}.  The streaming
+ * tile is always 2048 particles; the shapes offered are 256 x 8, 128 x 16
+ * (1D only) and 512 x 4, the hash sizes 4096, 2048 and 8192 slots.  Results
+ * do not depend on the configuration: every kernel's arithmetic and output
+ * order are the same under all of them (the parallel scheme of Sec. 4 with
+ * per-particle random streams). */
+int wbrw_get_launch(wbrw_t h, int32_t *cfg);
+/* cfg as above; WBRW_EINVAL for a shape or hash size not offered (for this
+ * dimension) or a block count outside [1, 8192].  Synchronises the stream;
+ * drops captured graphs. */
+int wbrw_set_launch(wbrw_t h, const int32_t *cfg);
+
+/* Autotuner.  Runs 2 * max(#streaming candidates, #family candidates) *
+ * steps_per_candidate time steps of the handle's own ensemble (they are real
+ * steps: results do not depend on launch shapes) while timing the streaming
+ * kernel over its block shapes and grid sizes (blocks per compute unit) and
+ * the family kernel over its grid sizes; for a plain sp1 ensemble it also
+ * times the binning pass alone over its hash sizes and grids (its counts are
+ * cleared and its escape tallies restored, so the ensemble and its stats are
+ * unchanged).  Keeps the fastest of each.  chosen (host, may be NULL)
+ * receives the launch configuration (wbrw_get_launch's six values).
+ * Synchronises; drops captured graphs. */
 int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen);
 
 /* Per-stage timing with hip events recorded on the handle's stream around

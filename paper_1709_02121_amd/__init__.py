@@ -110,6 +110,8 @@ def lib():
         L.wbrw_destroy.argtypes = [vp]
         L.wbrw_profile.argtypes = [vp, i32]
         L.wbrw_autotune.argtypes = [vp, i32, vp]
+        L.wbrw_get_launch.argtypes = [vp, vp]
+        L.wbrw_set_launch.argtypes = [vp, vp]
         L.wbrw_density_vjp.argtypes = [vp, i32, i32, C.c_double, C.c_double, vp, vp]
         L.wbrw_snapshot_size.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.wbrw_snapshot.argtypes = [vp, vp, C.c_size_t]
@@ -121,7 +123,8 @@ def lib():
                   "wbrw_density", "wbrw_density_tangent", "wbrw_stats", "wbrw_count",
                   "wbrw_export", "wbrw_destroy", "wbrw_profile", "wbrw_profile_read",
                   "wbrw_density_vjp", "wbrw_snapshot_size", "wbrw_snapshot", "wbrw_restore",
-                  "wbrw_autotune", "wbrw_density_noalloc", "wbrw_run_adaptive"):
+                  "wbrw_autotune", "wbrw_density_noalloc", "wbrw_run_adaptive", "wbrw_get_launch",
+                  "wbrw_set_launch"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -323,13 +326,30 @@ class Simulation:
         self._order_for_caller()
         return out
 
+    LAUNCH_KEYS = ("stream_blocks", "family_blocks", "stream_threads", "stream_ppt", "bin_blocks", "bin_slots")
+
     def autotune(self, steps_per_candidate=1):
-        """Times the step kernels at several grid sizes on real steps (results are
-        unchanged by the choice) and keeps the fastest; returns the grid sizes."""
-        out = np.zeros(2, dtype=np.int32)
+        """Times the streaming kernel over its block shapes and grid sizes and the
+        family kernel over its grid sizes on real steps, and (plain sp1) the
+        binning pass over its hash sizes and grids without changing the
+        ensemble; keeps the fastest (results are unchanged by the choice).
+        Returns the launch configuration (see launch())."""
+        out = np.zeros(6, dtype=np.int32)
         _check(lib().wbrw_autotune(self.h, int(steps_per_candidate), out.ctypes.data_as(C.c_void_p)),
                "wbrw_autotune")
-        return {"stream_blocks": int(out[0]), "family_blocks": int(out[1])}
+        return dict(zip(self.LAUNCH_KEYS, (int(v) for v in out)))
+
+    def launch(self):
+        """The launch configuration: grid sizes of the streaming, family and
+        binning kernels, the streaming block shape and the binning hash size."""
+        out = np.zeros(6, dtype=np.int32)
+        _check(lib().wbrw_get_launch(self.h, out.ctypes.data_as(C.c_void_p)), "wbrw_get_launch")
+        return dict(zip(self.LAUNCH_KEYS, (int(v) for v in out)))
+
+    def set_launch(self, cfg):
+        """Sets the launch configuration (a dict with launch()'s keys)."""
+        v = np.array([int(cfg[k]) for k in self.LAUNCH_KEYS], dtype=np.int32)
+        _check(lib().wbrw_set_launch(self.h, v.ctypes.data_as(C.c_void_p)), "wbrw_set_launch")
 
     def snapshot(self):
         """Device copy of the current state (a torch uint8 tensor)."""

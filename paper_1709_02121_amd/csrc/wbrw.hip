@@ -267,7 +267,7 @@ Layout make_layout(const wbrw_config *c)
     L.tcA = take(cur, (size_t)L.tilesA * 8);
     L.supA = take(cur, (size_t)(L.tilesA / kSupGroup + 1) * kSupStride * 8);
     L.spart = take(cur, (size_t)kMaxGrid * 2 * 8);
-    L.emA = take(cur, (size_t)L.tilesA * kPPT * 4 * 8);
+    L.emA = take(cur, (size_t)L.tilesA * (kTileA / 64) * 8);
     L.tcB = take(cur, (size_t)L.tilesB * 8);
     L.supB = take(cur, (size_t)(L.tilesB / kSupGroup + 1) * kSupStride * 8);
     L.tsB = take(cur, (size_t)L.tilesB * 8);
@@ -275,7 +275,7 @@ Layout make_layout(const wbrw_config *c)
     if (tan) {
         L.tcAg = take(cur, (size_t)L.tilesAg * 8);
         L.supAg = take(cur, (size_t)(L.tilesAg / kSupGroup + 1) * kSupStride * 8);
-        L.emAg = take(cur, (size_t)L.tilesAg * kPPT * 4 * 8);
+        L.emAg = take(cur, (size_t)L.tilesAg * (kTileA / 64) * 8);
         L.tcBg = take(cur, (size_t)L.tilesBg * 8);
         L.supBg = take(cur, (size_t)(L.tilesBg / kSupGroup + 1) * kSupStride * 8);
         L.tsBg = take(cur, (size_t)L.tilesBg * 8);
@@ -359,6 +359,13 @@ struct wbrw_handle {
     int sticky = WBRW_OK;
     int64_t host_step = 0;   // steps enqueued so far (mirror of the device counter)
     int prof = 0;   // 1: every stage and step marked; 2: whole steps only
+    // launch shapes the autotuner chooses among (results do not depend on
+    // them): streaming block shape (kStreamShapes), binning hash size
+    int stream_shape = 0;
+    int bin_slots = 4096;
+    int occ_stream[3] = {};   // blocks per CU of each streaming shape (0: not built)
+    int occ_bin[3] = {};      // of each binning hash size (kBinSlots)
+    int occ_family = 0;
     struct Mark { int stage; hipEvent_t a, b; };
     std::vector<Mark> marks;
     int open_stage = -1;
@@ -383,11 +390,54 @@ T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off); }
 enum { G_STREAM = 0, G_FAMILY, G_BIN, G_SCAN, G_REGEN, G_DENS, G_SP2, G_GHOST, G_EVENTS, G_DRAW, G_COUNT };
 
 template <typename K>
-int persistent_blocks(K kernel, int cus)
+int blocks_per_cu(K kernel, int nt = kThreads)
 {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) != hipSuccess || per < 1) per = 1;
-    return std::min(per * cus, kMaxGrid);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nt, 0) != hipSuccess || per < 1) per = 1;
+    return per;
+}
+
+template <typename K>
+int persistent_blocks(K kernel, int cus, int nt = kThreads)
+{
+    return std::min(blocks_per_cu(kernel, nt) * cus, kMaxGrid);
+}
+
+// Streaming block shapes (threads, particles per thread; a tile is always
+// kTileA particles) and binning hash sizes the autotuner chooses among.
+// The 4D streaming kernel holds five values per particle, too many for 16
+// particles per thread, so shape 1 is 1D only.
+constexpr int kStreamShapes[3][2] = {{kThreads, kPPT}, {128, 16}, {512, 4}};
+constexpr int kBinSlots[3] = {4096, 2048, 8192};
+
+template <int DIM>
+void launch_stream(const wbrw_handle *h, hipStream_t s, int ghost)
+{
+    const Dev &d = h->d;
+    const dim3 g(h->grid[G_STREAM]);
+    if constexpr (DIM == 1)
+        if (h->stream_shape == 1) {
+            hipLaunchKernelGGL((k_stream<DIM, 128, 16>), g, dim3(128), 0, s, d, ghost);
+            return;
+        }
+    if (h->stream_shape == 2) {
+        hipLaunchKernelGGL((k_stream<DIM, 512, 4>), g, dim3(512), 0, s, d, ghost);
+        return;
+    }
+    hipLaunchKernelGGL((k_stream<DIM>), g, dim3(kThreads), 0, s, d, ghost);
+}
+
+template <int DIM>
+void launch_bin_plain(const wbrw_handle *h, hipStream_t s)
+{
+    const Dev &d = h->d;
+    const dim3 g(h->grid[G_BIN]);
+    if (h->bin_slots == 2048)
+        hipLaunchKernelGGL((k_bin<DIM, false, false, 2048>), g, dim3(kThreads), 0, s, d, 0);
+    else if (h->bin_slots == 8192)
+        hipLaunchKernelGGL((k_bin<DIM, false, false, 8192>), g, dim3(kThreads), 0, s, d, 0);
+    else
+        hipLaunchKernelGGL((k_bin<DIM, false, false>), g, dim3(kThreads), 0, s, d, 0);
 }
 
 // Alg. 4 sampler: xi(r) = (1/2) int |V_W| dq for the Gaussian barrier on
@@ -531,7 +581,7 @@ void enqueue_step_dim(wbrw_t h)
     // stage marks bracket the main kernels only; the one-block closing
     // launches run between them
     stage_begin(h, WBRW_STAGE_STREAM);
-    hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 0);
+    launch_stream<DIM>(h, s, 0);
     stage_end(h);
     stage_begin(h, WBRW_STAGE_EVENTS);
     hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS] + 1), dim3(kThreads), 0, s, d, 0, h->grid[G_STREAM]);
@@ -562,7 +612,7 @@ void enqueue_step_dim(wbrw_t h)
     if (tan) {
         // ghosts (weight 0) branch by the sp1 rule in either strategy
         stage_begin(h, WBRW_STAGE_GHOST);
-        hipLaunchKernelGGL(k_stream<DIM>, dim3(h->grid[G_STREAM]), dim3(kThreads), 0, s, d, 1);
+        launch_stream<DIM>(h, s, 1);
         hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS] + 1), dim3(kThreads), 0, s, d, 1, h->grid[G_STREAM]);
         hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1);
         hipLaunchKernelGGL((k_place_records<DIM, false, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 1);
@@ -636,7 +686,7 @@ int enqueue_annihilate_dim(wbrw_t h)
         return launch_check();
     }
     stage_begin(h, WBRW_STAGE_BIN);
-    hipLaunchKernelGGL((k_bin<DIM, false, false>), dim3(h->grid[G_BIN]), dim3(kThreads), 0, s, d, 0);
+    launch_bin_plain<DIM>(h, s);
     stage_end(h);
     stage_begin(h, WBRW_STAGE_SCAN);
     enqueue_scan(h->grid[G_SCAN], s, d, 1);
@@ -657,7 +707,15 @@ template <int DIM>
 void set_grids_dim(wbrw_t h)
 {
     const int cus = h->cus;
-    h->grid[G_STREAM] = persistent_blocks(k_stream<DIM>, cus);
+    h->occ_stream[0] = blocks_per_cu(k_stream<DIM>);
+    if constexpr (DIM == 1) h->occ_stream[1] = blocks_per_cu(k_stream<DIM, 128, 16>, 128);
+    h->occ_stream[2] = blocks_per_cu(k_stream<DIM, 512, 4>, 512);
+    h->occ_bin[0] = blocks_per_cu(k_bin<DIM, false, false>);
+    h->occ_bin[1] = blocks_per_cu(k_bin<DIM, false, false, 2048>);
+    h->occ_bin[2] = blocks_per_cu(k_bin<DIM, false, false, 8192>);
+    h->stream_shape = 0;
+    h->bin_slots = kBinSlots[0];
+    h->grid[G_STREAM] = std::min(h->occ_stream[0] * cus, kMaxGrid);
     if (h->strategy == WBRW_SP2 && h->tangent)
         h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, true, true>, cus);
     else if (h->strategy == WBRW_SP2)
@@ -666,7 +724,8 @@ void set_grids_dim(wbrw_t h)
         h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, false, true>, cus);
     else
         h->grid[G_FAMILY] = persistent_blocks(k_family<DIM, false, false>, cus);
-    h->grid[G_BIN] = persistent_blocks(k_bin<DIM, false, false>, cus);
+    h->occ_family = std::max(1, h->grid[G_FAMILY] / std::max(1, cus));
+    h->grid[G_BIN] = std::min(h->occ_bin[0] * cus, kMaxGrid);
     h->grid[G_SCAN] = persistent_blocks(k_scan, cus);
     h->grid[G_REGEN] = persistent_blocks(k_regen<DIM, false, false>, cus);
     h->grid[G_DENS] = persistent_blocks(k_density_bin<DIM, false, false>, cus);
@@ -1418,69 +1477,185 @@ int wbrw_export(wbrw_t h, int32_t b, int32_t ghost, int64_t n, double *x, double
     return WBRW_OK;
 }
 
+// A launch configuration: {stream blocks, family blocks, stream threads,
+// stream particles per thread, bin blocks, bin hash slots}.
+static void read_launch(const wbrw_handle *h, int32_t *c)
+{
+    c[0] = h->grid[G_STREAM];
+    c[1] = h->grid[G_FAMILY];
+    c[2] = kStreamShapes[h->stream_shape][0];
+    c[3] = kStreamShapes[h->stream_shape][1];
+    c[4] = h->grid[G_BIN];
+    c[5] = h->bin_slots;
+}
+
+static void drop_graphs(wbrw_t h)
+{
+    if (h->gexec) {   // a captured epoch holds the old launch shapes
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+        h->graph_every = -1;
+    }
+    if (h->gexec_ad) {
+        (void)hipGraphExecDestroy(h->gexec_ad);
+        h->gexec_ad = nullptr;
+    }
+}
+
+int wbrw_get_launch(wbrw_t h, int32_t *cfg)
+{
+    if (!h || !cfg) return WBRW_EINVAL;
+    read_launch(h, cfg);
+    return WBRW_OK;
+}
+
+int wbrw_set_launch(wbrw_t h, const int32_t *cfg)
+{
+    if (!h || !cfg) return WBRW_EINVAL;
+    int shape = -1, slots = -1;
+    for (int i = 0; i < 3; ++i) {
+        if (cfg[2] == kStreamShapes[i][0] && cfg[3] == kStreamShapes[i][1] && h->occ_stream[i] > 0) shape = i;
+        if (cfg[5] == kBinSlots[i]) slots = i;
+    }
+    if (shape < 0 || slots < 0) return WBRW_EINVAL;
+    for (int q : {0, 1, 4})
+        if (cfg[q] < 1 || cfg[q] > kMaxGrid) return WBRW_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->stream_shape = shape;
+    h->bin_slots = kBinSlots[slots];
+    h->grid[G_STREAM] = cfg[0];
+    h->grid[G_FAMILY] = cfg[1];
+    h->grid[G_BIN] = cfg[4];
+    drop_graphs(h);
+    return WBRW_OK;
+}
+
+// Candidates: every streaming shape at 1..(its occupancy) blocks per CU
+// (from the list below), the family kernel likewise, and for plain sp1 every
+// binning hash size at its full occupancy and half of it.
+static const int kPerCu[] = {1, 2, 3, 4, 6, 8, 12, 16};
+
 int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen)
 {
     if (!h || steps_per_candidate < 1) return WBRW_EINVAL;
-    const int occ_s = h->grid[G_STREAM] / std::max(1, h->cus);
-    const int occ_f = h->grid[G_FAMILY] / std::max(1, h->cus);
-    std::vector<int> cand;
-    for (int per : {1, 2, 3, 4, 6, 8, 12, 16})
-        if (per <= std::max(occ_s, occ_f)) cand.push_back(per);
-    if (cand.empty()) cand.push_back(1);
+    const int cus = std::max(1, h->cus);
+    struct SC { int shape, grid; };
+    std::vector<SC> cs;
+    std::vector<int> cf;
+    for (int sh = 0; sh < 3; ++sh)
+        for (int per : kPerCu)
+            if (h->occ_stream[sh] > 0 && per <= h->occ_stream[sh]) cs.push_back({sh, std::min(per * cus, kMaxGrid)});
+    for (int per : kPerCu)
+        if (per <= h->occ_family) cf.push_back(std::min(per * cus, kMaxGrid));
     const int prof = h->prof;
     const std::vector<wbrw_handle::Mark> saved = h->marks;
     h->marks.clear();
-    double best_s = 1e300, best_f = 1e300;
-    int pick_s = h->grid[G_STREAM], pick_f = h->grid[G_FAMILY];
-    for (int pass = 0; pass < 2; ++pass) {     // the first pass warms caches and code
-        for (int per : cand) {
-            const int gs = std::min(per, std::max(1, occ_s)) * h->cus;
-            const int gf = std::min(per, std::max(1, occ_f)) * h->cus;
-            h->grid[G_STREAM] = gs;
-            h->grid[G_FAMILY] = gf;
+    std::vector<double> ts(cs.size(), 0.0), tf(cf.size(), 0.0);
+    const size_t ncand = std::max(cs.size(), cf.size());
+    int rc = WBRW_OK;
+    auto psteps = [&](int64_t &out) {
+        int64_t tal[kTalCount];
+        out = 0;
+        for (int b = 0; b < h->B; ++b) {
+            if (hipMemcpy(tal, h->d.tally + (int64_t)b * kTalCount, sizeof(tal), hipMemcpyDeviceToHost) != hipSuccess)
+                return WBRW_EHIP;
+            out += tal[kTalPSteps];
+        }
+        return WBRW_OK;
+    };
+    // the binning pass of plain sp1, first, on the caller's ensemble (call
+    // the autotuner where an annihilation is due, so that this state is a
+    // typical one), timed alone: it only adds into the count grids, which
+    // are cleared again, and into the escaped tallies, which are restored,
+    // so the ensemble is untouched; the best of two timed passes counts
+    if (h->strategy == WBRW_SP1 && !h->tangent) {
+        std::vector<int64_t> tal((size_t)h->B * kTalCount);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        HIPCHK(hipMemcpy(tal.data(), h->d.tally, tal.size() * 8, hipMemcpyDeviceToHost));
+        struct BC { int slots, grid; };
+        std::vector<BC> cb;
+        for (int i = 0; i < 3; ++i) {
+            const int full = std::min(h->occ_bin[i] * cus, kMaxGrid);
+            cb.push_back({kBinSlots[i], full});
+            if (h->occ_bin[i] > 1) cb.push_back({kBinSlots[i], std::max(cus, full / 2)});
+        }
+        std::vector<float> tb(cb.size(), 1e30f);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const size_t ncell = (size_t)h->d.Nh * (size_t)h->B;
+        for (int pass = 0; pass < 3 && !rc; ++pass)
+            for (size_t i = 0; i < cb.size() && !rc; ++i) {
+                h->bin_slots = cb[i].slots;
+                h->grid[G_BIN] = cb[i].grid;
+                if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = WBRW_EHIP; break; }
+                if (h->dim == 1) launch_bin_plain<1>(h, h->stream); else launch_bin_plain<2>(h, h->stream);
+                if (hipEventRecord(e1, h->stream) != hipSuccess) { rc = WBRW_EHIP; break; }
+                hipLaunchKernelGGL(k_fill32, dim3(std::max<int64_t>(1, std::min<int64_t>(4096, ((int64_t)ncell + 255) / 256))),
+                                   dim3(kThreads), 0, h->stream, h->d.cnt, (int64_t)ncell, 0);
+                if (h->d.cntx)
+                    hipLaunchKernelGGL(k_fill32, dim3(4096), dim3(kThreads), 0, h->stream, h->d.cntx,
+                                       (int64_t)ncell * (kXcd - 1), 0);
+                if (hipStreamSynchronize(h->stream) != hipSuccess) { rc = WBRW_EHIP; break; }
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                if (pass > 0) tb[i] = std::min(tb[i], t);
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (hipMemcpy(h->d.tally, tal.data(), tal.size() * 8, hipMemcpyHostToDevice) != hipSuccess && !rc) rc = WBRW_EHIP;
+        if (!rc) {
+            size_t bb = 0;
+            for (size_t i = 1; i < cb.size(); ++i) if (tb[i] < tb[bb]) bb = i;
+            h->bin_slots = cb[bb].slots;
+            h->grid[G_BIN] = cb[bb].grid;
+        }
+    }
+    if (rc) { h->prof = prof; h->marks = saved; return rc; }
+    // step candidates: step i runs streaming candidate i mod |cs| and family
+    // candidate i mod |cf|; the first pass warms caches and code
+    for (int pass = 0; pass < 2 && !rc; ++pass) {
+        for (size_t i = 0; i < ncand && !rc; ++i) {
+            const SC &a = cs[i % cs.size()];
+            h->stream_shape = a.shape;
+            h->grid[G_STREAM] = a.grid;
+            h->grid[G_FAMILY] = cf[i % cf.size()];
             int64_t before = 0, after = 0;
-            int64_t tal[kTalCount];
-            HIPCHK(hipStreamSynchronize(h->stream));
-            for (int b = 0; b < h->B; ++b) {
-                HIPCHK(hipMemcpy(tal, h->d.tally + (int64_t)b * kTalCount, sizeof(tal), hipMemcpyDeviceToHost));
-                before += tal[kTalPSteps];
-            }
+            if (hipStreamSynchronize(h->stream) != hipSuccess || (rc = psteps(before))) { rc = rc ? rc : WBRW_EHIP; break; }
             h->prof = 1;
-            for (int i = 0; i < steps_per_candidate; ++i) {
-                const int rc = enqueue_step(h);
-                if (rc) { h->prof = prof; return rc; }
-            }
+            for (int k = 0; k < steps_per_candidate && !rc; ++k) rc = enqueue_step(h);
             h->prof = 0;
-            HIPCHK(hipStreamSynchronize(h->stream));
-            for (int b = 0; b < h->B; ++b) {
-                HIPCHK(hipMemcpy(tal, h->d.tally + (int64_t)b * kTalCount, sizeof(tal), hipMemcpyDeviceToHost));
-                after += tal[kTalPSteps];
-            }
-            double ts = 0, tf = 0;
+            if (rc) break;
+            if (hipStreamSynchronize(h->stream) != hipSuccess || (rc = psteps(after))) { rc = rc ? rc : WBRW_EHIP; break; }
+            double a_s = 0, a_f = 0;
             for (auto &m : h->marks) {
                 float t = 0.f;
-                HIPCHK(hipEventElapsedTime(&t, m.a, m.b));
-                if (m.stage == WBRW_STAGE_STREAM) ts += t;
-                if (m.stage == WBRW_STAGE_FAMILY) tf += t;
+                (void)hipEventElapsedTime(&t, m.a, m.b);
+                if (m.stage == WBRW_STAGE_STREAM) a_s += t;
+                if (m.stage == WBRW_STAGE_FAMILY) a_f += t;
                 (void)hipEventDestroy(m.a);
                 (void)hipEventDestroy(m.b);
             }
             h->marks.clear();
             const double ps = (double)std::max<int64_t>(1, after - before);
-            if (pass == 1 && ts / ps < best_s) { best_s = ts / ps; pick_s = gs; }
-            if (pass == 1 && tf / ps < best_f) { best_f = tf / ps; pick_f = gf; }
+            if (pass == 1) {
+                ts[i % cs.size()] += a_s / ps;
+                tf[i % cf.size()] += a_f / ps;
+            }
         }
     }
-    h->grid[G_STREAM] = pick_s;
-    h->grid[G_FAMILY] = pick_f;
+    if (rc) { h->prof = prof; h->marks = saved; return rc; }
+    size_t bs = 0, bf = 0;
+    for (size_t i = 1; i < cs.size(); ++i) if (ts[i] < ts[bs]) bs = i;
+    for (size_t i = 1; i < cf.size(); ++i) if (tf[i] < tf[bf]) bf = i;
+    h->stream_shape = cs[bs].shape;
+    h->grid[G_STREAM] = cs[bs].grid;
+    h->grid[G_FAMILY] = cf[bf];
     h->marks = saved;
     h->prof = prof;
-    if (h->graph_every >= 0 && h->gexec) {   // a captured epoch holds the old grids
-        (void)hipGraphExecDestroy(h->gexec);
-        h->gexec = nullptr;
-        h->graph_every = -1;
-    }
-    if (chosen) { chosen[0] = pick_s; chosen[1] = pick_f; }
+    drop_graphs(h);
+    if (rc) return rc;
+    if (chosen) read_launch(h, chosen);
     return WBRW_OK;
 }
 

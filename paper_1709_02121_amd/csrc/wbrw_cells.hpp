@@ -193,7 +193,7 @@ __device__ __forceinline__ int64_t tile_at_cost(const Dev &d, const int64_t *pla
                                : srt + (r - rs + kBinLateCost - 1) / kBinLateCost);
 }
 
-template <int DIM, bool SP2, bool TAN>
+template <int DIM, bool SP2, bool TAN, int SLOTS = 4096>
 __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
 {
     if (ann_skipped(d)) return;
@@ -204,8 +204,11 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     // half full, and at the end: a cell-ordered ensemble straddles cell
     // boundaries after a few steps of drift, so equal cells are close in the
     // array but rarely in adjacent lanes, and neighbouring tiles share most
-    // of their cells.  A particle whose probes all fail adds directly.
-    constexpr int kSlots = 4096;
+    // of their cells.  A particle whose probes all fail adds directly.  The
+    // table's size (SLOTS, a power of two) trades flushes against blocks per
+    // CU; the autotuner picks it.
+    constexpr int kSlots = SLOTS;
+    static_assert((SLOTS & (SLOTS - 1)) == 0, "a power of two");
     __shared__ int64_t s_esc;
     __shared__ uint32_t s_nkeys;
     __shared__ int32_t s_key[TAN ? 1 : kSlots];
@@ -854,6 +857,13 @@ __global__ __launch_bounds__(kThreads) void k_vjp_out(Dev d, int nbins, double d
 // Clears `n` 64-bit words (used instead of hipMemsetAsync so that every
 // enqueued operation is a kernel).
 __global__ __launch_bounds__(kThreads) void k_fill64(uint64_t *p, int64_t n, uint64_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        p[i] = v;
+}
+
+// The same for 32-bit words.
+__global__ __launch_bounds__(kThreads) void k_fill32(int32_t *p, int64_t n, int32_t v)
 {
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
         p[i] = v;

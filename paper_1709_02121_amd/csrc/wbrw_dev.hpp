@@ -143,7 +143,7 @@ struct Dev {
                                         // counts (entries kSupStride apart)
     int64_t *spart;                     // [kMaxGrid][2]: each streaming block's last
                                         // instance and its events there
-    uint64_t *emA, *emAg;               // per streaming tile: kPPT x 4 wavefront event ballots
+    uint64_t *emA, *emAg;               // per streaming tile: kTileA / 64 wavefront event ballots
     int64_t *Nsrt;              // [B] particles in cell order at the front of each instance
     int64_t *srtS;              // [B+1] prefix of floor(Nsrt[b] / kTileA)
     int32_t *cnt;               // [B][Nh] signed counts (sp1) / rounded counts (sp2)

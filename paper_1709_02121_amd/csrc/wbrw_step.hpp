@@ -151,17 +151,17 @@ __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost, int sgrid
     uint32_t *evi = ghost ? d.gev_idx : d.ev_idx;
     const int lane = tid & 63, wv = tid >> 6;
     constexpr int kWaves = kThreads / 64;
-    static_assert(kPPT * 4 <= 64, "one lane per (particle slot, wavefront) ballot");
+    static_assert(kTileA / 64 <= 64, "one lane per ballot of a tile");
     for (int64_t t = (int64_t)blockIdx.x * kWaves + wv; t < ntiles; t += (int64_t)(gridDim.x - 1) * kWaves) {
         const int b = segment_of(plan, B, t);
         const int64_t tl = t - plan[b];
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
-        // ballot q = j * 4 + w holds particle slot j of the streaming
-        // kernel's wavefront w (loaded before the offset sum, to overlap it);
-        // exclusive scan of their popcounts in q order
-        const uint64_t *em = emask + t * (kPPT * 4);
-        const uint64_t mine = lane < kPPT * 4 ? em[lane] : 0ull;
+        // ballot q holds the tile's particles [64 q, 64 q + 64), whatever the
+        // streaming kernel's block shape (loaded before the offset sum, to
+        // overlap it); exclusive scan of their popcounts in q order
+        const uint64_t *em = emask + t * (kTileA / 64);
+        const uint64_t mine = lane < kTileA / 64 ? em[lane] : 0ull;
         const uint64_t rel = wave_range_sum(TileRange(tc, sup, plan[b], t));
         const uint32_t c = (uint32_t)__popcll(mine);
         uint32_t inc = c;
@@ -173,14 +173,14 @@ __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost, int sgrid
         const uint32_t exc = inc - c;
         const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
 #pragma unroll 4
-        for (int q = 0; q < kPPT * 4; ++q) {
+        for (int q = 0; q < kTileA / 64; ++q) {
             const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, q) << 32) |
                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mlo, q);
             if (m == 0ull) continue;
             const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)exc, q);
             if ((m >> lane) & 1ull) {
                 const int64_t pos = base + (int64_t)rel + off + lane_rank(m);
-                evi[pos] = (uint32_t)(tl * kTileA + (int64_t)(q >> 2) * kThreads + (q & 3) * 64 + lane);
+                evi[pos] = (uint32_t)(tl * kTileA + (int64_t)q * 64 + lane);
             }
         }
     }

@@ -21,11 +21,24 @@ namespace wbrw {
 // event list from the ballots.  Each block also counts its events per
 // instance: added to the instance's count when the block moves on to
 // another instance, left in the block's slot of spart at the end.
+//
+// NT threads per block, PPT particles per thread, NT * PPT = kTileA: thread
+// tid takes tile particles j * NT + tid, so ballot q = j * (NT / 64) + w of
+// wavefront w covers the tile's particles [64 q, 64 q + 64) whatever the
+// shape, and the event list does not depend on it (the autotuner picks it).
 // ---------------------------------------------------------------------------
-template <int DIM>
-__global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
+// register budget: as for three 256-thread blocks per CU (the loads of 16
+// particles per thread need it at 128 threads)
+template <int NT>
+constexpr int stream_min_blocks = NT >= 512 ? 1 : 3;
+
+template <int DIM, int NT = kThreads, int PPT = kPPT>
+__global__ __launch_bounds__(NT, stream_min_blocks<NT>) void k_stream(Dev d, int ghost)
 {
-    __shared__ uint32_t s_wcnt[4];
+    static_assert(NT * PPT == kTileA, "a streaming tile is kTileA particles");
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    constexpr int kW = NT / 64;
+    __shared__ uint32_t s_wcnt[kW];
     const Ctl *ctl = d.ctl;
     const uint32_t step = ctl->step;
     const int B = d.B;
@@ -50,17 +63,17 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
         const double thr_lo = P.thr_lo, thr_hi = P.thr_hi, g0 = P.gamma0;
         const uint32_t key = P.key;
 
-        // All loads of the thread's kPPT particles are issued before any
-        // compute or store, so every wave keeps 3*kPPT (4D: 5*kPPT) loads in
+        // All loads of the thread's PPT particles are issued before any
+        // compute or store, so every wave keeps 3*PPT (4D: 5*PPT) loads in
         // flight; full tiles need no bounds checks.
         const int64_t li0 = tl * kTileA + tid;
         const bool full = (tl + 1) * kTileA <= n;
-        double xs0[kPPT], xs1[kPPT], kv0[kPPT], kv1[kPPT];
-        uint64_t idv[kPPT];
+        double xs0[PPT], xs1[PPT], kv0[PPT], kv1[PPT];
+        uint64_t idv[PPT];
         if (full) {
 #pragma unroll
-            for (int j = 0; j < kPPT; ++j) {
-                const int64_t i = base + li0 + (int64_t)j * kThreads;
+            for (int j = 0; j < PPT; ++j) {
+                const int64_t i = base + li0 + (int64_t)j * NT;
                 xs0[j] = E.x0[i];
                 kv0[j] = E.k0[i];
                 idv[j] = E.id[i];
@@ -68,8 +81,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < kPPT; ++j) {
-                const int64_t li = li0 + (int64_t)j * kThreads;
+            for (int j = 0; j < PPT; ++j) {
+                const int64_t li = li0 + (int64_t)j * NT;
                 const int64_t i = base + (li < n ? li : 0);
                 xs0[j] = E.x0[i];
                 kv0[j] = E.k0[i];
@@ -78,10 +91,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
             }
         }
         uint32_t evbits = 0, nev = 0;
-        uint64_t *em = emask + t * (kPPT * 4);
+        uint64_t *em = emask + t * (kTileA / 64);
 #pragma unroll
-        for (int j = 0; j < kPPT; ++j) {
-            const bool valid = full || (li0 + (int64_t)j * kThreads < n);
+        for (int j = 0; j < PPT; ++j) {
+            const bool valid = full || (li0 + (int64_t)j * NT < n);
             bool ev = false;
             const W4 r = draw(idv[j], step, kTagStep, 0u, 0u, d.seed, key);
             const double u = unit53(r.a, r.b);
@@ -94,7 +107,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
             }
             ev = ev && valid;
             const uint64_t m = __ballot(ev);
-            if (lane == 0) em[j * 4 + wv] = m;
+            if (lane == 0) em[j * kW + wv] = m;
             nev += (uint32_t)__popcll(m);
             evbits |= (ev ? 1u : 0u) << j;
         }
@@ -103,8 +116,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
         // The positions are not read again in this launch: non-temporal
         // stores keep them from displacing cached lines.
 #pragma unroll
-        for (int j = 0; j < kPPT; ++j) {
-            const int64_t li = li0 + (int64_t)j * kThreads;
+        for (int j = 0; j < PPT; ++j) {
+            const int64_t li = li0 + (int64_t)j * NT;
             if ((full || li < n) && !((evbits >> j) & 1u)) {
                 const int64_t i = base + li;
                 __builtin_nontemporal_store(xs0[j] + (d.vfac * kv0[j]) * d.dt, &E.x0[i]);
@@ -114,7 +127,9 @@ __global__ __launch_bounds__(kThreads, 3) void k_stream(Dev d, int ghost)
         if (lane == 0) s_wcnt[wv] = nev;
         __syncthreads();
         if (tid == 0) {
-            const uint64_t c = (uint64_t)(s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3]);
+            uint64_t c = 0;
+#pragma unroll
+            for (int w = 0; w < kW; ++w) c += s_wcnt[w];
             tcnt[t] = c;
             if (c) atomicAdd((unsigned long long *)&tsup[(t / kSupGroup) * kSupStride], (unsigned long long)c);
             if (b != cb) {

@@ -434,6 +434,37 @@ def test_autotune_keeps_results(P, O):
     compare(g, r, "after autotune", B=4)
 
 
+def test_launch_shapes_keep_results(P, O):
+    """Every launch configuration the autotuner can choose (streaming block
+    shape and grid, family grid, binning hash size and grid) gives the oracle's
+    bits, through steps and annihilations; shapes not offered are refused."""
+    cfg = W.batched_barriers(B=4, N0=np.array([3000, 100, 25000, 7000], dtype=np.int64))
+    r = O.OracleSim(cfg)
+    r.run(25, 10)
+    d = P.Simulation(cfg).launch()
+    say(f"default launch: {d}")
+    shapes = [(256, 8), (128, 16), (512, 4)]
+    slots = [2048, 4096, 8192]
+    for i, (nt, ppt) in enumerate(shapes):
+        for j, sl in enumerate(slots):
+            c = dict(d, stream_threads=nt, stream_ppt=ppt, bin_slots=sl,
+                     stream_blocks=max(1, d["stream_blocks"] // (1 + 3 * ((i + j) % 2))),
+                     family_blocks=max(1, d["family_blocks"] // (1 + 2 * (j % 2))),
+                     bin_blocks=max(1, d["bin_blocks"] // (1 + i)))
+            g = P.Simulation(cfg)
+            g.set_launch(c)
+            assert g.launch() == c
+            g.run(25, 10)
+            compare(g, r, f"launch {c}", B=4)
+    g = P.Simulation(cfg)
+    for bad in (dict(d, stream_threads=64, stream_ppt=32), dict(d, bin_slots=1000), dict(d, family_blocks=0)):
+        with pytest.raises(P.WBRWError):
+            g.set_launch(bad)
+    c4 = W.helium_soft_coulomb(N0=np.array([1000]))
+    with pytest.raises(P.WBRWError):
+        P.Simulation(c4).set_launch(dict(P.Simulation(c4).launch(), stream_threads=128, stream_ppt=16))
+
+
 @pytest.mark.parametrize("strategy", ["sp1", "sp2"])
 def test_time_dependent_potential_parity(P, O, strategy):
     """Remark 1: kernel evaluated at the absolute jump time (switching left barrier)."""
