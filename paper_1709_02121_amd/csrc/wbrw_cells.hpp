@@ -278,6 +278,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
         const int64_t n = Ncur[b];
         const int64_t cbase = (int64_t)b * d.Nh;
         int64_t esc = 0;
+        uint32_t ins = 0;      // keys this thread added to the hash
         const int64_t li0 = (t - plan[b]) * kTileA + tid;
         double xa[kPPT], xb[kPPT], ka[kPPT], kb[kPPT];
         int sv[kPPT];
@@ -303,7 +304,11 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 if (!(isfinite(xa[j]) && isfinite(xb[j]) && isfinite(ka[j]) && isfinite(kb[j]))) err |= kErrRange;
             }
             if (!TAN) {
-                if (nu < 0 || s == 0) continue;
+                // lanes hold consecutive particles: equal-cell runs are summed
+                // in registers first, and only a run's last lane inserts
+                bool commit;
+                const int rs = run_sum<int>(nu, s, commit);
+                if (!commit || rs == 0) continue;
                 const int key = (int)nu;
                 const uint32_t h = ((uint32_t)key * 2654435761u) >> 20;
                 bool done = false;
@@ -312,14 +317,14 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                     int k = __hip_atomic_load(&s_key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     if (k == -1) {
                         k = atomicCAS(&s_key[slot], -1, key);
-                        if (k == -1) atomicAdd(&s_nkeys, 1u);
+                        if (k == -1) ++ins;
                     }
                     if (k == -1 || k == key) {
-                        atomicAdd(&s_val[slot], s);
+                        atomicAdd(&s_val[slot], rs);
                         done = true;
                     }
                 }
-                if (!done) atomicAdd(&cg[cbase + nu], s);
+                if (!done) atomicAdd(&cg[cbase + nu], rs);
             } else {
                 // lanes hold consecutive particles: sum equal-cell runs in
                 // registers, then one atomic per run
@@ -347,6 +352,12 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
             }
         }
         if (esc) atomicAdd((unsigned long long *)&s_esc, (unsigned long long)esc);
+        if (!TAN) {   // the tile's new keys, one LDS atomic per wavefront
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) ins += __shfl_xor(ins, o, 64);
+            if ((tid & 63) == 0 && ins) atomicAdd(&s_nkeys, ins);
+            ins = 0;
+        }
     }
     __syncthreads();
     if (cb >= 0) flush(cb);
