@@ -194,23 +194,25 @@ __global__ __launch_bounds__(kThreads) void k_sp2_close_classify(Dev d, int grid
 // Each block takes a contiguous run of tiles; the kept-copy sums per class
 // are summed per instance and left in fpart (instance changes, rare, add to
 // the counters) for k_sp2_tilescan.  The 128-bit residual sums are per tile.
-// floor(num / den) for num < 2^63, den > 0: a double-precision estimate,
-// exact to within one when the quotient is below 2^40, corrected with
-// integer arithmetic; larger quotients take the integer division.
-__device__ __forceinline__ uint64_t udiv_floor(uint64_t num, uint64_t den)
+
+// floor(num / den) and the remainder for num < 2^63, 0 < den < 2^63 and a
+// quotient below 2^32 (k_i <= N_c here), from rcp = 1/den in double: the
+// estimate num * rcp is within one of the quotient, and the remainder,
+// exact in 64-bit arithmetic since q den <= num + den < 2^64, corrects it.
+__device__ __forceinline__ uint64_t udiv_small(uint64_t num, uint64_t den, double rcp, uint64_t &rem)
 {
-    uint64_t q = (uint64_t)((double)num / (double)den);
-    if (q >= (1ull << 40)) return num / den;
-    const u128 p = (u128)q * den;
-    if (p > (u128)num) --q;
-    else if ((u128)num - p >= (u128)den) ++q;
+    uint64_t q = (uint64_t)((double)num * rcp);
+    int64_t r = (int64_t)(num - q * den);
+    while (r < 0) { --q; r += (int64_t)den; }
+    while ((uint64_t)r >= den) { ++q; r -= (int64_t)den; }
+    rem = (uint64_t)r;
     return q;
 }
 
 __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
 {
     if (ann_skipped(d)) return;
-    __shared__ unsigned long long s_acc[4];    // tile sums (lo,hi) x 2
+    __shared__ uint64_t s_wlo[2][kThreads / 64], s_whi[2][kThreads / 64];   // wavefront residual sums
     __shared__ unsigned long long s_w[kThreads / 64];
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -244,13 +246,13 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
             if (cb >= 0) publish(cb, false);
             cb = b;
         }
-        if (tid < 4) s_acc[tid] = 0ull;
         __syncthreads();
         const InstParam &P = d.ip[b];
         const int64_t n = d.N[b];
         const int64_t *st = d.bcls_stat + (int64_t)b * 8;
         const uint64_t Nc[2] = {(uint64_t)st[kBN0], (uint64_t)st[kBN1]};
         const uint64_t Sc[2] = {(uint64_t)st[kBS0], (uint64_t)st[kBS1]};
+        const double rcp[2] = {Sc[0] ? 1.0 / (double)Sc[0] : 0.0, Sc[1] ? 1.0 / (double)Sc[1] : 0.0};
         u128 rs[2] = {0, 0};
         const int64_t li0 = (t - plan[b]) * kTileA + tid;
         int8_t cv[kPPT];
@@ -271,28 +273,32 @@ __global__ __launch_bounds__(kThreads) void k_sp2_resid(Dev d)
             uint64_t k = 0, r = 0;
             if (c >= 0 && Sc[c] > 0) {
                 const uint64_t num = Nc[c] * av[j];       // < 2^63
-                k = udiv_floor(num, Sc[c]);
-                r = num - k * Sc[c];
+                k = udiv_small(num, Sc[c], rcp[c], r);
                 ks[c] += k;
                 rs[c] += r;
             }
             d.bcopies[i] = (int32_t)k;
             d.bA[i] = r;               // A_i is no longer needed: the residual
         }
-        // block sums: 64-bit halves of the 128-bit residual sums
+        // tile sums of the 128-bit residuals: within each wavefront (64-bit
+        // halves with carry), then the four wavefront sums by one thread
         for (int c = 0; c < 2; ++c) {
-            // residual sums of a thread stay < 2^66: add as lo + carry-free hi
-            const uint64_t lo = (uint64_t)rs[c], hi = (uint64_t)(rs[c] >> 64);
-            const unsigned long long old = atomicAdd(&s_acc[2 * c], (unsigned long long)lo);
-            const uint64_t carry = (old + lo < old) ? 1ull : 0ull;
-            if (hi + carry) atomicAdd(&s_acc[1 + 2 * c], (unsigned long long)(hi + carry));
+            uint64_t lo = (uint64_t)rs[c], hi = (uint64_t)(rs[c] >> 64);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint64_t plo = __shfl_xor(lo, o, 64), phi = __shfl_xor(hi, o, 64);
+                const uint64_t nlo = lo + plo;
+                hi = hi + phi + (nlo < lo ? 1ull : 0ull);
+                lo = nlo;
+            }
+            if ((tid & 63) == 0) { s_wlo[c][tid >> 6] = lo; s_whi[c][tid >> 6] = hi; }
         }
         __syncthreads();
         if (tid == 0) {
             for (int c = 0; c < 2; ++c) {
-                uint64_t *ts = d.bTile + 2 * ((int64_t)c * d.tstride + t);
-                ts[0] = s_acc[2 * c];
-                ts[1] = s_acc[1 + 2 * c];
+                u128 sum = 0;
+                for (int w = 0; w < kThreads / 64; ++w) sum += ((u128)s_whi[c][w] << 64) | s_wlo[c][w];
+                st128(d.bTile + 2 * ((int64_t)c * d.tstride + t), sum);
             }
         }
         __syncthreads();
