@@ -304,11 +304,8 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 if (!(isfinite(xa[j]) && isfinite(xb[j]) && isfinite(ka[j]) && isfinite(kb[j]))) err |= kErrRange;
             }
             if (!TAN) {
-                // lanes hold consecutive particles: equal-cell runs are summed
-                // in registers first, and only a run's last lane inserts
-                bool commit;
-                const int rs = run_sum<int>(nu, s, commit);
-                if (!commit || rs == 0) continue;
+                if (nu < 0 || s == 0) continue;
+                const int rs = s;
                 const int key = (int)nu;
                 const uint32_t h = ((uint32_t)key * 2654435761u) >> 20;
                 bool done = false;
