@@ -1550,7 +1550,8 @@ int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen)
     const int prof = h->prof;
     const std::vector<wbrw_handle::Mark> saved = h->marks;
     h->marks.clear();
-    std::vector<double> ts(cs.size(), 0.0), tf(cf.size(), 0.0);
+    std::vector<double> ts(cs.size(), 0.0), tf(cf.size(), 0.0);   // time per particle-step, summed
+    std::vector<int> ns(cs.size(), 0), nf(cf.size(), 0);             // timed runs of each
     const size_t ncand = std::max(cs.size(), cf.size());
     int rc = WBRW_OK;
     auto psteps = [&](int64_t &out) {
@@ -1570,8 +1571,11 @@ int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen)
     // so the ensemble is untouched; the best of two timed passes counts
     if (h->strategy == WBRW_SP1 && !h->tangent) {
         std::vector<int64_t> tal((size_t)h->B * kTalCount);
-        HIPCHK(hipStreamSynchronize(h->stream));
-        HIPCHK(hipMemcpy(tal.data(), h->d.tally, tal.size() * 8, hipMemcpyDeviceToHost));
+        if (hipStreamSynchronize(h->stream) != hipSuccess ||
+            hipMemcpy(tal.data(), h->d.tally, tal.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+            h->marks = saved;
+            return WBRW_EHIP;
+        }
         struct BC { int slots, grid; };
         std::vector<BC> cb;
         for (int i = 0; i < 3; ++i) {
@@ -1580,9 +1584,8 @@ int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen)
             if (h->occ_bin[i] > 1) cb.push_back({kBinSlots[i], std::max(cus, full / 2)});
         }
         std::vector<float> tb(cb.size(), 1e30f);
-        hipEvent_t e0, e1;
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = WBRW_EHIP;
         const size_t ncell = (size_t)h->d.Nh * (size_t)h->B;
         for (int pass = 0; pass < 3 && !rc; ++pass)
             for (size_t i = 0; i < cb.size() && !rc; ++i) {
@@ -1601,8 +1604,8 @@ int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen)
                 (void)hipEventElapsedTime(&t, e0, e1);
                 if (pass > 0) tb[i] = std::min(tb[i], t);
             }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
         if (hipMemcpy(h->d.tally, tal.data(), tal.size() * 8, hipMemcpyHostToDevice) != hipSuccess && !rc) rc = WBRW_EHIP;
         if (!rc) {
             size_t bb = 0;
@@ -1640,14 +1643,16 @@ int wbrw_autotune(wbrw_t h, int32_t steps_per_candidate, int32_t *chosen)
             const double ps = (double)std::max<int64_t>(1, after - before);
             if (pass == 1) {
                 ts[i % cs.size()] += a_s / ps;
+                ns[i % cs.size()] += 1;
                 tf[i % cf.size()] += a_f / ps;
+                nf[i % cf.size()] += 1;
             }
         }
     }
     if (rc) { h->prof = prof; h->marks = saved; return rc; }
-    size_t bs = 0, bf = 0;
-    for (size_t i = 1; i < cs.size(); ++i) if (ts[i] < ts[bs]) bs = i;
-    for (size_t i = 1; i < cf.size(); ++i) if (tf[i] < tf[bf]) bf = i;
+    size_t bs = 0, bf = 0;   // the least mean time per particle-step
+    for (size_t i = 1; i < cs.size(); ++i) if (ts[i] * ns[bs] < ts[bs] * ns[i]) bs = i;
+    for (size_t i = 1; i < cf.size(); ++i) if (tf[i] * nf[bf] < tf[bf] * nf[i]) bf = i;
     h->stream_shape = cs[bs].shape;
     h->grid[G_STREAM] = cs[bs].grid;
     h->grid[G_FAMILY] = cf[bf];
