@@ -230,6 +230,21 @@ def test_sp2_batched_and_wide(P, O):
     compare(g, r, "sp2 batched", B=3)
 
 
+def test_sp2_tiny_instances(P, O):
+    """sp2 on instances of 1 to 300 particles: sign classes with no draw, one
+    draw and a few (the draw guide's one- and four-bucket cases, a residual
+    prefix shorter than a tile), through three annihilations."""
+    n0 = np.array([1, 2, 3, 5, 8, 13, 40, 300], dtype=np.int64)
+    cfg = W.batched_barriers(B=len(n0), N0=n0, strategy="sp2")
+    g, r = P.Simulation(cfg), O.OracleSim(cfg)
+    for ep in range(3):
+        g.run(4, 4)
+        r.run(4, 4)
+        compare(g, r, f"sp2 tiny instances, epoch {ep}", B=len(n0))
+    st = [r.stats(b) for b in range(len(n0))]
+    say("sp2 tiny: n " + ", ".join(str(x["n"]) for x in st))
+
+
 def _exact(a, b, what):
     """Tangents and their readouts: bit-identical.  Every sum of tangents is an
     exact 32.32 fixed-point integer sum on both sides, so the GPU's order of
