@@ -207,12 +207,19 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     // of their cells.  A particle whose probes all fail adds directly.  The
     // table's size (SLOTS, a power of two) trades flushes against blocks per
     // CU; the autotuner picks it.
-    constexpr int kSlots = SLOTS;
+    // With tangents the table's slots hold, per cell, the count, the
+    // occupancy and the six 32.32 fixed-point halves of the tangent sums
+    // (kTSlots of them), and each run of equal cells in consecutive lanes,
+    // summed in registers first, adds to its slot with LDS atomics.
+    constexpr int kSlots = TAN ? 512 : SLOTS;
     static_assert((SLOTS & (SLOTS - 1)) == 0, "a power of two");
+    constexpr int kHashShift = 32 - (TAN ? 9 : 12);
     __shared__ int64_t s_esc;
     __shared__ uint32_t s_nkeys;
-    __shared__ int32_t s_key[TAN ? 1 : kSlots];
-    __shared__ int32_t s_val[TAN ? 1 : kSlots];
+    __shared__ int32_t s_key[kSlots];
+    __shared__ int32_t s_val[kSlots];                      // count
+    __shared__ int32_t s_occ[TAN ? kSlots : 1];
+    __shared__ unsigned long long s_tq[TAN ? 6 : 1][TAN ? kSlots : 1];
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t *plan = d.tileA + (int64_t)ghost * (B + 1);
@@ -229,19 +236,34 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
     int32_t *const og = own ? d.occ : d.occx + (int64_t)(xc - 1) * ncell;
     int64_t *const tg = own ? d.Tq : d.Tqx + (int64_t)(xc - 1) * 6 * ncell;
     uint32_t err = 0;
-    if (!TAN)
-        for (int j = tid; j < kSlots; j += kThreads) { s_key[j] = -1; s_val[j] = 0; }
+    for (int j = tid; j < kSlots; j += kThreads) {
+        s_key[j] = -1;
+        s_val[j] = 0;
+        if constexpr (TAN) {
+            s_occ[j] = 0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s_tq[q][j] = 0ull;
+        }
+    }
     if (tid == 0) { s_esc = 0; s_nkeys = 0; }
     auto flush = [&](int fb) {
-        if (!TAN) {
-            const int64_t fbase = (int64_t)fb * d.Nh;
-            for (int j = tid; j < kSlots; j += kThreads) {
-                const int k = s_key[j];
-                if (k < 0) continue;
-                const int v = s_val[j];
-                if (v != 0) atomicAdd(&cg[fbase + k], v);
-                s_key[j] = -1;
-                s_val[j] = 0;
+        const int64_t fbase = (int64_t)fb * d.Nh;
+        for (int j = tid; j < kSlots; j += kThreads) {
+            const int k = s_key[j];
+            if (k < 0) continue;
+            const int v = s_val[j];
+            if (v != 0) atomicAdd(&cg[fbase + k], v);
+            s_key[j] = -1;
+            s_val[j] = 0;
+            if constexpr (TAN) {
+                if (s_occ[j] != 0) atomicAdd(&og[fbase + k], s_occ[j]);
+                s_occ[j] = 0;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    const unsigned long long t = s_tq[q][j];
+                    if (t) atomicAdd((unsigned long long *)&tg[(int64_t)q * ncell + fbase + k], t);
+                    s_tq[q][j] = 0ull;
+                }
             }
         }
         if (tid == 0) {
@@ -307,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 if (nu < 0 || s == 0) continue;
                 const int rs = s;
                 const int key = (int)nu;
-                const uint32_t h = ((uint32_t)key * 2654435761u) >> 20;
+                const uint32_t h = ((uint32_t)key * 2654435761u) >> kHashShift;
                 bool done = false;
                 for (int pr = 0; pr < 8 && !done; ++pr) {
                     const int slot = (int)((h + (uint32_t)pr) & (uint32_t)(kSlots - 1));
@@ -324,32 +346,54 @@ __global__ __launch_bounds__(kThreads) void k_bin(Dev d, int ghost)
                 if (!done) atomicAdd(&cg[cbase + nu], rs);
             } else {
                 // lanes hold consecutive particles: sum equal-cell runs in
-                // registers, then one atomic per run
+                // registers, then the run's last lane adds them to the cell's
+                // slot (sp2's cell counts come from the bootstrap)
                 bool commit;
-                if (!ghost && !SP2) {   // sp2's cell counts come from the bootstrap
-                    const int ns = run_sum<int>(nu, nu >= 0 ? s : 0, commit);
-                    if (commit && ns != 0) atomicAdd(&cg[cbase + nu], ns);
-                }
+                const bool cnt = !ghost && !SP2;
+                const int ns = run_sum<int>(nu, (cnt && nu >= 0) ? s : 0, commit);
                 const bool in = nu >= 0;
                 const int64_t ds = ghost ? d.gcap_total : d.cap_total;
                 const int no = run_sum<int>(nu, in ? 1 : 0, commit);
+                unsigned long long tq[6];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     int64_t hi = 0;
                     uint64_t lo = 0;
                     if (in && !fx_split(E.D[c * ds + i], hi, lo)) err |= kErrRange;
-                    hi = run_sum<int64_t>(nu, hi, commit);
-                    lo = run_sum<uint64_t>(nu, lo, commit);
-                    if (commit) {
-                        if (hi) atomicAdd((unsigned long long *)&tg[(2 * c) * ncell + cbase + nu], (unsigned long long)hi);
-                        if (lo) atomicAdd((unsigned long long *)&tg[(2 * c + 1) * ncell + cbase + nu], (unsigned long long)lo);
+                    tq[2 * c] = (unsigned long long)run_sum<int64_t>(nu, hi, commit);
+                    tq[2 * c + 1] = (unsigned long long)run_sum<uint64_t>(nu, lo, commit);
+                }
+                if (commit) {
+                    const int key = (int)nu;
+                    const uint32_t h = ((uint32_t)key * 2654435761u) >> kHashShift;
+                    int slot = -1;
+                    for (int pr = 0; pr < 8 && slot < 0; ++pr) {
+                        const int sl = (int)((h + (uint32_t)pr) & (uint32_t)(kSlots - 1));
+                        int k = __hip_atomic_load(&s_key[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (k == -1) {
+                            k = atomicCAS(&s_key[sl], -1, key);
+                            if (k == -1) ++ins;
+                        }
+                        if (k == -1 || k == key) slot = sl;
+                    }
+                    if (slot >= 0) {
+                        if (ns) atomicAdd(&s_val[slot], ns);
+                        atomicAdd(&s_occ[slot], no);
+#pragma unroll
+                        for (int q = 0; q < 6; ++q)
+                            if (tq[q]) atomicAdd(&s_tq[q][slot], tq[q]);
+                    } else {   // every probe taken: straight to the grids
+                        if (ns) atomicAdd(&cg[cbase + nu], ns);
+                        atomicAdd(&og[cbase + nu], no);
+#pragma unroll
+                        for (int q = 0; q < 6; ++q)
+                            if (tq[q]) atomicAdd((unsigned long long *)&tg[(int64_t)q * ncell + cbase + nu], tq[q]);
                     }
                 }
-                if (commit) atomicAdd(&og[cbase + nu], no);
             }
         }
         if (esc) atomicAdd((unsigned long long *)&s_esc, (unsigned long long)esc);
-        if (!TAN) {   // the tile's new keys, one LDS atomic per wavefront
+        {   // the tile's new keys, one LDS atomic per wavefront
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) ins += __shfl_xor(ins, o, 64);
             if ((tid & 63) == 0 && ins) atomicAdd(&s_nkeys, ins);
