@@ -387,7 +387,7 @@ namespace {
 template <typename T>
 T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off); }
 
-enum { G_STREAM = 0, G_FAMILY, G_BIN, G_SCAN, G_REGEN, G_DENS, G_SP2, G_GHOST, G_EVENTS, G_DRAW, G_COUNT };
+enum { G_STREAM = 0, G_FAMILY, G_BIN, G_SCAN, G_REGEN, G_DENS, G_SP2, G_GHOST, G_EVENTS, G_DRAW, G_DENST, G_COUNT };
 
 template <typename K>
 int blocks_per_cu(K kernel, int nt = kThreads)
@@ -729,6 +729,7 @@ void set_grids_dim(wbrw_t h)
     h->grid[G_SCAN] = persistent_blocks(k_scan, cus);
     h->grid[G_REGEN] = persistent_blocks(k_regen<DIM, false, false>, cus);
     h->grid[G_DENS] = persistent_blocks(k_density_bin<DIM, false, false>, cus);
+    h->grid[G_DENST] = persistent_blocks(k_density_bin<1, false, true>, cus);
     h->grid[G_SP2] = persistent_blocks(k_sp2_classify<DIM>, cus);
     h->grid[G_GHOST] = persistent_blocks(k_ghosts, cus);
     h->grid[G_EVENTS] = persistent_blocks(k_events, cus);
@@ -1196,8 +1197,8 @@ int wbrw_density_tangent(wbrw_t h, int32_t axis, int32_t nbins, double lo, doubl
     const double dxb = (hi - lo) / (double)nbins;
     const Dev &d = h->d;
     hipStream_t s = h->stream;
-    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
-    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 1, axis, nbins, lo, dxb);
+    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENST]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENST]), dim3(kThreads), 0, s, d, 1, axis, nbins, lo, dxb);
     const int outb = std::max(1, std::min(h->cus * 4, (int)ceil_div((int64_t)h->B * 3 * nbins, kThreads)));
     hipLaunchKernelGGL((k_density_out<false, true>), dim3(outb), dim3(kThreads), 0, s, d, nbins, dxb, d_out);
     return launch_check();
@@ -1214,9 +1215,9 @@ int wbrw_density_vjp(wbrw_t h, int32_t axis, int32_t nbins, double lo, double hi
     // the tangent bin sums (fixed point, real particles and ghosts), then the
     // contraction with g in bin order
     stage_begin(h, WBRW_STAGE_DENSITY);
-    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
-    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENS]), dim3(kThreads), 0, s, d, 1, axis, nbins, lo, dxb);
-    const int ob = std::max(1, (int)ceil_div((int64_t)h->B * 3, kThreads));
+    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENST]), dim3(kThreads), 0, s, d, 0, axis, nbins, lo, dxb);
+    hipLaunchKernelGGL((k_density_bin<1, false, true>), dim3(h->grid[G_DENST]), dim3(kThreads), 0, s, d, 1, axis, nbins, lo, dxb);
+    const int ob = std::max(1, (int)ceil_div((int64_t)h->B * 3, kThreads / 64));   // a wavefront each
     hipLaunchKernelGGL(k_vjp_out, dim3(ob), dim3(kThreads), 0, s, d, nbins, dxb, g, grad_out);
     stage_end(h);
     return launch_check();

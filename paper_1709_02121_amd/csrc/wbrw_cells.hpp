@@ -726,8 +726,10 @@ __global__ __launch_bounds__(kThreads) void k_density_bin(Dev d, int ghost, int 
     // in LDS and adds its non-zero bins to the global accumulator when its
     // tiles move on to the next instance and when it runs out of tiles.
     // Integer weights (signs, 32.32 fixed-point weights) sum exactly in any
-    // order.  Histograms wider than the LDS array go straight to HBM.
-    constexpr int kLds = 4096;
+    // order.  Histograms wider than the LDS array go straight to HBM.  The
+    // tangent histogram (six words per bin) keeps up to 2048 bins in LDS,
+    // 96 KB: one block per CU, each flushing once (its own grid).
+    constexpr int kLds = TAN ? 12288 : 4096;
     __shared__ uint64_t s_raw[kLds];
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -890,19 +892,36 @@ __global__ __launch_bounds__(kThreads) void k_density_out(Dev d, int nbins, doub
 // particle.
 __global__ __launch_bounds__(kThreads) void k_vjp_out(Dev d, int nbins, double dxb, const double *g, double *out)
 {
-    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < (int64_t)d.B * 3;
-         q += (int64_t)gridDim.x * kThreads) {
+    // One wavefront per (instance, component): the lanes load 64 bins at a
+    // time and form their products g_j T_j, which are then added in
+    // ascending bin order (the order that fixes the result's bits).
+    const int lane = threadIdx.x & 63;
+    constexpr int kW = kThreads / 64;
+    for (int64_t q = (int64_t)blockIdx.x * kW + (threadIdx.x >> 6); q < (int64_t)d.B * 3;
+         q += (int64_t)gridDim.x * kW) {
         const int64_t b = q / 3, c = q - b * 3;
         int64_t *hi = d.dTq + b * 6 * d.max_bins + (2 * c) * d.max_bins;
         int64_t *lo = hi + d.max_bins;
         const double *gb = g + b * nbins;
         double acc = 0.0;
-        for (int j = 0; j < nbins; ++j) {
-            acc = acc + gb[j] * fx_value(hi[j], (uint64_t)lo[j]);
-            hi[j] = 0;
-            lo[j] = 0;
+        for (int j0 = 0; j0 < nbins; j0 += 64) {
+            const int j = j0 + lane;
+            double p = 0.0;
+            if (j < nbins) {
+                p = gb[j] * fx_value(hi[j], (uint64_t)lo[j]);
+                hi[j] = 0;
+                lo[j] = 0;
+            }
+            const int m = min(64, nbins - j0);
+            const uint64_t pb = (uint64_t)__double_as_longlong(p);
+            const int plo = (int)(uint32_t)pb, phi = (int)(uint32_t)(pb >> 32);
+            for (int k = 0; k < m; ++k) {   // lane k's product, read as a scalar
+                const uint64_t v = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(phi, k) << 32) |
+                                   (uint64_t)(uint32_t)__builtin_amdgcn_readlane(plo, k);
+                acc = acc + __longlong_as_double((long long)v);
+            }
         }
-        out[q] = acc / ((double)d.ip[b].N0 * dxb);
+        if (lane == 0) out[q] = acc / ((double)d.ip[b].N0 * dxb);
     }
 }
 
