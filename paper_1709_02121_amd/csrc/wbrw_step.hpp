@@ -908,10 +908,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     constexpr int FS = Stash<DIM, SP2, TAN>::F;
     constexpr int SPT = FS / kThreads;
     constexpr int NN = Tree<DIM, SP2, TAN>::kNodes;
-    // level-by-level expansion for the 1D plain and sp2 kernels; the 4D and
-    // tangent ones (more or larger slow families per tile, more LDS per
-    // record) keep the pool and one depth-first walk per lane
-    constexpr bool kTree = DIM == 1 && !TAN;
+    // level-by-level expansion for the 1D kernels (with tangents the table
+    // needs 78 KB of LDS, two blocks per CU, which their registers allow
+    // anyway); the 4D ones (about half the families of a tile are slow) keep
+    // the pool and one depth-first walk per lane
+    constexpr bool kTree = DIM == 1;
     __shared__ int64_t s_t;
     __shared__ uint32_t s_wsum[4];
     __shared__ int64_t s_excl;
