@@ -37,7 +37,8 @@ struct Layout {
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
            tcA = 0, tcAg = 0, supA = 0, supAg = 0, spart = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, occx = 0, Tqx = 0, off = 0,
            occ = 0, Tq = 0, ntil = 0, dacc = 0, dTq = 0, bA = 0, bcopies = 0, bcls = 0,
-           bcell = 0, bP = 0, bTile = 0, bG = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, hist = 0, xitab = 0;
+           bcell = 0, bP = 0, bTile = 0, bG = 0, bcls_stat = 0, tileD = 0, bscan_tiles = 0, hist = 0, xitab = 0,
+           gpool = 0;
     int64_t cap_total = 0, gcap_total = 0, Nh = 0;
     int64_t tilesA = 0, tilesAg = 0, tilesB = 0, tilesBg = 0, tilesS = 0, tilesP = 0;
 };
@@ -238,6 +239,7 @@ Layout make_layout(const wbrw_config *c)
     bool alg4 = false;
     for (int m = 0; m < c->n_components; ++m) alg4 = alg4 || c->comp[m].sampler == 1;
     if (alg4) L.xitab = take(cur, BB * (size_t)c->n_components * (kXiN + 1) * 8);
+    if (c->dim == 2) L.gpool = take(cur, (size_t)kGPoolBlocks * kGPoolBytes);
     if (sp2) {
         L.bA = take(cur, C * 8);
         L.bcopies = take(cur, C * 4);
@@ -907,6 +909,8 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.tileG = at<int64_t>(w, L.tileG);
     d.tally = at<int64_t>(w, L.tally);
     d.fpart = at<int64_t>(w, L.fpart);
+    d.gpool = L.gpool ? at<char>(w, L.gpool) : nullptr;
+    d.gpool_blocks = L.gpool ? kGPoolBlocks : 0;
     d.rstart = at<int64_t>(w, L.rstart);
     d.ev_idx = at<uint32_t>(w, L.ev_idx);
     d.gev_idx = h->tangent ? at<uint32_t>(w, L.gev_idx) : nullptr;

@@ -28,6 +28,14 @@ constexpr int kXiN = 4096;              // xi(r) grid intervals (Alg. 4 sampler)
 constexpr int kXiQ = 8192;              // quadrature nodes for xi(r)
 constexpr uint32_t kRejectMax = 256u;   // rejection proposals per kick
 constexpr int kMaxGrid = 8192;          // blocks of a persistent launch (per-block partials)
+// 4D family kernels: records of the general walks beyond the block's LDS pool
+// go to a per-block overflow area in HBM (kGPool records for each of the
+// first kGPoolBlocks blocks), so that they need not be walked a second time
+// when they are written.  Per record: eight doubles (x0, k0, x1, k1, w and
+// three tangents), the id, slot and rank, and the sign.
+constexpr int kGPool = 1024;
+constexpr int kGPoolBlocks = 1024;
+constexpr size_t kGPoolBytes = (size_t)kGPool * (8 * 8 + 8 + 4 + 1);
 
 // Event parents per family tile of the particle pass.  A tile's slow family
 // walks run concurrently, so larger tiles shorten the walk-bound critical
@@ -128,6 +136,8 @@ struct Dev {
     int64_t *tileG;             // [B+1] ghost-regeneration plan
     int64_t *tally;             // [B][kTalCount]
     int64_t *fpart;             // [kMaxGrid][8]: instance and tallies of each family block
+    char *gpool;                // [gpool_blocks][kGPoolBytes] (4D only, else null)
+    int32_t gpool_blocks;
     int64_t *rstart;            // first cell of every regeneration tile (written by k_scan)
     uint32_t *ev_idx;           // [cap_total] event-parent index within its instance
     uint32_t *gev_idx;          // ghosts

@@ -228,14 +228,18 @@ struct Tally {
 };
 
 // The records of a family found by fast_family (at most R: nearly always
-// one pair, and with derivative pairs at most one of each), kept in LDS
-// until the ordered scan has placed them.
+// one pair in 1D; in 4D, where each of the three components may add a pair,
+// up to two; with derivative pairs at most one of each), kept in LDS until
+// the ordered scan has placed them.  All of them are born at the family's
+// one jump, so that jump's position and time are kept once per slot and the
+// end-of-step positions are formed when the records are written.
 template <int DIM, bool SP2, bool TAN>
 struct Stash {
-    static constexpr int R = (TAN && !SP2) ? 4 : 2;
+    static constexpr int R = (!SP2 && (TAN || DIM == 2)) ? 4 : 2;
     static constexpr int F = fam_tile(DIM, TAN);   // event parents per tile
-    double x0[R][F], k0[R][F];
-    double x1[DIM == 2 ? R : 1][DIM == 2 ? F : 1];
+    double xe0[F], te[F];
+    double xe1[DIM == 2 ? F : 1];
+    double k0[R][F];
     double k1[DIM == 2 ? R : 1][DIM == 2 ? F : 1];
     double w[SP2 ? R : 1][SP2 ? F : 1];
     double D[TAN ? 3 * R : 1][TAN ? F : 1];
@@ -277,13 +281,17 @@ struct Tree {
     uint32_t n, nf[2], maxd;
 };
 
-// 4D and tangent kernels: the records of the families that took the general
-// walk, in order of creation across the tile, each tagged with its family's
-// slot and its rank within the family.  A family whose records do not all
-// fit is walked again when the records are written.  (In 4D about half the
-// families of a tile are not of the lockstep kind, too many for a Tree in an
-// LDS budget that keeps three blocks per CU.)
-constexpr int kPool = 256;
+// 4D kernels: the records of the families that took the general walk, in
+// order of creation across the tile, each tagged with its family's slot and
+// its rank within the family; past kPool they go on in the block's overflow
+// area in HBM.  A family whose records do not all fit there either is walked
+// again when the records are written.  (In 4D about a fifth of
+// the families of a tile are not of the lockstep kind, with some ten records
+// each: too many nodes for a Tree in an LDS budget that keeps three blocks
+// per CU.)  384 records fill the LDS that three blocks per CU leave; a record
+// kept in LDS is cheaper than one stored to HBM, since a later load of the
+// walk waits on the same counter as every store before it.
+constexpr int kPool = 384;
 template <int DIM, bool SP2, bool TAN>
 struct Pool {
     double x0[kPool], k0[kPool];
@@ -470,18 +478,13 @@ __device__ __forceinline__ int64_t killed_amount(const Node &ch)
     return ch.sg;
 }
 
-// End-of-step record of a child created at time te at position xe, kept in
-// stash row r of `slot`.
+// Child ch of the family in `slot`, kept in stash row r (the family's jump
+// is kept in the slot's xe0, xe1, te).
 template <int DIM, bool SP2, bool TAN>
-__device__ __forceinline__ void stash_record(const Dev &d, Stash<DIM, SP2, TAN> *sh, int r, int slot,
-                                             const double *xe, double te, const Node &ch)
+__device__ __forceinline__ void stash_record(Stash<DIM, SP2, TAN> *sh, int r, int slot, const Node &ch)
 {
-    sh->x0[r][slot] = xe[0] + (d.vfac * ch.k[0]) * (d.dt - te);
     sh->k0[r][slot] = ch.k[0];
-    if (DIM == 2) {
-        sh->x1[r][slot] = xe[1] + (d.vfac * ch.k[1]) * (d.dt - te);
-        sh->k1[r][slot] = ch.k[1];
-    }
+    if (DIM == 2) sh->k1[r][slot] = ch.k[1];
     if (SP2) sh->w[r][slot] = ch.w; else sh->sg[r][slot] = (int8_t)ch.sg;
     sh->id[r][slot] = ch.id;
     if (TAN) {
@@ -491,36 +494,76 @@ __device__ __forceinline__ void stash_record(const Dev &d, Stash<DIM, SP2, TAN> 
     }
 }
 
+// The block's overflow area of the pool (see kGPool): field f of record g
+// is at f * kGPool + g of the doubles.
+struct GPoolView {
+    double *f;
+    uint64_t *id;
+    uint32_t *sr;    // slot | rank << 16
+    int8_t *sg;
+};
+__device__ __forceinline__ GPoolView gpool_view(const Dev &d)
+{
+    char *b = d.gpool + (size_t)blockIdx.x * kGPoolBytes;
+    return {(double *)b, (uint64_t *)(b + (size_t)8 * 8 * kGPool), (uint32_t *)(b + (size_t)9 * 8 * kGPool),
+            (int8_t *)(b + (size_t)(9 * 8 + 4) * kGPool)};
+}
+__device__ __forceinline__ uint32_t gpool_cap(const Dev &d)
+{
+    return (int)blockIdx.x < d.gpool_blocks ? (uint32_t)kGPool : 0u;
+}
+
 template <int DIM, bool SP2, bool TAN>
 __device__ __forceinline__ bool pool_record(const Dev &d, Pool<DIM, SP2, TAN> *pl, int rank, int slot,
                                             const double *xe, double te, const Node &ch)
 {
     const uint32_t r = atomicAdd(&pl->n, 1u);
-    if (r >= (uint32_t)kPool) return false;
-    pl->x0[r] = xe[0] + (d.vfac * ch.k[0]) * (d.dt - te);
-    pl->k0[r] = ch.k[0];
+    const double x0 = xe[0] + (d.vfac * ch.k[0]) * (d.dt - te);
+    const double x1 = DIM == 2 ? xe[1] + (d.vfac * ch.k[1]) * (d.dt - te) : 0.0;
+    if (r < (uint32_t)kPool) {
+        pl->x0[r] = x0;
+        pl->k0[r] = ch.k[0];
+        if (DIM == 2) {
+            pl->x1[r] = x1;
+            pl->k1[r] = ch.k[1];
+        }
+        if (SP2) pl->w[r] = ch.w; else pl->sg[r] = (int8_t)ch.sg;
+        pl->id[r] = ch.id;
+        if (TAN) {
+            pl->D[0][r] = ch.D[0];
+            pl->D[1][r] = ch.D[1];
+            pl->D[2][r] = ch.D[2];
+        }
+        pl->slot[r] = (uint16_t)slot;
+        pl->rank[r] = (uint16_t)rank;
+        return true;
+    }
+    const uint32_t g = r - (uint32_t)kPool;
+    if (g >= gpool_cap(d)) return false;
+    const GPoolView v = gpool_view(d);
+    v.f[g] = x0;
+    v.f[kGPool + g] = ch.k[0];
     if (DIM == 2) {
-        pl->x1[r] = xe[1] + (d.vfac * ch.k[1]) * (d.dt - te);
-        pl->k1[r] = ch.k[1];
+        v.f[2 * kGPool + g] = x1;
+        v.f[3 * kGPool + g] = ch.k[1];
     }
-    if (SP2) pl->w[r] = ch.w; else pl->sg[r] = (int8_t)ch.sg;
-    pl->id[r] = ch.id;
+    if (SP2) v.f[4 * kGPool + g] = ch.w; else v.sg[g] = (int8_t)ch.sg;
     if (TAN) {
-        pl->D[0][r] = ch.D[0];
-        pl->D[1][r] = ch.D[1];
-        pl->D[2][r] = ch.D[2];
+        v.f[5 * kGPool + g] = ch.D[0];
+        v.f[6 * kGPool + g] = ch.D[1];
+        v.f[7 * kGPool + g] = ch.D[2];
     }
-    pl->slot[r] = (uint16_t)slot;
-    pl->rank[r] = (uint16_t)rank;
+    v.id[g] = ch.id;
+    v.sr[g] = (uint32_t)slot | ((uint32_t)rank << 16);
     return true;
 }
 
-// A pair created at time te at xe, as fast_family keeps it: both children
-// into the stash (clearing `fast` if it is full) unless the k-box removes
-// them, and `fast` cleared if either child jumps again within the step.
+// A pair created at time te, as fast_family keeps it: both children into
+// the stash (clearing `fast` if it is full) unless the k-box removes them,
+// and `fast` cleared if either child jumps again within the step.
 template <int DIM, bool SP2, bool TAN>
 __device__ __forceinline__ void leaf_pair(const Dev &d, const InstParam &P, uint32_t step, const Node (&ch)[2],
-                                          const double *xe, double te, Stash<DIM, SP2, TAN> *sh, int slot,
+                                          double te, Stash<DIM, SP2, TAN> *sh, int slot,
                                           uint32_t &cnt, Tally &tl, bool &fast)
 {
     // both offspring's first clock draws, together
@@ -533,7 +576,7 @@ __device__ __forceinline__ void leaf_pair(const Dev &d, const InstParam &P, uint
             continue;
         }
         if (cnt < (uint32_t)Stash<DIM, SP2, TAN>::R)
-            stash_record<DIM, SP2, TAN>(d, sh, (int)cnt, slot, xe, te, ch[side]);
+            stash_record<DIM, SP2, TAN>(sh, (int)cnt, slot, ch[side]);
         else fast = false;
         cnt++;
         if (tl.maxdepth < 1) tl.maxdepth = 1;
@@ -571,6 +614,9 @@ __device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, ui
     double xe[2];
     xe[0] = root.x[0] + (d.vfac * root.k[0]) * (te - root.t0);
     xe[1] = DIM == 2 ? root.x[1] + (d.vfac * root.k[1]) * (te - root.t0) : 0.0;
+    sh->xe0[slot] = xe[0];
+    if (DIM == 2) sh->xe1[slot] = xe[1];
+    sh->te[slot] = te;
     bool fast = true;
     for (int m = 0; m < d.M; ++m) {
         PairDraw J;
@@ -581,7 +627,7 @@ __device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, ui
         Node ch[2];
         make_child<SP2, TAN>(d, P, root, m, 0, J, rc, ch[0]);
         make_child<SP2, TAN>(d, P, root, m, 1, J, rc, ch[1]);
-        leaf_pair<DIM, SP2, TAN>(d, P, step, ch, xe, te, sh, slot, cnt, tl, fast);
+        leaf_pair<DIM, SP2, TAN>(d, P, step, ch, te, sh, slot, cnt, tl, fast);
     }
     if constexpr (TAN) {
         if (d.tangent == 2 && root.sg != 0) {
@@ -592,7 +638,7 @@ __device__ __forceinline__ bool fast_family(const Dev &d, const InstParam &P, ui
                 Node ch[2];
                 make_deriv_child(d, root, m, 0, J, rc, ch[0]);
                 make_deriv_child(d, root, m, 1, J, rc, ch[1]);
-                leaf_pair<DIM, SP2, TAN>(d, P, step, ch, xe, te, sh, slot, cnt, tl, fast);
+                leaf_pair<DIM, SP2, TAN>(d, P, step, ch, te, sh, slot, cnt, tl, fast);
             }
         }
     }
@@ -945,11 +991,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t err = 0;
 
-    // the event parent of tile position `slot`, at the start of the step
-    auto load_root = [&](int64_t base, int64_t j0, int slot) {
+    // the event parent at index i of the particle set, at the start of the
+    // step, and that of tile position `slot`
+    auto load_root_at = [&](int64_t i) {
         Node root;
-        const int64_t pos = base + j0 + slot;
-        const int64_t i = base + (int64_t)evi[pos];
         root.x[0] = E.x0[i];
         root.x[1] = DIM == 2 ? E.x1[i] : 0.0;
         root.k[0] = E.k0[i];
@@ -966,6 +1011,9 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             root.D[0] = root.D[1] = root.D[2] = 0.0;
         }
         return root;
+    };
+    auto load_root = [&](int64_t base, int64_t j0, int slot) {
+        return load_root_at(base + (int64_t)evi[base + j0 + slot]);
     };
 
     // Tallies stay in LDS while the block works on one instance; they go to
@@ -1013,7 +1061,12 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             uint32_t cnt = 0;
             bool fast = false;
             if (j0 + slot < nev) {
-                const Node root = load_root(base, j0, slot);
+                const int64_t pi = base + (int64_t)evi[base + j0 + slot];
+                const Node root = load_root_at(pi);
+                // the parent's position at the end of the step (k_stream left
+                // it at the start)
+                const double xend0 = root.x[0] + (d.vfac * root.k[0]) * d.dt;
+                const double xend1 = DIM == 2 ? root.x[1] + (d.vfac * root.k[1]) * d.dt : 0.0;
                 Tally th{0, 0, 0, 0, 0};
                 fast = fast_family<DIM, SP2, TAN>(d, P, step, root, &s_stash, slot, cnt, th);
                 if (fast) {
@@ -1022,6 +1075,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
                     tal.killed += th.killed;
                     tal.cap += th.cap;
                     tal.maxdepth = max(tal.maxdepth, th.maxdepth);
+                    // nothing in this launch reads a lockstep family's parent
+                    // again: it moves now, with no second gather
+                    E.x0[pi] = xend0;
+                    if (DIM == 2) E.x1[pi] = xend1;
                 } else {
                     s_slow[atomicAdd(&s_nslow, 1u)] = (uint16_t)slot;
                 }
@@ -1230,15 +1287,19 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             if (!s_fast[slot]) continue;
             const uint32_t cnt = s_cnt[slot];
             const int64_t my_first = s_excl + (int64_t)excl[h];
+            const double xe0 = s_stash.xe0[slot], xe1 = DIM == 2 ? s_stash.xe1[slot] : 0.0;
+            const double rest = d.dt - s_stash.te[slot];
             for (uint32_t r = 0; r < cnt; ++r) {
                 const int64_t li = my_first + r;
                 if (li >= cap) { err |= kErrCapacity; continue; }
                 const int64_t o = base + li;
-                S.x0[o] = s_stash.x0[r][slot];
-                S.k0[o] = s_stash.k0[r][slot];
+                const double k0 = s_stash.k0[r][slot];
+                S.x0[o] = xe0 + (d.vfac * k0) * rest;
+                S.k0[o] = k0;
                 if (DIM == 2) {
-                    S.x1[o] = s_stash.x1[r][slot];
-                    S.k1[o] = s_stash.k1[r][slot];
+                    const double k1 = s_stash.k1[r][slot];
+                    S.x1[o] = xe1 + (d.vfac * k1) * rest;
+                    S.k1[o] = k1;
                 }
                 if (SP2) S.w[o] = s_stash.w[r][slot]; else S.sg[o] = s_stash.sg[r][slot];
                 S.id[o] = s_stash.id[r][slot];
@@ -1304,6 +1365,33 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
                     S.D[2 * dstride + o] = s_pool.D[2][r];
                 }
             }
+            // the overflow area (written by this block's threads before the
+            // last barrier)
+            const int ngp = (int)min(s_pool.n - min(s_pool.n, (uint32_t)kPool), gpool_cap(d));
+            if (ngp) {
+                const GPoolView v = gpool_view(d);
+                for (int g = tid; g < ngp; g += kThreads) {
+                    const uint32_t sr = v.sr[g];
+                    const int slot = (int)(sr & 0xFFFFu);
+                    if (!s_tree[slot]) continue;
+                    const int64_t li = s_first[slot] + (int64_t)(sr >> 16);
+                    if (li >= cap) { err |= kErrCapacity; continue; }
+                    const int64_t o = base + li;
+                    S.x0[o] = v.f[g];
+                    S.k0[o] = v.f[kGPool + g];
+                    if (DIM == 2) {
+                        S.x1[o] = v.f[2 * kGPool + g];
+                        S.k1[o] = v.f[3 * kGPool + g];
+                    }
+                    if (SP2) S.w[o] = v.f[4 * kGPool + g]; else S.sg[o] = v.sg[g];
+                    S.id[o] = v.id[g];
+                    if (TAN) {
+                        S.D[o] = v.f[5 * kGPool + g];
+                        S.D[dstride + o] = v.f[6 * kGPool + g];
+                        S.D[2 * dstride + o] = v.f[7 * kGPool + g];
+                    }
+                }
+            }
             for (int k = kme; k < nslow; k += kThreads) {
                 const int slot = s_slow[k];
                 if (s_tree[slot]) continue;
@@ -1330,12 +1418,12 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
             if (tm) atomicMax((unsigned long long *)&s_tal[4], (unsigned long long)tm);
         }
         __syncthreads();
-        // every walk of this tile is done: the parents move to the end of the
-        // step (k_stream left them at their start positions)
+        // every walk of this tile is done: the other parents move to the end
+        // of the step
 #pragma unroll
         for (int h = 0; h < SPT; ++h) {
             const int slot = tid + h * kThreads;
-            if (j0 + slot < nev) {
+            if (j0 + slot < nev && !s_fast[slot]) {
                 const int64_t pi = base + (int64_t)evi[base + j0 + slot];
                 E.x0[pi] = E.x0[pi] + (d.vfac * E.k0[pi]) * d.dt;
                 if (DIM == 2) E.x1[pi] = E.x1[pi] + (d.vfac * E.k1[pi]) * d.dt;
