@@ -11,7 +11,7 @@ annihilation and the density readout, which are inside the timed region.
 value = sum over timed steps of the particles held at the start of the step,
 divided by the wall time.  Inputs are resident on the GPU before timing starts.
 
-Roofline: the whole step (its five launches) against HBM, with the survey's
+Roofline: the whole step (its four launches) against HBM, with the survey's
 model of 34 algorithmic bytes per particle-step (read x, k, id; write x; the
 offspring records and the parents' signs), timed by HIP events around every
 step on the launch stream inside the timed region.  The same steps are then
@@ -37,8 +37,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 ANN_EVERY = 10
 STEP_MODEL_BYTES = 34   # algorithmic bytes per particle-step of the 1D sp1 step
+# the placement launch's first block closes the step (tallies, counts, the next plan)
 STEP_KERNELS = (("stream", "k_stream"), ("events", "k_events"), ("family", "k_family"),
-                ("place", "k_place_records"), ("close", "k_close_family"))
+                ("place", "k_place_records"))
 TRAFFIC_SOURCES = ("wbrw_stream.hpp", "wbrw_step.hpp", "wbrw_math.hpp", "wbrw_dev.hpp")
 
 
@@ -198,7 +199,7 @@ def step_roofline(res):
     dominant = max(kern, key=lambda k: kern[k]["avg_launch_us"])
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-           "scope": "whole step: k_stream, k_events, k_family, k_place_records, k_close_family",
+           "scope": "whole step: k_stream, k_events, k_family, k_place_records (with the closing block)",
            "kernel": dominant, "dominant_kernel": dominant,
            "avg_step_us": round(avg_step_s * 1e6, 2), "steps_timed": nsteps,
            "particle_steps_per_step": int(ps_step), "bytes_per_particle_step": STEP_MODEL_BYTES,

@@ -166,7 +166,7 @@ enum wbrw_stage {
     WBRW_STAGE_GHOST = 7,     /* tangent ghosts and ghost steps */
     WBRW_STAGE_EVENTS = 8,    /* step: ordered event list */
     WBRW_STAGE_PLACE = 9,     /* step: record placement */
-    WBRW_STAGE_CLOSE = 10,    /* step: one-block bookkeeping */
+    WBRW_STAGE_CLOSE = 10,    /* unused: the placement launch's first block closes the step */
     WBRW_STAGE_STEP = 11,     /* a whole step, all of its launches (brackets the others) */
     WBRW_STAGE_COUNT = 12
 };
@@ -189,9 +189,10 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes,
               void *hip_stream, wbrw_t *out);
 
 /* Advances every instance by nsteps time steps (Alg. 1 between t_l and
- * t_{l+1} = t_l + dt; Sec. 2).  Enqueues 5 kernels per step (streaming, event
- * list, families, record placement, one-block bookkeeping; 10 with tangents,
- * whose ghosts take a second such pass); no host synchronisation. */
+ * t_{l+1} = t_l + dt; Sec. 2).  Enqueues 4 kernels per step (streaming, event
+ * list, families, record placement whose first block does the bookkeeping;
+ * 8 with tangents, whose ghosts take a second such pass); no host
+ * synchronisation. */
 int wbrw_step(wbrw_t h, int32_t nsteps);
 
 /* Annihilation (Sec. 4.3): particles outside the grid are removed (escaped

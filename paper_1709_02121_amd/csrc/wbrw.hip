@@ -33,7 +33,7 @@ struct Layout {
     // offsets
     size_t ens[2][8] = {}, gens[2][8] = {};
     size_t ip = 0, tab[kMaxM] = {}, guide[kMaxM] = {}, ctl = 0;
-    size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, evc = 0, tileA = 0, Nsrt = 0, srtS = 0, tileB = 0, tileR = 0,
+    size_t N = 0, NG = 0, Nnew = 0, NGnew = 0, Nbase = 0, evc = 0, tileA = 0, Nsrt = 0, srtS = 0, tileB = 0, tileR = 0,
            tileG = 0, tally = 0, fpart = 0, rstart = 0, rtiles = 0, ev_idx = 0, gev_idx = 0,
            tcA = 0, tcAg = 0, supA = 0, supAg = 0, spart = 0, emA = 0, emAg = 0, tcB = 0, tcBg = 0, supB = 0, supBg = 0, tsB = 0, tsBg = 0, stg = 0, stS = 0, stG = 0, cnt = 0, cntx = 0, occx = 0, Tqx = 0, off = 0,
            occ = 0, Tq = 0, ntil = 0, dacc = 0, dTq = 0, bA = 0, bcopies = 0, bcls = 0,
@@ -256,6 +256,7 @@ Layout make_layout(const wbrw_config *c)
     L.NG = take(cur, BB * 8);
     L.Nnew = take(cur, BB * 8);
     L.NGnew = take(cur, BB * 8);
+    L.Nbase = take(cur, 2 * BB * 8);
     L.evc = take(cur, 2 * BB * 8);
     L.tileA = take(cur, 2 * (BB + 1) * 8);
     L.Nsrt = take(cur, BB * 8);
@@ -580,8 +581,8 @@ void enqueue_step_dim(wbrw_t h)
     const Dev &d = h->d;
     hipStream_t s = h->stream;
     const bool tan = h->tangent != 0;
-    // stage marks bracket the main kernels only; the one-block closing
-    // launches run between them
+    // stage marks bracket the main kernels (the placement launch's last
+    // block closes the step)
     stage_begin(h, WBRW_STAGE_STREAM);
     launch_stream<DIM>(h, s, 0);
     stage_end(h);
@@ -599,17 +600,16 @@ void enqueue_step_dim(wbrw_t h)
         hipLaunchKernelGGL((k_family<DIM, false, false>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 0);
     stage_end(h);
     stage_begin(h, WBRW_STAGE_PLACE);
+    const dim3 pg(h->grid[G_EVENTS] + 1);
+    const int adv = tan ? 0 : 1, fg = h->grid[G_FAMILY];
     if (h->strategy == WBRW_SP2 && tan)
-        hipLaunchKernelGGL((k_place_records<DIM, true, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
+        hipLaunchKernelGGL((k_place_records<DIM, true, true>), pg, dim3(kThreads), 0, s, d, 0, adv, fg);
     else if (h->strategy == WBRW_SP2)
-        hipLaunchKernelGGL((k_place_records<DIM, true, false>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
+        hipLaunchKernelGGL((k_place_records<DIM, true, false>), pg, dim3(kThreads), 0, s, d, 0, adv, fg);
     else if (tan)
-        hipLaunchKernelGGL((k_place_records<DIM, false, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
+        hipLaunchKernelGGL((k_place_records<DIM, false, true>), pg, dim3(kThreads), 0, s, d, 0, adv, fg);
     else
-        hipLaunchKernelGGL((k_place_records<DIM, false, false>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 0);
-    stage_end(h);
-    stage_begin(h, WBRW_STAGE_CLOSE);
-    hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 0, tan ? 0 : 1, h->grid[G_FAMILY]);
+        hipLaunchKernelGGL((k_place_records<DIM, false, false>), pg, dim3(kThreads), 0, s, d, 0, adv, fg);
     stage_end(h);
     if (tan) {
         // ghosts (weight 0) branch by the sp1 rule in either strategy
@@ -617,8 +617,7 @@ void enqueue_step_dim(wbrw_t h)
         launch_stream<DIM>(h, s, 1);
         hipLaunchKernelGGL(k_events, dim3(h->grid[G_EVENTS] + 1), dim3(kThreads), 0, s, d, 1, h->grid[G_STREAM]);
         hipLaunchKernelGGL((k_family<DIM, false, true>), dim3(h->grid[G_FAMILY]), dim3(kThreads), 0, s, d, 1);
-        hipLaunchKernelGGL((k_place_records<DIM, false, true>), dim3(h->grid[G_EVENTS]), dim3(kThreads), 0, s, d, 1);
-        hipLaunchKernelGGL(k_close_family, dim3(1), dim3(kThreads), 0, s, d, 1, 1, h->grid[G_FAMILY]);
+        hipLaunchKernelGGL((k_place_records<DIM, false, true>), pg, dim3(kThreads), 0, s, d, 1, 1, fg);
         stage_end(h);
     }
 }
@@ -900,6 +899,7 @@ int wbrw_init(const wbrw_config *cfg, void *workspace, size_t workspace_bytes, v
     d.NG = at<int64_t>(w, L.NG);
     d.Nnew = at<int64_t>(w, L.Nnew);
     d.NGnew = at<int64_t>(w, L.NGnew);
+    d.Nbase = at<int64_t>(w, L.Nbase);
     d.evc = at<int64_t>(w, L.evc);
     d.tileA = at<int64_t>(w, L.tileA);
     d.Nsrt = at<int64_t>(w, L.Nsrt);

@@ -129,6 +129,7 @@ struct Dev {
     const InstParam *ip;
     Ctl *ctl;
     int64_t *N, *NG, *Nnew, *NGnew;
+    int64_t *Nbase;             // [2][B] counts at the start of the step (real, ghost): the records go after them
     int64_t *evc;               // [2][B] event counts (real, ghost)
     int64_t *tileA;             // [2][B+1] streaming-tile plan (real, ghost)
     int64_t *tileB;             // [2][B+1] family-tile plan
@@ -345,8 +346,8 @@ __device__ __forceinline__ uint32_t tile_prefix(uint64_t *st, int64_t t, int64_t
 // ntiles + gridDim.x tickets, and the block that draws the last of them
 // clears the counter for the next launch (which sees it after the kernel
 // boundary).  No block waits for the others at the end, and no device-wide
-// fence is needed.  Work that needs every block's results runs in a separate
-// one-block launch.
+// fence is needed.  Work that needs every block's results runs in one extra
+// block of the next launch.
 __device__ __forceinline__ int64_t next_tile(uint32_t *ctr, int64_t ntiles)
 {
     const uint32_t t = atomicAdd(ctr, 1u);

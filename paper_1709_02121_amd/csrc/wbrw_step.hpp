@@ -108,7 +108,10 @@ __device__ __forceinline__ bool in_kbox(const Dev &d, const double *k)
 // lane, as in the particle array); the offset is the sum of the event counts
 // of the instance's earlier tiles, taken from the 64-tile group sums.  The
 // last block instead adds up the streaming blocks' per-instance event counts
-// and lays out the family tiles.
+// and lays out the family tiles.  Before that it clears the previous step's
+// family-tile group sums (read by the previous placement launch, so its
+// closing block could not) and keeps the particle counts, after which the
+// step's records go (the placement launch's closing block updates them).
 __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost, int sgrid)
 {
     const int B = d.B;
@@ -120,6 +123,13 @@ __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost, int sgrid
         const bool lds = B <= kLdsB;
         if (lds)
             for (int b = tid; b < B; b += kThreads) s_ev[b] = 0;
+        {
+            uint64_t *supB = ghost ? d.supBg : d.supB;
+            const int64_t nb = (d.tileB[(int64_t)ghost * (B + 1) + B] + kSupGroup - 1) / kSupGroup;
+            for (int64_t g = tid; g < nb; g += kThreads) supB[g * kSupStride] = 0;
+            const int64_t *Ncur = ghost ? d.NG : d.N;
+            for (int b = tid; b < B; b += kThreads) d.Nbase[(int64_t)ghost * B + b] = Ncur[b];
+        }
         __syncthreads();
         for (int g = tid; g < sgrid; g += kThreads) {
             const int64_t cb = d.spart[2 * g], c = d.spart[2 * g + 1];
@@ -1438,17 +1448,24 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     if (err) atomicOr(&ctl->err, err);
 }
 
+__device__ void close_family(const Dev &d, int ghost, int advance, int fgrid);
+
 // Every family tile's staged records (contiguous in the inactive buffer set)
 // go to their place after the instance's particles: tile order, then the
-// order of the family walks within the tile.
+// order of the family walks within the tile.  Block 0 (dispatched first)
+// closes the step (close_family).
 template <int DIM, bool SP2, bool TAN>
-__global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost)
+__global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost, int advance, int fgrid)
 {
+    if (blockIdx.x == 0) {
+        close_family(d, ghost, advance, fgrid);
+        return;
+    }
     Ctl *ctl = d.ctl;
     const int B = d.B;
     const int64_t *plan = d.tileB + (int64_t)ghost * (B + 1);
     const int64_t ntiles = plan[B];
-    const int64_t *Ncur = ghost ? d.NG : d.N;
+    const int64_t *Nb = d.Nbase + (int64_t)ghost * B;   // counts at the start of the step
     const uint32_t set = ghost ? ctl->gcur : ctl->cur;
     const Ens E = pick_set(d, ghost, set);
     const Ens S = pick_set(d, ghost, set ^ 1u);
@@ -1458,7 +1475,7 @@ __global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost)
     __shared__ uint64_t s_w[kThreads / 64];
     const int64_t dstride = ghost ? d.gcap_total : d.cap_total;
     uint32_t err = 0;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = blockIdx.x - 1; t < ntiles; t += gridDim.x - 1) {
         const int b = segment_of(plan, B, t);
         const InstParam &P = d.ip[b];
         const int64_t base = ghost ? P.gbase : P.base;
@@ -1503,7 +1520,7 @@ __global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost)
             const int64_t r = threadIdx.x + (int64_t)h * kThreads;
             if (r < n && src + r < cap) pre[h] = load(r);
         }
-        const int64_t dst = Ncur[b] + (int64_t)block_range_sum(TileRange(tc, sup, plan[b], t), s_w);
+        const int64_t dst = Nb[b] + (int64_t)block_range_sum(TileRange(tc, sup, plan[b], t), s_w);
 #pragma unroll
         for (int h = 0; h < kPre; ++h) {
             const int64_t r = threadIdx.x + (int64_t)h * kThreads;
@@ -1515,10 +1532,13 @@ __global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost)
     if (err) atomicOr(&ctl->err, err);
 }
 
-// After k_family (one block): the family blocks' tallies, the new particle
-// counts with the capacity clamp, cleared event and record counts, the
-// streaming-tile plan of the next step, and the step counter.
-__global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int advance, int fgrid)
+// After k_family, in the last block of the placement launch: the family
+// blocks' tallies, the new particle counts with the capacity clamp, cleared
+// event and record counts, the streaming-tile plan of the next step, and the
+// step counter.  Nothing here is read by the placing blocks: they take the
+// particle counts kept by k_events, and the family-tile group sums are
+// cleared by the next k_events.
+__device__ void close_family(const Dev &d, int ghost, int advance, int fgrid)
 {
     Ctl *ctl = d.ctl;
     const int B = d.B;
@@ -1531,7 +1551,6 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
     // keeps instance b's values in registers.
     const uint32_t step = ctl->step;
     const int64_t tilesA = d.tileA[(int64_t)ghost * (B + 1) + B];
-    const int64_t tilesB = d.tileB[(int64_t)ghost * (B + 1) + B];
     const bool own = tid < B;
     int64_t n_own = 0, rec_own = 0, cap_own = 0, tal_own[kTalCount] = {};
     if (own) {
@@ -1543,7 +1562,7 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
     }
     // the family blocks' last tallies, summed per instance in LDS when the
     // instances fit (global atomics from one block on one line serialise)
-    constexpr int kLdsB = 512;
+    constexpr int kLdsB = 256;
     __shared__ int64_t s_acc[5][kLdsB];
     const bool lds = B <= kLdsB;
     if (lds)
@@ -1608,11 +1627,10 @@ __global__ __launch_bounds__(kThreads) void k_close_family(Dev d, int ghost, int
         if (any_over && !sched)
             for (int b = 0; b < B; ++b) d.tally[(int64_t)b * kTalCount + kTalTrig] += 1;
     }
-    {   // clear the group sums of this step's streaming and family tiles
-        uint64_t *supA = ghost ? d.supAg : d.supA, *supB = ghost ? d.supBg : d.supB;
-        const int64_t na = (tilesA + kSupGroup - 1) / kSupGroup, nb = (tilesB + kSupGroup - 1) / kSupGroup;
+    {   // clear the group sums of this step's streaming tiles
+        uint64_t *supA = ghost ? d.supAg : d.supA;
+        const int64_t na = (tilesA + kSupGroup - 1) / kSupGroup;
         for (int64_t g = tid; g < na; g += kThreads) supA[g * kSupStride] = 0;
-        for (int64_t g = tid; g < nb; g += kThreads) supB[g * kSupStride] = 0;
     }
     __syncthreads();
     // the next step's tile plan (block_prefix evaluates instance b on thread
