@@ -356,6 +356,27 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *ctr, int64_t ntiles)
     return (int64_t)t;
 }
 
+// The same dispenser with every block's first tile given statically (block
+// b takes tile b): when the tiles are about as many as the blocks, every
+// block starts at once instead of queueing behind one atomic on one line
+// (some 11 ns each).  The counter then hands out tiles gridDim.x, ...: each
+// of those tickets is drawn once and every block draws one ticket past the
+// end, so the block that draws ticket max(0, ntiles - gridDim.x) +
+// gridDim.x - 1 clears the counter.  `first` is the caller's flag, true on
+// its first call.
+__device__ __forceinline__ int64_t next_tile_static_first(uint32_t *ctr, int64_t ntiles, bool &first)
+{
+    const int64_t G = (int64_t)gridDim.x;
+    if (first) {
+        first = false;
+        if ((int64_t)blockIdx.x < ntiles) return (int64_t)blockIdx.x;
+    }
+    const int64_t D = ntiles > G ? ntiles - G : 0;
+    const uint32_t u = atomicAdd(ctr, 1u);
+    if ((int64_t)u == D + G - 1) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return G + (int64_t)u;
+}
+
 // Exclusive scan of the per-tile counts cnt[0..T) into pre[0..T) by one
 // block (pre may be cnt); returns the total to every thread.  Chunks of
 // kThreads x P counts are loaded coalesced (all loads in flight together)

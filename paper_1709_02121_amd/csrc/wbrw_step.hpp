@@ -1032,10 +1032,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     // closing launch.  Per-tile atomics on one cache line would serialise
     // the whole grid.
     int cb = -1;
+    bool first = true;
     if (tid < 5) s_tal[tid] = 0;
     for (;;) {
         if (tid == 0) {
-            s_t = next_tile(&ctl->ticket[pass], ntiles);
+            s_t = next_tile_static_first(&ctl->ticket[pass], ntiles, first);
             s_nslow = 0;
             if constexpr (!kTree) s_walk.n = 0;
         }

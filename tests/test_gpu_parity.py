@@ -480,6 +480,25 @@ def test_launch_shapes_keep_results(P, O):
         P.Simulation(c4).set_launch(dict(P.Simulation(c4).launch(), stream_threads=128, stream_ppt=16))
 
 
+def test_4d_family_grids_keep_results(P, O):
+    """4D family kernels keep the general walks' records past the LDS pool in
+    a per-block overflow area in HBM.  The default grid, a few blocks that
+    reuse their areas tile after tile, and a grid wider than the areas cover
+    all give the oracle's bits (full 256-parent tiles, some 50 general walks
+    each, so the pool overflows in every tile)."""
+    cfg = W.helium_soft_coulomb(N0=np.array([200_000]))
+    r = O.OracleSim(cfg)
+    r.step(3)
+    say(f"4d grids: n={r.count()}")
+    d = P.Simulation(cfg).launch()
+    for fb in (d["family_blocks"], 7, 1100):
+        g = P.Simulation(cfg)
+        g.set_launch(dict(d, family_blocks=fb))
+        g.step(3)
+        compare(g, r, f"4d family grid {fb}")
+        del g
+
+
 @pytest.mark.parametrize("strategy", ["sp1", "sp2"])
 def test_time_dependent_potential_parity(P, O, strategy):
     """Remark 1: kernel evaluated at the absolute jump time (switching left barrier)."""
