@@ -106,9 +106,9 @@ __device__ __forceinline__ bool in_kbox(const Dev &d, const double *k)
 // ballots into the within-instance indices of its event parents, at the
 // tile's offset in its instance's list (order: particle slot, wavefront,
 // lane, as in the particle array); the offset is the sum of the event counts
-// of the instance's earlier tiles, taken from the 64-tile group sums.  The
-// last block instead adds up the streaming blocks' per-instance event counts
-// and lays out the family tiles.  Before that it clears the previous step's
+// of the instance's earlier tiles, taken from the 64-tile group sums.  Block
+// 0 (dispatched first) instead adds up the streaming blocks' per-instance
+// event counts and lays out the family tiles.  Before that it clears the previous step's
 // family-tile group sums (read by the previous placement launch, so its
 // closing block could not) and keeps the particle counts, after which the
 // step's records go (the placement launch's closing block updates them).
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost, int sgrid
 {
     const int B = d.B;
     const int tid = threadIdx.x;
-    if (blockIdx.x == gridDim.x - 1) {
+    if (blockIdx.x == 0) {
         constexpr int kLdsB = 512;
         __shared__ int64_t s_ev[kLdsB];
         int64_t *evc = d.evc + (int64_t)ghost * B;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost, int sgrid
     const int lane = tid & 63, wv = tid >> 6;
     constexpr int kWaves = kThreads / 64;
     static_assert(kTileA / 64 <= 64, "one lane per ballot of a tile");
-    for (int64_t t = (int64_t)blockIdx.x * kWaves + wv; t < ntiles; t += (int64_t)(gridDim.x - 1) * kWaves) {
+    for (int64_t t = (int64_t)(blockIdx.x - 1) * kWaves + wv; t < ntiles; t += (int64_t)(gridDim.x - 1) * kWaves) {
         const int b = segment_of(plan, B, t);
         const int64_t tl = t - plan[b];
         const InstParam &P = d.ip[b];
@@ -1533,7 +1533,7 @@ __global__ __launch_bounds__(kThreads) void k_place_records(Dev d, int ghost, in
     if (err) atomicOr(&ctl->err, err);
 }
 
-// After k_family, in the last block of the placement launch: the family
+// After k_family, in the first block of the placement launch: the family
 // blocks' tallies, the new particle counts with the capacity clamp, cleared
 // event and record counts, the streaming-tile plan of the next step, and the
 // step counter.  Nothing here is read by the placing blocks: they take the
