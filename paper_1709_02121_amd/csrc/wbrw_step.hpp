@@ -108,10 +108,11 @@ __device__ __forceinline__ bool in_kbox(const Dev &d, const double *k)
 // lane, as in the particle array); the offset is the sum of the event counts
 // of the instance's earlier tiles, taken from the 64-tile group sums.  Block
 // 0 (dispatched first) instead adds up the streaming blocks' per-instance
-// event counts and lays out the family tiles.  Before that it clears the previous step's
-// family-tile group sums (read by the previous placement launch, so its
-// closing block could not) and keeps the particle counts, after which the
-// step's records go (the placement launch's closing block updates them).
+// event counts and lays out the family tiles.  Before that it clears the
+// previous step's family-tile group sums (read by the previous placement
+// launch, so its closing block could not) and keeps the particle counts,
+// after which the step's records go (the placement launch's closing block
+// updates them).
 __global__ __launch_bounds__(kThreads) void k_events(Dev d, int ghost, int sgrid)
 {
     const int B = d.B;
@@ -1029,7 +1030,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_family(Dev d, int ghost)
     // Tallies stay in LDS while the block works on one instance; they go to
     // the instance's counters when the block moves on to another one, and the
     // last instance's share is left in the block's slot of fpart for the
-    // closing launch.  Per-tile atomics on one cache line would serialise
+    // closing block of the placement launch.  Per-tile atomics on one cache line would serialise
     // the whole grid.
     int cb = -1;
     bool first = true;
@@ -1620,7 +1621,7 @@ __device__ void close_family(const Dev &d, int ghost, int advance, int fgrid)
         if (d.ann_limit > 0 && n > d.ann_limit) over = 1;
     }
     // conditional annihilation after this step: scheduled, or an instance
-    // about to outgrow the threshold (the real ensemble's closing launch)
+    // about to outgrow the threshold (the real ensemble's closing block)
     const int any_over = __syncthreads_or(over);
     if (d.cond_ann && !ghost && tid == 0) {
         const bool sched = d.ann_every > 0 && (step + 1u) % (uint32_t)d.ann_every == 0u;
