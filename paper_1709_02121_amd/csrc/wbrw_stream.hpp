@@ -113,15 +113,18 @@ __global__ __launch_bounds__(NT, stream_min_blocks<NT>) void k_stream(Dev d, int
         }
         // free flight to the end of the step; an event parent keeps its
         // start position, which its family walk needs, and k_family moves it.
-        // The positions are not read again in this launch: non-temporal
-        // stores keep them from displacing cached lines.
+        // Its start position is written back too, so that every line is
+        // written whole (no byte-masked partial writes).  The positions are
+        // not read again in this launch: non-temporal stores keep them from
+        // displacing cached lines.
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const int64_t li = li0 + (int64_t)j * NT;
-            if ((full || li < n) && !((evbits >> j) & 1u)) {
+            if (full || li < n) {
                 const int64_t i = base + li;
-                __builtin_nontemporal_store(xs0[j] + (d.vfac * kv0[j]) * d.dt, &E.x0[i]);
-                if (DIM == 2) __builtin_nontemporal_store(xs1[j] + (d.vfac * kv1[j]) * d.dt, &E.x1[i]);
+                const bool evj = (evbits >> j) & 1u;
+                __builtin_nontemporal_store(evj ? xs0[j] : xs0[j] + (d.vfac * kv0[j]) * d.dt, &E.x0[i]);
+                if (DIM == 2) __builtin_nontemporal_store(evj ? xs1[j] : xs1[j] + (d.vfac * kv1[j]) * d.dt, &E.x1[i]);
             }
         }
         if (lane == 0) s_wcnt[wv] = nev;
